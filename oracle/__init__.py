@@ -1,0 +1,32 @@
+"""Plain FP64 CPU oracle for the multiple-scattering operator in a two-layer
+elastic medium (Zhang, He, Lai, "A fast solver for many-particle elastic
+scattering in layered media").
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call this package.  It shares
+no code with the HIP library and never imports it.
+
+What it computes (paper frame: particles in y < 0, interface y = 0):
+
+* ``media``        wavenumbers (Section 2, Helmholtz split; density kept).
+* ``smatrix``      closed-form disk scattering matrices, rigid and
+                   traction-free (Section 3.1), and basis rotation (Section 3.3).
+* ``graf``         dense O(N^2) free-space translations (Section 3.2, Graf).
+* ``interface``    the per-node 2x2 P-SV reflection of the welded interface
+                   (Section 2.2, the 4x4 system solved per Fourier mode).
+* ``sommerfeld``   the layered reflected part: multipole-to-Sommerfeld
+                   (Lemma, Section 4.4), reflection, Sommerfeld-to-local
+                   (Jacobi-Anger, Section 4.3), integrated by adaptive
+                   Gauss-Kronrod quadrature on the real axis.
+* ``incident``     plane-wave right-hand side (Section 6.3).
+* ``operator``     y = x - S (T_free + T_refl) x, the Schur-complement operator
+                   of Section 4.2, and its conjugate transpose.
+* ``gmres``        textbook GMRES (Saad-Schultz) with CGS2 Arnoldi.
+* ``field``        scattered displacement at receivers (Section 4, coupled
+                   representation).
+
+Parity unpinned: nothing in this package; each part is pinned by the tests in
+``tests/test_oracle_*.py`` (closed forms, invariants, brute force).
+"""
+from . import media, smatrix, graf, interface, sommerfeld, incident, operator, gmres, field  # noqa: F401
+from .media import Media, wavenumbers  # noqa: F401

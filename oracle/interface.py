@@ -1,0 +1,84 @@
+"""Welded-interface reflection of plane-wave potentials, one Fourier mode at a time.
+
+Section 2.2: the Sommerfeld representation diagonalises the tangential
+variable, so continuity of displacement and traction T_y across y = 0 is
+imposed per mode xi (the paper's 4x4 system A_xi sigma = b_xi, written there
+with rho = 1 for densities on the interface).  The oracle writes the same four
+conditions for potentials (density kept):
+
+A potential e^{i xi x + q y} in a medium (lambda, mu, rho) gives
+(u1, u2, t1, t2) with t = T_y u = (mu(d_y u1 + d_x u2), (lambda+2mu) d_y u2 + lambda d_x u1):
+  P (u = grad phi):        (i xi, q, 2 mu i xi q, (lambda + 2 mu) q^2 - lambda xi^2)
+  S (u = grad^perp psi):   (-q, i xi, -mu (q^2 + xi^2), 2 mu i xi q)
+
+Branch (the paper asks only for decay away from the interface): s(xi; k) =
+-i sqrt(k^2 - xi^2) with the principal root; on the real axis s > 0 for
+|xi| > k and s = -i sqrt(k^2 - xi^2) for |xi| < k, chosen by cases.
+In the host (y < 0) the wave going up to the interface is e^{i xi x - s y},
+the reflected one e^{i xi x + s y}; in the substrate the transmitted one is
+e^{i xi x - s_b y}.
+
+R(xi) is the top 2x2 block of X in
+  [P_h(+s_p), S_h(+s_s), -P_b(-s_pb), -S_b(-s_sb)] X = -[P_h(-s_p), S_h(-s_s)],
+column 0 answering a unit upgoing P potential, column 1 a unit S potential.
+The bottom 2x2 block is the transmission T(xi).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .media import Media
+
+
+def branch_s(xi, k: float):
+    """s(xi; k) = sqrt(xi^2 - k^2) with Re s >= 0 (decaying branch).
+
+    Real xi is split by cases; complex xi with Im(k^2 - xi^2) >= 0 uses the
+    principal root of k^2 - xi^2.
+    """
+    xi = np.asarray(xi)
+    if np.isrealobj(xi):
+        xr = xi.astype(float)
+        out = np.where(np.abs(xr) > k, np.sqrt(np.maximum(xr * xr - k * k, 0.0)) + 0j,
+                       -1j * np.sqrt(np.maximum(k * k - xr * xr, 0.0)))
+        return out
+    return -1j * np.sqrt(k * k - xi * xi)
+
+
+def _cols(xi, q, lam, mu):
+    P = np.array([1j * xi, q, 2 * mu * 1j * xi * q, (lam + 2 * mu) * q * q - lam * xi * xi])
+    S = np.array([-q, 1j * xi, -mu * (q * q + xi * xi), 2 * mu * 1j * xi * q])
+    return P, S
+
+
+def system(xi, m: Media):
+    """The 4x4 matrix and 4x2 right-hand side at one xi."""
+    sp = branch_s(xi, m.kp)
+    ss = branch_s(xi, m.ks)
+    spb = branch_s(xi, m.kpb)
+    ssb = branch_s(xi, m.ksb)
+    Pr, _ = _cols(xi, +sp, m.lam_h, m.mu_h)
+    _, Sr = _cols(xi, +ss, m.lam_h, m.mu_h)
+    Pi, _ = _cols(xi, -sp, m.lam_h, m.mu_h)
+    _, Si = _cols(xi, -ss, m.lam_h, m.mu_h)
+    Pt, _ = _cols(xi, -spb, m.lam_b, m.mu_b)
+    _, St = _cols(xi, -ssb, m.lam_b, m.mu_b)
+    M = np.stack([Pr, Sr, -Pt, -St], axis=1)
+    rhs = -np.stack([Pi, Si], axis=1)
+    return M, rhs
+
+
+def reflect_transmit(xi, m: Media):
+    """(R, T), each 2x2, at one scalar xi."""
+    M, rhs = system(xi, m)
+    X = np.linalg.solve(M, rhs)
+    return X[:2, :], X[2:, :]
+
+
+def reflection(xi, m: Media) -> np.ndarray:
+    return reflect_transmit(xi, m)[0]
+
+
+def reflection_many(xis, m: Media) -> np.ndarray:
+    """R at many real xi: array [len(xis), 2, 2]."""
+    return np.stack([reflection(float(x) if np.isrealobj(x) else x, m) for x in np.asarray(xis)])
