@@ -1,0 +1,213 @@
+/*
+ * ems.h -- C ABI of the MI355X (gfx950) multiple-scattering operator library.
+ *
+ * Elastic scattering by many rigid or traction-free particles buried in the
+ * lower layer of a two-layer medium with a welded flat interface (Zhang, He,
+ * Lai, "A fast solver for many-particle elastic scattering in layered media").
+ *
+ * Frame (Section 2): interface y = 0; the particles and their host medium are
+ * in y < 0; the other medium ("substrate") fills y > 0.  Every coefficient
+ * vector crossing this ABI is complex128, interleaved (re, im), laid out as
+ * [nrhs][sum_m 2(2 p_m + 1)], and per particle [alpha_{-p..p}, beta_{-p..p}]
+ * (outgoing coefficients of grad H_n(kp r) e^{i n th} and
+ * grad^perp H_n(ks r) e^{i n th}, Section 3.1; truncation Z_p, Section 3.1
+ * remark; block order of the multiple-scattering system, Section 3.2).
+ *
+ * Ownership: the caller owns every buffer passed in; "host" pointers are read
+ * (or written) during the call only; "device" pointers must stay valid until
+ * the work queued on the given stream has finished.  Calls that take a stream
+ * queue work on it and return without waiting, except ems_build and
+ * ems_solve, which finish before returning.  A handle must not be used by two
+ * threads at once.
+ *
+ * Errors: 0 = OK, > 0 warning, < 0 error; ems_last_error() returns a message.
+ * No C++ exception crosses this boundary.
+ */
+#ifndef EMS_H
+#define EMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMS_OK 0
+#define EMS_NOT_CONVERGED 1       /* solve: iteration limit reached            */
+#define EMS_ERR_ARG (-1)          /* bad argument (null, size, range)          */
+#define EMS_ERR_GEOMETRY (-2)     /* overlapping disks, disk crossing y = 0    */
+#define EMS_ERR_HIP (-3)          /* a HIP runtime call failed                  */
+#define EMS_ERR_OOM (-4)          /* device allocation failed                   */
+#define EMS_ERR_STATE (-5)        /* call order (e.g. apply before build)       */
+#define EMS_ERR_NUMERIC (-6)      /* NaN / Inf in an input, singular 4x4 system */
+#define EMS_ERR_UNIMPLEMENTED (-7)
+
+typedef struct ems_handle ems_handle;
+typedef void *ems_stream_t; /* a hipStream_t; NULL means the default stream */
+
+/* Lame parameters and density of one homogeneous layer (Section 2; the paper
+ * sets rho = 1, the library keeps it: kp = omega sqrt(rho/(lambda+2mu)),
+ * ks = omega sqrt(rho/mu)). */
+typedef struct {
+  double lambda, mu, rho;
+} ems_medium;
+
+/* host = the particle layer (y < 0), substrate = y > 0; omega > 0. */
+typedef struct {
+  ems_medium host, substrate;
+  double omega;
+} ems_media;
+
+/* Sommerfeld quadrature on the xi axis (Section 4.1).
+ *  kind 0: the paper's hyperbolic-tangent contour xi(t) = t - i delta tanh t,
+ *          t in [-t_max, t_max], trapezoidal rule with q nodes;
+ *  kind 1: real axis, composite Gauss-Legendre panels with a xi = k +- u^2
+ *          substitution on the panel next to each branch point (+-kp, +-ks of
+ *          both layers), panel length from the horizontal extent of the
+ *          particle cloud, tails to +-t_max; q is an output (node count);
+ *  kind 2: user nodes: q entries of nodes = [Re xi, Im xi, Re w, Im w].
+ * t_max <= 0 asks the library to choose it from the depth of the shallowest
+ * particle and the largest p (decay of exp(-|xi| D)(2|xi|/k)^(2p)).
+ * panel_scale multiplies the default panel length of kind 1 (1 = default);
+ * panel_order is the Gauss-Legendre order of the kind 1 panels (0 = 64). */
+typedef struct {
+  int32_t kind;
+  int32_t q;
+  double t_max;
+  double delta;
+  double panel_scale;
+  const double *nodes; /* host, kind 2 only */
+  int32_t panel_order;
+} ems_sommerfeld;
+
+/* Plane wave sent from the particle side towards the interface, direction
+ * (sin a, cos a) in the paper frame.  wave 0: P, unit displacement
+ * d e^{i kp d.x}; wave 1: SV, d_perp e^{i ks d.x} (Section 6.3). */
+typedef struct {
+  int32_t wave;
+  double angle;
+} ems_plane_wave;
+
+typedef struct {
+  double tol;        /* relative residual target ||b - A x|| / ||b||          */
+  int32_t restart;   /* Krylov dimension before a restart                      */
+  int32_t maxit;     /* total inner iterations                                 */
+  int32_t precision; /* 0: FP64 GMRES; 1: FP32 contractions in the inner
+                        solve with FP64 iterative refinement                    */
+  double inner_tol;  /* precision 1: relative tolerance of each inner solve    */
+} ems_solver_opts;
+
+typedef struct {
+  int32_t iters;       /* inner iterations (all RHS, lock-step: per RHS)      */
+  int32_t outer_iters; /* refinement sweeps (precision 1), else 1             */
+  int32_t converged;
+  double relres;       /* max over RHS of the final FP64 relative residual    */
+  double seconds;
+} ems_solve_info;
+
+typedef struct {
+  int32_t n;            /* particles                                          */
+  int32_t p_max;
+  int64_t n_coeff;      /* complex unknowns per right-hand side               */
+  int32_t q;            /* Sommerfeld nodes                                   */
+  double t_max;
+  int64_t n_pairs;      /* free-space particle pairs evaluated directly       */
+  double kp, ks, kpb, ksb;
+} ems_build_info;
+
+/* Parts of the operator selected by ems_apply's flags. */
+#define EMS_PART_FREE 1      /* T_free: Graf translations (Section 3.2)          */
+#define EMS_PART_REFL 2      /* T_refl: Sommerfeld reflected part (Section 4)    */
+#define EMS_PART_S 4         /* multiply by the particle S-matrices              */
+#define EMS_PART_IDENTITY 8  /* y = x - (...); requires EMS_PART_S               */
+#define EMS_APPLY_ALL 15
+#define EMS_MIXED 256        /* FP32 contractions (FP64 coefficient generation)  */
+
+/* Create an empty handle on the current HIP device. */
+int ems_create(ems_handle **out);
+void ems_destroy(ems_handle *h);
+const char *ems_last_error(const ems_handle *h);
+
+/* Materials and frequency (Section 2).  Host data. */
+int ems_set_media(ems_handle *h, const ems_media *m);
+
+/* Particles (Section 2, well-separated enclosing disks, Section 3.3): n centres
+ * xy[n][2] in the paper frame, enclosing radii R[n], truncation orders
+ * p[n] in [1, 15].  Host data, copied.  Validation at ems_build:
+ * |x_m - x_l| > R_m + R_l and y_m + R_m < 0, else EMS_ERR_GEOMETRY. */
+int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *R,
+                      const int32_t *p);
+
+/* Per-particle scattering matrices (Section 3.1 and 3.3), host data, copied:
+ * S + 2*offsets[m] doubles hold particle m's (4p_m+2)^2 complex matrix,
+ * row-major, rows and columns in the [alpha, beta] / [a, b] order above.
+ * offsets has n+1 entries counted in complex elements. */
+int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets);
+
+/* Closed-form scattering matrix of a disk of radius a (Section 3.1: boundary
+ * condition imposed mode by mode; bc 0 rigid u = 0, bc 1 traction-free).
+ * Writes (4p+2)^2 complex128 row-major into host memory S_out. */
+int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double *S_out);
+
+/* Sommerfeld quadrature choice (Section 4.1); default kind 1 when never set. */
+int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s);
+
+/* Host-only: the node table that ems_build would use for this cloud (same
+ * rules as ems_set_sommerfeld), without touching the GPU.  xy [n][2] and p[n]
+ * host.  On entry *q is the capacity of nodes_out (entries of 6 doubles:
+ * Re xi, Im xi, Re w, Im w, bp, d where a node of a branch-point panel has
+ * xi = bp + d exactly and bp = 0 marks an ordinary node); on return *q is the
+ * node count.  nodes_out may be NULL to query the count.  *t_max receives the
+ * tail extent used. */
+int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
+                         const double *xy, const int32_t *p, int32_t *q, double *nodes_out,
+                         double *t_max);
+
+/* Host-only: the 2x2 reflection R(xi) of upgoing P / S potentials at the
+ * welded interface (Section 2.2, the 4x4 continuity system per Fourier mode,
+ * density kept), row-major complex128 into R_out[8]. */
+int ems_reflection(const ems_media *m, double xi_re, double xi_im, double *R_out);
+
+/* Validate, build the node table and the per-node 2x2 reflection R(xi_j)
+ * (the 4x4 interface system of Section 2.2 solved per node), pack the S
+ * store, allocate device workspace.  Synchronous. */
+int ems_build(ems_handle *h, ems_stream_t stream);
+int ems_get_info(const ems_handle *h, ems_build_info *out);
+
+/* Operator apply on device buffers x, y (complex128, [nrhs][n_coeff], may not
+ * alias): with flags = EMS_APPLY_ALL,
+ *   y_m = x_m - S_m ( (T_free x)_m + (T_refl x)_m )
+ * the Schur-complement operator of Section 4.2 (free part: Section 3.2,
+ * reflected part: Sections 4.3-4.4).  Fewer part bits give the pieces
+ * (e.g. EMS_PART_REFL alone returns the raw reflected local coefficients).
+ * EMS_MIXED runs the contractions in FP32. */
+int ems_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+              ems_stream_t stream);
+
+/* Conjugate-transpose apply (same flags; y = x - T^H S^H x for ALL). */
+int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+                      ems_stream_t stream);
+
+/* Right-hand side S_m (a0^m, b0^m) of the S-preconditioned system (Section
+ * 3.2) for nrhs plane waves (incident + interface-reflected background,
+ * Section 6.3), into device memory rhs [nrhs][n_coeff]. */
+int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void *rhs,
+                 ems_stream_t stream);
+
+/* GMRES on the operator (Sections 3.2 and 4.2): x0 = 0, nrhs independent
+ * systems advanced in lock-step.  b, x device memory [nrhs][n_coeff].
+ * Returns EMS_NOT_CONVERGED when maxit is reached.  Synchronous. */
+int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_solver_opts *o,
+              ems_solve_info *info, ems_stream_t stream);
+
+/* Scattered displacement at npts host points (Section 4, coupled
+ * representation: outgoing particle fields plus the reflected Sommerfeld
+ * field).  gamma device [nrhs][n_coeff]; pts device [npts][2] doubles;
+ * u device [nrhs][npts][2] complex128. */
+int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
+                       const double *pts, void *u, ems_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMS_H */

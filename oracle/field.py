@@ -73,9 +73,9 @@ def reflected_part(w, m: Media, gamma: np.ndarray, pts: np.ndarray, tol: float =
     px, py = pts[:, 0], pts[:, 1]
     npt = len(pts)
 
-    def f(xi):
-        sp = complex(interface.branch_s(xi, kp))
-        ss = complex(interface.branch_s(xi, ks))
+    def f(xi, bp=None, d=None):
+        sv = interface.s_values(xi, m, bp, d)
+        sp, ss = sv[0], sv[1]
         zp = (xi - sp) / kp
         zs = (xi - ss) / ks
         Ip = 0j
@@ -86,7 +86,7 @@ def reflected_part(w, m: Media, gamma: np.ndarray, pts: np.ndarray, tol: float =
             Is += np.sum(np.exp(ss * ys - 1j * xi * xs) * (cb @ ((-1j * zs) ** n)))
         Ip /= 1j * math.pi * sp
         Is /= 1j * math.pi * ss
-        R = interface.reflection(xi, m)
+        R = interface.reflection(xi, m, sv)
         RP = R[0, 0] * Ip + R[0, 1] * Is
         RS = R[1, 0] * Ip + R[1, 1] * Is
         ep = np.exp(1j * xi * px + sp * py) * RP

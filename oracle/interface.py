@@ -25,6 +25,8 @@ The bottom 2x2 block is the transmission T(xi).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from .media import Media
@@ -45,18 +47,32 @@ def branch_s(xi, k: float):
     return -1j * np.sqrt(k * k - xi * xi)
 
 
+def branch_s_offset(bp: float, d: float, k: float):
+    """s at xi = bp + d exactly, bp = +-k: xi^2 - k^2 = d (2 bp + d), no cancellation."""
+    v = d * (2.0 * bp + d)
+    return math.sqrt(v) + 0j if v > 0 else -1j * math.sqrt(max(-v, 0.0))
+
+
+def s_values(xi, m: Media, bp=None, d=None):
+    """(s_p, s_s, s_pb, s_sb) at xi; with (bp, d) the wavenumber equal to |bp| uses the offset."""
+    out = []
+    for k in (m.kp, m.ks, m.kpb, m.ksb):
+        if bp is not None and abs(abs(bp) - k) <= 1e-14 * k:
+            out.append(branch_s_offset(bp, d, k))
+        else:
+            out.append(complex(branch_s(xi, k)))
+    return out
+
+
 def _cols(xi, q, lam, mu):
     P = np.array([1j * xi, q, 2 * mu * 1j * xi * q, (lam + 2 * mu) * q * q - lam * xi * xi])
     S = np.array([-q, 1j * xi, -mu * (q * q + xi * xi), 2 * mu * 1j * xi * q])
     return P, S
 
 
-def system(xi, m: Media):
+def system(xi, m: Media, svals=None):
     """The 4x4 matrix and 4x2 right-hand side at one xi."""
-    sp = branch_s(xi, m.kp)
-    ss = branch_s(xi, m.ks)
-    spb = branch_s(xi, m.kpb)
-    ssb = branch_s(xi, m.ksb)
+    sp, ss, spb, ssb = svals if svals is not None else s_values(xi, m)
     Pr, _ = _cols(xi, +sp, m.lam_h, m.mu_h)
     _, Sr = _cols(xi, +ss, m.lam_h, m.mu_h)
     Pi, _ = _cols(xi, -sp, m.lam_h, m.mu_h)
@@ -68,15 +84,15 @@ def system(xi, m: Media):
     return M, rhs
 
 
-def reflect_transmit(xi, m: Media):
+def reflect_transmit(xi, m: Media, svals=None):
     """(R, T), each 2x2, at one scalar xi."""
-    M, rhs = system(xi, m)
+    M, rhs = system(xi, m, svals)
     X = np.linalg.solve(M, rhs)
     return X[:2, :], X[2:, :]
 
 
-def reflection(xi, m: Media) -> np.ndarray:
-    return reflect_transmit(xi, m)[0]
+def reflection(xi, m: Media, svals=None) -> np.ndarray:
+    return reflect_transmit(xi, m, svals)[0]
 
 
 def reflection_many(xis, m: Media) -> np.ndarray:

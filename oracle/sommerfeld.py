@@ -64,9 +64,9 @@ def _integrand_factory(w, m: Media, x: np.ndarray, targets, S_blocks, R_fun):
         src_coef.append((c[:, :N], c[:, N:]))
     out_len = int(sum(2 * (2 * pv + 1) * len(sel) for pv, sel, *_ in tgt.items))
 
-    def f(xi: float) -> np.ndarray:
-        sp = complex(interface.branch_s(xi, kp))
-        ss = complex(interface.branch_s(xi, ks))
+    def f(xi: float, bp=None, d=None) -> np.ndarray:
+        sv = interface.s_values(xi, m, bp, d)
+        sp, ss = sv[0], sv[1]
         zp = (xi - sp) / kp
         zs = (xi - ss) / ks
         Ip = 0j
@@ -79,7 +79,7 @@ def _integrand_factory(w, m: Media, x: np.ndarray, targets, S_blocks, R_fun):
             Is += np.sum(Es * (cb @ ((-1j * zs) ** n)))
         Ip /= 1j * math.pi * sp
         Is /= 1j * math.pi * ss
-        R = R_fun(xi)
+        R = R_fun(xi, sv)
         RP = R[0, 0] * Ip + R[0, 1] * Is
         RS = R[1, 0] * Ip + R[1, 1] * Is
         parts = []
@@ -134,11 +134,13 @@ def _pieces(m: Media, T: float, sub_len: float = 0.5):
 def _integrate(f, out_len, pieces, tol, limit, floor=0.0):
     """Sum of adaptive integrals over the pieces, real-valued output vector."""
     def wrap(kind, a, b):
+        # on a substituted piece the exact offset u^2 from the branch point is
+        # passed along, so s = sqrt(d (2 bp + d)) loses nothing to cancellation
         if kind == 0:
             return (lambda t: f(t)), a, b
         if kind == +1:
-            return (lambda u: f(a + u * u) * (2.0 * u)), 0.0, math.sqrt(b - a)
-        return (lambda u: f(b - u * u) * (2.0 * u)), 0.0, math.sqrt(b - a)
+            return (lambda u: f(a + u * u, a, u * u) * (2.0 * u)), 0.0, math.sqrt(b - a)
+        return (lambda u: f(b - u * u, b, -u * u) * (2.0 * u)), 0.0, math.sqrt(b - a)
 
     # coarse pass to set the absolute error scale
     coarse = np.zeros(2 * out_len)
@@ -172,7 +174,10 @@ def apply_refl(w, m: Media, x: np.ndarray, targets=None, S_blocks=None, R_fun=No
     if targets is None:
         targets = list(range(w.n))
     if R_fun is None:
-        R_fun = lambda xi: interface.reflection(xi, m)  # noqa: E731
+        R_fun = lambda xi, sv: interface.reflection(xi, m, sv)  # noqa: E731
+    else:
+        user_R = R_fun
+        R_fun = lambda xi, sv: user_R(xi)  # noqa: E731
     f, out_len, tgt = _integrand_factory(w, m, np.asarray(x, complex), targets, S_blocks, R_fun)
     if T is None:
         T = tail_extent(w, m)

@@ -1,0 +1,294 @@
+"""Python binding of libems.so, the MI355X multiple-scattering operator library.
+
+Argument marshalling only: every step of the operator runs in the HIP
+kernels of ``csrc/``.  Torch supplies device memory and the stream.  Importing
+this module fails loudly when the compiled library is missing.
+
+Names follow include/ems.h.  Coefficient vectors are complex128 torch tensors
+of shape [nrhs, n_coeff] on the current CUDA (HIP) device, per particle laid
+out as [alpha_{-p..p}, beta_{-p..p}].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libems.so")
+
+EMS_PART_FREE = 1
+EMS_PART_REFL = 2
+EMS_PART_S = 4
+EMS_PART_IDENTITY = 8
+EMS_APPLY_ALL = 15
+EMS_MIXED = 256
+EMS_OK = 0
+EMS_NOT_CONVERGED = 1
+
+
+class EmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ems error {code}: {msg}")
+        self.code = code
+
+
+class Medium(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
+
+
+class Media(ctypes.Structure):
+    _fields_ = [("host", Medium), ("substrate", Medium), ("omega", ctypes.c_double)]
+
+
+class Sommerfeld(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q", ctypes.c_int32), ("t_max", ctypes.c_double),
+                ("delta", ctypes.c_double), ("panel_scale", ctypes.c_double),
+                ("nodes", ctypes.POINTER(ctypes.c_double)), ("panel_order", ctypes.c_int32)]
+
+
+class PlaneWave(ctypes.Structure):
+    _fields_ = [("wave", ctypes.c_int32), ("angle", ctypes.c_double)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class BuildInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p_max", ctypes.c_int32), ("n_coeff", ctypes.c_int64),
+                ("q", ctypes.c_int32), ("t_max", ctypes.c_double), ("n_pairs", ctypes.c_int64),
+                ("kp", ctypes.c_double), ("ks", ctypes.c_double), ("kpb", ctypes.c_double),
+                ("ksb", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ems_create": ([ctypes.POINTER(P)], I32),
+        "ems_destroy": ([P], None),
+        "ems_last_error": ([P], ctypes.c_char_p),
+        "ems_set_media": ([P, ctypes.POINTER(Media)], I32),
+        "ems_set_particles": ([P, I32, P, P, P], I32),
+        "ems_set_smatrices": ([P, P, P], I32),
+        "ems_smatrix_disk": ([ctypes.POINTER(Media), D, I32, I32, P], I32),
+        "ems_set_sommerfeld": ([P, ctypes.POINTER(Sommerfeld)], I32),
+        "ems_build": ([P, P], I32),
+        "ems_get_info": ([P, ctypes.POINTER(BuildInfo)], I32),
+        "ems_apply": ([P, P, P, I32, I32, P], I32),
+        "ems_apply_adjoint": ([P, P, P, I32, I32, P], I32),
+        "ems_incident": ([P, ctypes.POINTER(PlaneWave), I32, P, P], I32),
+        "ems_solve": ([P, P, P, I32, ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveInfo), P], I32),
+        "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
+        "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
+                                  ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
+        "ems_reflection": ([ctypes.POINTER(Media), D, D, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
+            "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
+            "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
+            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection")
+
+
+def lib():
+    return _lib
+
+
+def make_media(host, substrate, omega) -> Media:
+    """host/substrate: objects with lam, mu, rho attributes or 3-tuples."""
+    def med(m):
+        if hasattr(m, "lam"):
+            return Medium(m.lam, m.mu, m.rho)
+        return Medium(*m)
+    return Media(med(host), med(substrate), float(omega))
+
+
+def smatrix_disk(media: Media, a: float, p: int, bc: int) -> np.ndarray:
+    """Closed-form disk scattering matrix [(4p+2), (4p+2)] complex128 (host)."""
+    K = 4 * p + 2
+    out = np.zeros((K, K), dtype=np.complex128)
+    rc = _lib.ems_smatrix_disk(ctypes.byref(media), float(a), int(p), int(bc),
+                               out.ctypes.data_as(ctypes.c_void_p))
+    if rc != EMS_OK:
+        raise EmsError(rc, "ems_smatrix_disk failed")
+    return out
+
+
+def sommerfeld_nodes(media: Media, xy, p, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0,
+                     panel_order=0):
+    """Host-only node table [q, 6] = (Re xi, Im xi, Re w, Im w, bp, d) and the tail extent."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.int32)
+    s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), None,
+                   int(panel_order))
+    cnt = ctypes.c_int32(0)
+    tm = ctypes.c_double(0)
+    rc = _lib.ems_sommerfeld_nodes(ctypes.byref(media), ctypes.byref(s), len(p), xy.ctypes.data,
+                                   p.ctypes.data, ctypes.byref(cnt), None, ctypes.byref(tm))
+    if rc != EMS_OK:
+        raise EmsError(rc, "ems_sommerfeld_nodes failed")
+    out = np.zeros((cnt.value, 6))
+    rc = _lib.ems_sommerfeld_nodes(ctypes.byref(media), ctypes.byref(s), len(p), xy.ctypes.data,
+                                   p.ctypes.data, ctypes.byref(cnt), out.ctypes.data, ctypes.byref(tm))
+    if rc != EMS_OK:
+        raise EmsError(rc, "ems_sommerfeld_nodes failed")
+    return out, tm.value
+
+
+def reflection(media: Media, xi: complex) -> np.ndarray:
+    """Host-only 2x2 interface reflection R(xi)."""
+    out = np.zeros(8)
+    rc = _lib.ems_reflection(ctypes.byref(media), float(np.real(xi)), float(np.imag(xi)),
+                             out.ctypes.data)
+    if rc != EMS_OK:
+        raise EmsError(rc, "ems_reflection failed")
+    return (out[0::2] + 1j * out[1::2]).reshape(2, 2)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Operator:
+    """Handle around one particle cloud, its media, S-matrices and node table."""
+
+    def __init__(self, xy, radius, p, media: Media, S_blocks=None, bc=None, sommerfeld=None):
+        self.h = ctypes.c_void_p()
+        self._check(_lib.ems_create(ctypes.byref(self.h)))
+        self.media = media
+        self.n = len(p)
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.radius = np.ascontiguousarray(radius, dtype=np.float64)
+        self.p = np.ascontiguousarray(p, dtype=np.int32)
+        self._check(_lib.ems_set_media(self.h, ctypes.byref(media)))
+        self._check(_lib.ems_set_particles(self.h, self.n, self.xy.ctypes.data, self.radius.ctypes.data,
+                                           self.p.ctypes.data))
+        if S_blocks is None:
+            if bc is None:
+                raise ValueError("give S_blocks or bc for closed-form disks")
+            S_blocks = self.disk_blocks(bc)
+        self.set_smatrices(S_blocks)
+        if sommerfeld is not None:
+            self.set_sommerfeld(**sommerfeld)
+        self.built = False
+
+    def disk_blocks(self, bc):
+        cache = {}
+        out = []
+        for a, pm, b in zip(self.radius, self.p, np.asarray(bc)):
+            key = (float(a), int(pm), int(b))
+            if key not in cache:
+                cache[key] = smatrix_disk(self.media, *key)
+            out.append(cache[key])
+        return out
+
+    def set_smatrices(self, blocks):
+        sizes = [b.size for b in blocks]
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.complex128).ravel() for b in blocks]))
+        self._S_keep = flat
+        self._check(_lib.ems_set_smatrices(self.h, flat.ctypes.data, off.ctypes.data))
+        self.built = False
+
+    def set_sommerfeld(self, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0, nodes=None,
+                       panel_order=0):
+        ptr = None
+        if nodes is not None:
+            self._nodes_keep = np.ascontiguousarray(nodes, dtype=np.float64)
+            ptr = self._nodes_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            q = self._nodes_keep.shape[0]
+        s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), ptr,
+                       int(panel_order))
+        self._check(_lib.ems_set_sommerfeld(self.h, ctypes.byref(s)))
+        self.built = False
+
+    def build(self, stream=None):
+        self._check(_lib.ems_build(self.h, _stream_ptr(stream)))
+        self.built = True
+        return self.info()
+
+    def info(self) -> dict:
+        bi = BuildInfo()
+        self._check(_lib.ems_get_info(self.h, ctypes.byref(bi)))
+        return {k: getattr(bi, k) for k, _ in BuildInfo._fields_}
+
+    @property
+    def n_coeff(self) -> int:
+        return int(np.sum(2 * (2 * self.p.astype(np.int64) + 1)))
+
+    def _vec_check(self, t, nrhs=None):
+        import torch
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("coefficient tensors must be contiguous complex128 on the GPU")
+        if t.shape[-1] != self.n_coeff:
+            raise ValueError(f"last dimension must be n_coeff = {self.n_coeff}")
+        return 1 if t.dim() == 1 else t.shape[0]
+
+    def apply(self, x, y=None, flags=EMS_APPLY_ALL, adjoint=False, stream=None):
+        import torch
+        nrhs = self._vec_check(x)
+        if y is None:
+            y = torch.empty_like(x)
+        self._vec_check(y)
+        f = _lib.ems_apply_adjoint if adjoint else _lib.ems_apply
+        self._check(f(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nrhs,
+                      int(flags), _stream_ptr(stream)))
+        return y
+
+    def incident(self, waves, stream=None):
+        """waves: list of (wave, angle) with wave 0 = P, 1 = SV."""
+        import torch
+        arr = (PlaneWave * len(waves))(*[PlaneWave(int(w), float(a)) for w, a in waves])
+        out = torch.empty((len(waves), self.n_coeff), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_incident(self.h, arr, len(waves), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_ptr(stream)))
+        return out
+
+    def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-6,
+              stream=None):
+        import torch
+        nrhs = self._vec_check(b)
+        x = torch.empty_like(b)
+        o = SolverOpts(float(tol), int(restart), int(maxit), int(precision), float(inner_tol))
+        info = SolveInfo()
+        rc = _lib.ems_solve(self.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            nrhs, ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+        if rc < 0:
+            self._check(rc)
+        return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+
+    def _check(self, rc):
+        if rc < 0:
+            msg = _lib.ems_last_error(self.h).decode() if self.h else ""
+            raise EmsError(rc, msg)
+        return rc
+
+    def __del__(self):
+        try:
+            if self.h:
+                _lib.ems_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass

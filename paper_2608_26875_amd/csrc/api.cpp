@@ -1,0 +1,807 @@
+// C ABI of the library: handle life cycle, validation, set-up, the operator
+// apply pipeline and the GMRES driver (Saad-Schultz GMRES named in Sections
+// 3.2 and 4.2, restarted, CGS2 Arnoldi on the device, Givens on the host).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "ems_internal.h"
+
+namespace ems {
+hipError_t launch_s_apply(const ems_handle *h, const double2 *c, double2 *y, int nrhs,
+                          bool adjoint, hipStream_t st);
+hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, double2 *c,
+                              hipStream_t st);
+}  // namespace ems
+
+using ems::cd;
+
+namespace {
+
+int fail(ems_handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((h), e_ == hipErrorOutOfMemory ? EMS_ERR_OOM : EMS_ERR_HIP,            \
+                  std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_device(ems_handle *h) {
+  dfree(h->d_xy);
+  dfree(h->d_p);
+  dfree(h->d_off);
+  dfree(h->d_S);
+  dfree(h->d_S32);
+  dfree(h->d_Soff);
+  dfree(h->d_xi);
+  dfree(h->d_w);
+  dfree(h->d_sp);
+  dfree(h->d_ss);
+  dfree(h->d_R);
+  dfree(h->d_Vp);
+  dfree(h->d_Vs);
+  dfree(h->d_agg);
+  dfree(h->d_refl);
+  dfree(h->d_dis);
+  dfree(h->d_free);
+  dfree(h->d_V);
+  dfree(h->d_tmp);
+  dfree(h->d_red);
+  h->ws_nrhs = 0;
+  h->V_bytes = h->tmp_bytes = h->red_bytes = 0;
+}
+
+template <typename T>
+int upload(ems_handle *h, T *&dst, const T *src, size_t count) {
+  dfree(dst);
+  if (count == 0) return EMS_OK;
+  HIPCHK(h, hipMalloc(&dst, count * sizeof(T)));
+  HIPCHK(h, hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return EMS_OK;
+}
+
+bool finite_all(const double *v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// Workspace for nrhs right-hand sides.
+int ensure_ws(ems_handle *h, int nrhs) {
+  if (h->ws_nrhs >= nrhs) return EMS_OK;
+  dfree(h->d_agg);
+  dfree(h->d_refl);
+  dfree(h->d_dis);
+  dfree(h->d_free);
+  const int node_tiles = (h->q + 255) / 256;
+  const int part_tiles = (h->n + 255) / 256;
+  h->agg_chunks = std::max(1, std::min(std::max(1, h->n / 8),
+                                       (4096 + 2 * nrhs * node_tiles - 1) / (2 * nrhs * node_tiles)));
+  h->dis_chunks = std::max(1, std::min(std::max(1, h->q / 32),
+                                       (4096 + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
+  const size_t nc = (size_t)h->ncoef;
+  HIPCHK(h, hipMalloc(&h->d_agg, sizeof(double2) * (size_t)nrhs * 2 * h->agg_chunks * h->q));
+  HIPCHK(h, hipMalloc(&h->d_refl, sizeof(double2) * (size_t)nrhs * 2 * h->q));
+  HIPCHK(h, hipMalloc(&h->d_dis, sizeof(double2) * (size_t)nrhs * h->dis_chunks * nc));
+  HIPCHK(h, hipMalloc(&h->d_free, sizeof(double2) * (size_t)nrhs * nc));
+  h->ws_nrhs = nrhs;
+  return EMS_OK;
+}
+
+int ensure_tmp(ems_handle *h, size_t bytes) {
+  if (h->tmp_bytes >= bytes) return EMS_OK;
+  dfree(h->d_tmp);
+  HIPCHK(h, hipMalloc(&h->d_tmp, bytes));
+  h->tmp_bytes = bytes;
+  return EMS_OK;
+}
+
+int ensure_red(ems_handle *h, size_t bytes) {
+  if (h->red_bytes >= bytes) return EMS_OK;
+  dfree(h->d_red);
+  HIPCHK(h, hipMalloc(&h->d_red, bytes));
+  h->red_bytes = bytes;
+  return EMS_OK;
+}
+
+int check_geometry(ems_handle *h) {
+  const int n = h->n;
+  double Rmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!(h->R[i] > 0)) return fail(h, EMS_ERR_GEOMETRY, "enclosing radius must be > 0");
+    if (!(h->xy[2 * i + 1] + h->R[i] < 0))
+      return fail(h, EMS_ERR_GEOMETRY,
+                  "particle " + std::to_string(i) + ": enclosing disk reaches the interface y = 0");
+    Rmax = std::max(Rmax, h->R[i]);
+  }
+  // cell grid with cell >= 2 Rmax: overlapping disks are in neighbouring cells
+  const double cell = 2.0 * Rmax;
+  std::map<std::pair<long, long>, std::vector<int>> grid;
+  for (int i = 0; i < n; ++i)
+    grid[{(long)std::floor(h->xy[2 * i] / cell), (long)std::floor(h->xy[2 * i + 1] / cell)}]
+        .push_back(i);
+  for (int i = 0; i < n; ++i) {
+    const long cx = (long)std::floor(h->xy[2 * i] / cell);
+    const long cy = (long)std::floor(h->xy[2 * i + 1] / cell);
+    for (long gx = cx - 1; gx <= cx + 1; ++gx)
+      for (long gy = cy - 1; gy <= cy + 1; ++gy) {
+        auto it = grid.find({gx, gy});
+        if (it == grid.end()) continue;
+        for (int j : it->second) {
+          if (j <= i) continue;
+          const double dx = h->xy[2 * i] - h->xy[2 * j], dy = h->xy[2 * i + 1] - h->xy[2 * j + 1];
+          if (std::sqrt(dx * dx + dy * dy) <= h->R[i] + h->R[j])
+            return fail(h, EMS_ERR_GEOMETRY,
+                        "enclosing disks of particles " + std::to_string(i) + " and " +
+                            std::to_string(j) + " overlap");
+        }
+      }
+  }
+  return EMS_OK;
+}
+
+int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags, bool adjoint,
+               hipStream_t st) {
+  const bool mixed = (flags & EMS_MIXED) != 0;
+  const int parts = flags & 15;
+  if ((parts & EMS_PART_IDENTITY) && !(parts & EMS_PART_S))
+    return fail(h, EMS_ERR_ARG, "EMS_PART_IDENTITY needs EMS_PART_S");
+  int rc = ensure_ws(h, nrhs);
+  if (rc) return rc;
+  const double2 *src = x;
+  if (adjoint && (parts & EMS_PART_S)) {
+    rc = ensure_tmp(h, sizeof(double2) * (size_t)nrhs * h->ncoef);
+    if (rc) return rc;
+    HIPCHK(h, ems::launch_s_apply(h, x, h->d_tmp, nrhs, true, st));
+    src = h->d_tmp;
+  }
+  if (parts & EMS_PART_FREE) HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+  if (parts & EMS_PART_REFL) {
+    HIPCHK(h, ems::launch_somm_aggregate(h, src, nrhs, adjoint, mixed, st));
+    HIPCHK(h, ems::launch_somm_reflect(h, nrhs, adjoint, st));
+    HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, adjoint, mixed, st));
+  }
+  int cflags = parts;
+  if (adjoint) cflags &= ~EMS_PART_S;
+  HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, st));
+  return EMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ems_create(ems_handle **out) {
+  if (!out) return EMS_ERR_ARG;
+  ems_handle *h = new (std::nothrow) ems_handle();
+  if (!h) return EMS_ERR_OOM;
+  // No device is touched before ems_build, so argument and geometry checks
+  // also run on hosts without a GPU.
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
+  *out = h;
+  return EMS_OK;
+}
+
+void ems_destroy(ems_handle *h) {
+  if (!h) return;
+  free_device(h);
+  delete h;
+}
+
+const char *ems_last_error(const ems_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int ems_set_media(ems_handle *h, const ems_media *m) {
+  if (!h || !m) return EMS_ERR_ARG;
+  const double v[7] = {m->host.lambda, m->host.mu, m->host.rho, m->substrate.lambda,
+                       m->substrate.mu, m->substrate.rho, m->omega};
+  if (!finite_all(v, 7)) return fail(h, EMS_ERR_NUMERIC, "non-finite media parameter");
+  if (!(m->host.mu > 0 && m->host.lambda + m->host.mu > 0 && m->substrate.mu > 0 &&
+        m->substrate.lambda + m->substrate.mu > 0 && m->host.rho > 0 && m->substrate.rho > 0 &&
+        m->omega > 0))
+    return fail(h, EMS_ERR_ARG, "need mu > 0, lambda + mu > 0, rho > 0, omega > 0");
+  h->md = ems::make_media(*m);
+  h->have_media = true;
+  h->built = false;
+  return EMS_OK;
+}
+
+int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *R,
+                      const int32_t *p) {
+  if (!h || n <= 0 || !xy || !R || !p) return fail(h, EMS_ERR_ARG, "bad particle arguments");
+  if (!finite_all(xy, 2 * (size_t)n) || !finite_all(R, n))
+    return fail(h, EMS_ERR_NUMERIC, "non-finite particle data");
+  h->n = n;
+  h->xy.assign(xy, xy + 2 * (size_t)n);
+  h->R.assign(R, R + n);
+  h->p.assign(p, p + n);
+  h->off.assign(n + 1, 0);
+  h->pmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (p[i] < 1 || p[i] > ems::kMaxP)
+      return fail(h, EMS_ERR_UNIMPLEMENTED, "truncation order must be in [1, 15]");
+    h->off[i + 1] = h->off[i] + 2 * (2 * p[i] + 1);
+    h->pmax = std::max(h->pmax, p[i]);
+  }
+  h->ncoef = h->off[n];
+  h->have_particles = true;
+  h->have_s = false;
+  h->built = false;
+  return EMS_OK;
+}
+
+int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets) {
+  if (!h || !S || !offsets) return fail(h, EMS_ERR_ARG, "null S");
+  if (!h->have_particles) return fail(h, EMS_ERR_STATE, "set particles before S-matrices");
+  h->S_off.assign(offsets, offsets + h->n + 1);
+  for (int i = 0; i < h->n; ++i) {
+    const int64_t K = 4 * h->p[i] + 2;
+    if (offsets[i + 1] - offsets[i] != K * K)
+      return fail(h, EMS_ERR_ARG, "S offsets do not match (4p+2)^2 blocks");
+  }
+  const size_t tot = (size_t)offsets[h->n];
+  if (!finite_all(S, 2 * tot)) return fail(h, EMS_ERR_NUMERIC, "non-finite S entry");
+  h->S_host.resize(tot);
+  for (size_t k = 0; k < tot; ++k) h->S_host[k] = cd(S[2 * k], S[2 * k + 1]);
+  h->have_s = true;
+  h->built = false;
+  return EMS_OK;
+}
+
+int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double *S_out) {
+  if (!m || !S_out || !(a > 0) || p < 0 || (bc != 0 && bc != 1)) return EMS_ERR_ARG;
+  std::vector<cd> S;
+  const int rc = ems::disk_smatrix(ems::make_media(*m), a, p, bc, S);
+  if (rc) return rc;
+  for (size_t k = 0; k < S.size(); ++k) {
+    S_out[2 * k] = S[k].real();
+    S_out[2 * k + 1] = S[k].imag();
+  }
+  return EMS_OK;
+}
+
+static int spec_from(const ems_sommerfeld *s, ems::SommerfeldSpec &o, std::string &err) {
+  if (s->kind < 0 || s->kind > 2) {
+    err = "sommerfeld kind must be 0, 1, 2";
+    return EMS_ERR_ARG;
+  }
+  o.kind = s->kind;
+  o.q = s->q;
+  o.t_max = s->t_max;
+  o.delta = s->delta > 0 ? s->delta : 0.5;
+  o.panel_scale = s->panel_scale > 0 ? s->panel_scale : 1.0;
+  o.panel_order = s->panel_order > 0 ? s->panel_order : 64;
+  if (o.panel_order < 8 || o.panel_order > 256) {
+    err = "panel_order must be in [8, 256]";
+    return EMS_ERR_ARG;
+  }
+  o.user.clear();
+  if (s->kind == 2) {
+    if (!s->nodes || s->q <= 0) {
+      err = "kind 2 needs q nodes";
+      return EMS_ERR_ARG;
+    }
+    o.user.assign(s->nodes, s->nodes + 4 * (size_t)s->q);
+  }
+  return EMS_OK;
+}
+
+int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
+                         const double *xy, const int32_t *p, int32_t *q, double *nodes_out,
+                         double *t_max) {
+  if (!m || !s || n <= 0 || !xy || !p || !q) return EMS_ERR_ARG;
+  ems::SommerfeldSpec spec;
+  std::string err;
+  int rc = spec_from(s, spec, err);
+  if (rc) return rc;
+  std::vector<double> vxy(xy, xy + 2 * (size_t)n);
+  std::vector<int> vp(p, p + n);
+  ems::NodeTable nt;
+  rc = ems::build_nodes(spec, ems::make_media(*m), vxy, vp, nt, err);
+  if (rc) return rc;
+  const int cap = *q;
+  *q = (int32_t)nt.xi.size();
+  if (t_max) *t_max = nt.t_max;
+  if (nodes_out) {
+    if (cap < (int)nt.xi.size()) return EMS_ERR_ARG;
+    for (size_t j = 0; j < nt.xi.size(); ++j) {
+      nodes_out[6 * j] = nt.xi[j].real();
+      nodes_out[6 * j + 1] = nt.xi[j].imag();
+      nodes_out[6 * j + 2] = nt.w[j].real();
+      nodes_out[6 * j + 3] = nt.w[j].imag();
+      nodes_out[6 * j + 4] = nt.bp[j];
+      nodes_out[6 * j + 5] = nt.d[j];
+    }
+  }
+  return EMS_OK;
+}
+
+int ems_reflection(const ems_media *m, double xi_re, double xi_im, double *R_out) {
+  if (!m || !R_out) return EMS_ERR_ARG;
+  cd R[4];
+  const int rc = ems::reflection(cd(xi_re, xi_im), ems::make_media(*m), R);
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) {
+    R_out[2 * k] = R[k].real();
+    R_out[2 * k + 1] = R[k].imag();
+  }
+  return EMS_OK;
+}
+
+int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s) {
+  if (!h || !s) return EMS_ERR_ARG;
+  const int rc = spec_from(s, h->somm, h->err);
+  if (rc) return rc;
+  h->built = false;
+  return EMS_OK;
+}
+
+int ems_build(ems_handle *h, ems_stream_t stream) {
+  (void)stream;
+  if (!h) return EMS_ERR_ARG;
+  if (!h->have_media || !h->have_particles || !h->have_s)
+    return fail(h, EMS_ERR_STATE, "set media, particles and S-matrices before build");
+  int rc = check_geometry(h);
+  if (rc) return rc;
+  if (h->device < 0) return fail(h, EMS_ERR_HIP, "no HIP device");
+  free_device(h);
+  // node table and per-node reflection
+  ems::NodeTable nt;
+  rc = ems::build_nodes(h->somm, h->md, h->xy, h->p, nt, h->err);
+  if (rc) return rc;
+  h->nodes = nt;
+  h->q = (int)nt.xi.size();
+  const int q = h->q, ld = 2 * h->pmax + 1;
+  std::vector<double2> xi(q), w(q), sp(q), ss(q), R(4 * (size_t)q), Vp((size_t)q * ld),
+      Vs((size_t)q * ld);
+  const cd I(0.0, 1.0);
+  for (int j = 0; j < q; ++j) {
+    const cd x = nt.xi[j];
+    cd s4[4];
+    ems::node_s(x, nt.bp[j], nt.d[j], h->md, s4);
+    const cd s1 = s4[0], s2 = s4[1];
+    cd Rj[4];
+    rc = ems::reflection_s(x, s4, h->md, Rj);
+    if (rc) return fail(h, rc, "singular interface system at a Sommerfeld node");
+    xi[j] = make_double2(x.real(), x.imag());
+    w[j] = make_double2(nt.w[j].real(), nt.w[j].imag());
+    sp[j] = make_double2(s1.real(), s1.imag());
+    ss[j] = make_double2(s2.real(), s2.imag());
+    for (int k = 0; k < 4; ++k) R[4 * (size_t)j + k] = make_double2(Rj[k].real(), Rj[k].imag());
+    // V[j][n] = (-i zeta)^n, zeta = (xi - s)/k
+    const cd zp = -I * (x - s1) / h->md.kp, zs = -I * (x - s2) / h->md.ks;
+    cd ap = 1.0, as = 1.0, bp = 1.0, bs = 1.0;
+    const cd izp = 1.0 / zp, izs = 1.0 / zs;
+    Vp[(size_t)j * ld + h->pmax] = make_double2(1.0, 0.0);
+    Vs[(size_t)j * ld + h->pmax] = make_double2(1.0, 0.0);
+    for (int n = 1; n <= h->pmax; ++n) {
+      ap *= zp;
+      as *= zs;
+      bp *= izp;
+      bs *= izs;
+      Vp[(size_t)j * ld + h->pmax + n] = make_double2(ap.real(), ap.imag());
+      Vs[(size_t)j * ld + h->pmax + n] = make_double2(as.real(), as.imag());
+      Vp[(size_t)j * ld + h->pmax - n] = make_double2(bp.real(), bp.imag());
+      Vs[(size_t)j * ld + h->pmax - n] = make_double2(bs.real(), bs.imag());
+    }
+  }
+  // packed S store: per particle column-major
+  std::vector<double2> St(h->S_host.size());
+  for (int m = 0; m < h->n; ++m) {
+    const int64_t K = 4 * h->p[m] + 2, o = h->S_off[m];
+    for (int64_t r = 0; r < K; ++r)
+      for (int64_t c = 0; c < K; ++c) {
+        const cd v = h->S_host[o + r * K + c];
+        St[o + c * K + r] = make_double2(v.real(), v.imag());
+      }
+  }
+  std::vector<float2> St32(St.size());
+  for (size_t k = 0; k < St.size(); ++k) St32[k] = make_float2((float)St[k].x, (float)St[k].y);
+  if ((rc = upload(h, h->d_xy, h->xy.data(), h->xy.size()))) return rc;
+  std::vector<int> pv(h->p.begin(), h->p.end());
+  if ((rc = upload(h, h->d_p, pv.data(), pv.size()))) return rc;
+  if ((rc = upload(h, h->d_off, h->off.data(), h->off.size()))) return rc;
+  if ((rc = upload(h, h->d_Soff, h->S_off.data(), h->S_off.size()))) return rc;
+  if ((rc = upload(h, h->d_S, St.data(), St.size()))) return rc;
+  if ((rc = upload(h, h->d_S32, St32.data(), St32.size()))) return rc;
+  if ((rc = upload(h, h->d_xi, xi.data(), xi.size()))) return rc;
+  if ((rc = upload(h, h->d_w, w.data(), w.size()))) return rc;
+  if ((rc = upload(h, h->d_sp, sp.data(), sp.size()))) return rc;
+  if ((rc = upload(h, h->d_ss, ss.data(), ss.size()))) return rc;
+  if ((rc = upload(h, h->d_R, R.data(), R.size()))) return rc;
+  if ((rc = upload(h, h->d_Vp, Vp.data(), Vp.size()))) return rc;
+  if ((rc = upload(h, h->d_Vs, Vs.data(), Vs.size()))) return rc;
+  h->n_pairs = (int64_t)h->n * (h->n - 1);
+  if ((rc = ensure_ws(h, 1))) return rc;
+  HIPCHK(h, hipDeviceSynchronize());
+  h->built = true;
+  return EMS_OK;
+}
+
+int ems_get_info(const ems_handle *h, ems_build_info *out) {
+  if (!h || !out) return EMS_ERR_ARG;
+  out->n = h->n;
+  out->p_max = h->pmax;
+  out->n_coeff = h->ncoef;
+  out->q = h->q;
+  out->t_max = h->nodes.t_max;
+  out->n_pairs = h->n_pairs;
+  out->kp = h->md.kp;
+  out->ks = h->md.ks;
+  out->kpb = h->md.kpb;
+  out->ksb = h->md.ksb;
+  return EMS_OK;
+}
+
+int ems_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+              ems_stream_t stream) {
+  if (!h || !x || !y || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad apply arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  if (x == y) return fail(h, EMS_ERR_ARG, "x and y must not alias");
+  return apply_impl(h, (const double2 *)x, (double2 *)y, nrhs, flags, false,
+                    (hipStream_t)stream);
+}
+
+int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+                      ems_stream_t stream) {
+  if (!h || !x || !y || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad apply arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  if (x == y) return fail(h, EMS_ERR_ARG, "x and y must not alias");
+  return apply_impl(h, (const double2 *)x, (double2 *)y, nrhs, flags, true, (hipStream_t)stream);
+}
+
+int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void *rhs,
+                 ems_stream_t stream) {
+  if (!h || !waves || !rhs || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad incident arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double2> pw(7 * (size_t)nrhs);
+  const cd I(0.0, 1.0);
+  for (int r = 0; r < nrhs; ++r) {
+    const int wv = waves[r].wave;
+    if (wv != 0 && wv != 1) return fail(h, EMS_ERR_ARG, "wave must be 0 (P) or 1 (SV)");
+    const double k = wv == 0 ? h->md.kp : h->md.ks;
+    const double xi0 = k * std::sin(waves[r].angle);
+    if (!(std::cos(waves[r].angle) > 0))
+      return fail(h, EMS_ERR_ARG, "plane wave must travel towards the interface (|angle| < pi/2)");
+    const cd A = 1.0 / (I * k);
+    const cd Ain_p = wv == 0 ? A : 0.0, Ain_s = wv == 1 ? A : 0.0;
+    cd R[4];
+    int rc = ems::reflection(cd(xi0, 0.0), h->md, R);
+    if (rc) return fail(h, rc, "singular interface system at the incident wavenumber");
+    const cd Ar_p = R[0] * Ain_p + R[1] * Ain_s, Ar_s = R[2] * Ain_p + R[3] * Ain_s;
+    const cd s1 = ems::branch_s(cd(xi0, 0.0), h->md.kp), s2 = ems::branch_s(cd(xi0, 0.0), h->md.ks);
+    const cd v[7] = {cd(xi0, 0.0), s1, s2, Ain_p, Ain_s, Ar_p, Ar_s};
+    for (int k2 = 0; k2 < 7; ++k2) pw[7 * (size_t)r + k2] = make_double2(v[k2].real(), v[k2].imag());
+  }
+  const size_t nvec = (size_t)nrhs * h->ncoef;
+  int rc = ensure_tmp(h, sizeof(double2) * nvec + sizeof(double2) * pw.size());
+  if (rc) return rc;
+  double2 *c = h->d_tmp;
+  double2 *dpw = h->d_tmp + nvec;
+  HIPCHK(h, hipMemcpyAsync(dpw, pw.data(), pw.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(h, ems::launch_incident_pw(h, dpw, nrhs, c, st));
+  HIPCHK(h, ems::launch_s_apply(h, c, (double2 *)rhs, nrhs, false, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  return EMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// GMRES
+namespace {
+
+struct Givens {
+  std::vector<cd> cs, sn, g;
+  std::vector<std::vector<cd>> H;  // columns
+};
+
+// Restarted GMRES on nrhs systems in lock-step; op(x, y) applies the operator
+// to nrhs vectors.  x is updated in place (initial guess taken as given).
+template <typename Op>
+int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, double tol,
+              int restart, int maxit, bool x_zero, hipStream_t st, int &iters, double &relres,
+              std::vector<double> &bnorm_out) {
+  const int64_t n = h->ncoef;
+  const size_t vec = (size_t)n;
+  restart = std::max(1, std::min(restart, maxit));
+  // basis V[k][r][n]
+  const size_t vbytes = sizeof(double2) * (size_t)(restart + 1) * nrhs * vec;
+  if (h->V_bytes < vbytes) {
+    if (h->d_V) (void)hipFree(h->d_V);
+    h->d_V = nullptr;
+    h->V_bytes = 0;
+    HIPCHK(h, hipMalloc(&h->d_V, vbytes));
+    h->V_bytes = vbytes;
+  }
+  int rc = ensure_tmp(h, sizeof(double2) * 2 * nrhs * vec);
+  if (rc) return rc;
+  rc = ensure_red(h, sizeof(double2) * ((size_t)(restart + 2) * 520 + 64 * (restart + 2)));
+  if (rc) return rc;
+  double2 *W = h->d_tmp;                 // [nrhs][n] operator output
+  double2 *d_h = reinterpret_cast<double2 *>(h->d_red);  // device coefficients
+  double2 *d_h2 = d_h + (restart + 2);
+  double *d_nrm = reinterpret_cast<double *>(d_h2 + (restart + 2));
+  double *scratch = reinterpret_cast<double *>(d_h2 + 2 * (restart + 2) + 8);
+  auto Vk = [&](int k, int r) { return h->d_V + ((size_t)k * nrhs + r) * vec; };
+  const int64_t ldv = (int64_t)nrhs * n;
+
+  std::vector<double> bnorm(nrhs), beta(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    HIPCHK(h, ems::launch_norm2(b + r * vec, n, d_nrm, scratch, st));
+    HIPCHK(h, hipMemcpyAsync(&bnorm[r], d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+  }
+  bnorm_out = bnorm;
+  std::vector<bool> done(nrhs, false);
+  std::vector<double> rel(nrhs, 0.0);
+  iters = 0;
+  bool first = true;
+  while (true) {
+    // residual r0 = b - A x (x = 0 on the first sweep when x_zero)
+    if (first && x_zero) {
+      for (int r = 0; r < nrhs; ++r)
+        HIPCHK(h, hipMemcpyAsync(W + r * vec, b + r * vec, sizeof(double2) * vec,
+                                 hipMemcpyDeviceToDevice, st));
+    } else {
+      rc = op(x, W);
+      if (rc) return rc;
+      for (int r = 0; r < nrhs; ++r) {
+        // W = b - A x
+        HIPCHK(h, ems::launch_scale(W + r * vec, n, -1.0, st));
+        HIPCHK(h, ems::launch_axpy(W + r * vec, b + r * vec, n, 1.0, st));
+      }
+    }
+    first = false;
+    std::vector<Givens> G(nrhs);
+    std::vector<int> kk(nrhs, 0);
+    std::vector<bool> active(nrhs, false);
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      HIPCHK(h, ems::launch_norm2(W + r * vec, n, d_nrm, scratch, st));
+      HIPCHK(h, hipMemcpyAsync(&beta[r], d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(h, hipStreamSynchronize(st));
+      rel[r] = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
+      if (bnorm[r] == 0.0 || rel[r] <= tol) {
+        done[r] = true;
+        continue;
+      }
+      done[r] = false;
+      active[r] = true;
+      any = true;
+      G[r].g.assign(restart + 1, cd(0.0));
+      G[r].g[0] = beta[r];
+      G[r].cs.assign(restart, 0.0);
+      G[r].sn.assign(restart, 0.0);
+      G[r].H.assign(restart, std::vector<cd>(restart + 1, 0.0));
+      HIPCHK(h, ems::launch_copy_scaled(W + r * vec, Vk(0, r), n, 1.0 / beta[r], st));
+    }
+    if (!any) break;
+    int k = 0;
+    for (; k < restart && iters < maxit; ++k) {
+      // W = A V_k (all right-hand sides; inactive ones are ignored)
+      rc = op(Vk(k, 0), W);
+      if (rc) return rc;
+      ++iters;
+      bool all_done = true;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!active[r]) continue;
+        double2 *w = W + r * vec;
+        // CGS2
+        HIPCHK(h, ems::launch_mdot(Vk(0, r), ldv, k + 1, w, n, d_h, scratch, st));
+        HIPCHK(h, ems::launch_mupdate(Vk(0, r), ldv, k + 1, d_h, w, n, st));
+        HIPCHK(h, ems::launch_mdot(Vk(0, r), ldv, k + 1, w, n, d_h2, scratch, st));
+        HIPCHK(h, ems::launch_mupdate(Vk(0, r), ldv, k + 1, d_h2, w, n, st));
+        HIPCHK(h, ems::launch_norm2(w, n, d_nrm, scratch, st));
+        std::vector<double2> h1(k + 1), h2(k + 1);
+        double nrm = 0;
+        HIPCHK(h, hipMemcpyAsync(h1.data(), d_h, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(h2.data(), d_h2, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(&nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        std::vector<cd> col(k + 2);
+        for (int i = 0; i <= k; ++i) col[i] = cd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+        col[k + 1] = nrm;
+        if (nrm > 0) HIPCHK(h, ems::launch_copy_scaled(w, Vk(k + 1, r), n, 1.0 / nrm, st));
+        Givens &g = G[r];
+        for (int i = 0; i < k; ++i) {
+          const cd t = g.cs[i] * col[i] + g.sn[i] * col[i + 1];
+          col[i + 1] = -std::conj(g.sn[i]) * col[i] + std::conj(g.cs[i]) * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::hypot(std::abs(col[k]), std::abs(col[k + 1]));
+        if (den == 0) {
+          g.cs[k] = 1.0;
+          g.sn[k] = 0.0;
+        } else {
+          g.cs[k] = std::conj(col[k]) / den;
+          g.sn[k] = std::conj(col[k + 1]) / den;
+        }
+        col[k] = g.cs[k] * col[k] + g.sn[k] * col[k + 1];
+        col[k + 1] = 0.0;
+        g.g[k + 1] = -std::conj(g.sn[k]) * g.g[k];
+        g.g[k] = g.cs[k] * g.g[k];
+        g.H[k] = col;
+        kk[r] = k + 1;
+        rel[r] = std::abs(g.g[k + 1]) / bnorm[r];
+        if (rel[r] <= tol || nrm == 0) active[r] = false;
+        else all_done = false;
+      }
+      if (all_done) {
+        ++k;
+        break;
+      }
+    }
+    // x += V y for every system that took steps in this sweep
+    for (int r = 0; r < nrhs; ++r) {
+      const int kr = kk[r];
+      if (kr == 0) continue;
+      std::vector<cd> y(kr);
+      Givens &g = G[r];
+      for (int i = kr - 1; i >= 0; --i) {
+        cd s = g.g[i];
+        for (int j = i + 1; j < kr; ++j) s -= g.H[j][i] * y[j];
+        y[i] = s / g.H[i][i];
+      }
+      std::vector<double2> yd(kr);
+      for (int i = 0; i < kr; ++i) yd[i] = make_double2(y[i].real(), y[i].imag());
+      HIPCHK(h, hipMemcpyAsync(d_h, yd.data(), sizeof(double2) * kr, hipMemcpyHostToDevice, st));
+      HIPCHK(h, ems::launch_maccum(Vk(0, r), ldv, kr, d_h, x + r * vec, n, st));
+      HIPCHK(h, hipStreamSynchronize(st));
+    }
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r)
+      if (bnorm[r] > 0 && rel[r] > tol) all = false;
+    if (all || iters >= maxit) break;
+  }
+  // true residual
+  rc = op(x, W);
+  if (rc) return rc;
+  relres = 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    HIPCHK(h, ems::launch_scale(W + r * vec, n, -1.0, st));
+    HIPCHK(h, ems::launch_axpy(W + r * vec, b + r * vec, n, 1.0, st));
+    double nr = 0;
+    HIPCHK(h, ems::launch_norm2(W + r * vec, n, d_nrm, scratch, st));
+    HIPCHK(h, hipMemcpyAsync(&nr, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (bnorm[r] > 0) relres = std::max(relres, nr / bnorm[r]);
+  }
+  return EMS_OK;
+}
+
+}  // namespace
+
+extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
+                         const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream) {
+  if (!h || !b || !x || !o || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad solve arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  if (!(o->tol > 0) || o->maxit <= 0) return fail(h, EMS_ERR_ARG, "need tol > 0 and maxit > 0");
+  hipStream_t st = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t vec = (size_t)h->ncoef;
+  double2 *X = (double2 *)x;
+  const double2 *B = (const double2 *)b;
+  HIPCHK(h, hipMemsetAsync(X, 0, sizeof(double2) * vec * nrhs, st));
+  const int restart = o->restart > 0 ? o->restart : 200;
+  int iters = 0, outer = 1;
+  double relres = 0;
+  std::vector<double> bn;
+  int rc;
+  // The operator buffer passed to GMRES must not alias its internal W; the
+  // apply writes into y = W, reads x = the basis vector (distinct buffers).
+  auto op64 = [&](const double2 *in, double2 *out) {
+    return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL, false, st);
+  };
+  if (o->precision == 0) {
+    rc = gmres_run(h, op64, B, X, nrhs, o->tol, restart, o->maxit, true, st, iters, relres, bn);
+    if (rc) return rc;
+  } else {
+    // Mixed form: inner GMRES with FP32 contractions on the residual
+    // equation, outer FP64 residual and update (iterative refinement).
+    double2 *R = nullptr, *D = nullptr;
+    HIPCHK(h, hipMalloc(&R, sizeof(double2) * vec * nrhs));
+    HIPCHK(h, hipMalloc(&D, sizeof(double2) * vec * nrhs));
+    auto op32 = [&](const double2 *in, double2 *out) {
+      return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL | EMS_MIXED, false, st);
+    };
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-6;
+    outer = 0;
+    rc = EMS_OK;
+    while (true) {
+      // R = b - A64 x
+      rc = op64(X, R);
+      if (rc) break;
+      relres = 0;
+      std::vector<double> nb(nrhs);
+      for (int r = 0; r < nrhs; ++r) {
+        ems::launch_scale(R + r * vec, h->ncoef, -1.0, st);
+        ems::launch_axpy(R + r * vec, B + r * vec, h->ncoef, 1.0, st);
+      }
+      if (bn.empty()) {
+        bn.resize(nrhs);
+        double *dn = nullptr;
+        (void)hipMalloc(&dn, sizeof(double) * 8);
+        double *scr = nullptr;
+        (void)hipMalloc(&scr, sizeof(double2) * 1024);
+        for (int r = 0; r < nrhs; ++r) {
+          ems::launch_norm2(B + r * vec, h->ncoef, dn, scr, st);
+          (void)hipMemcpyAsync(&bn[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
+          (void)hipStreamSynchronize(st);
+        }
+        double *dd = nullptr;
+        (void)dd;
+        for (int r = 0; r < nrhs; ++r) {
+          ems::launch_norm2(R + r * vec, h->ncoef, dn, scr, st);
+          (void)hipMemcpyAsync(&nb[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
+          (void)hipStreamSynchronize(st);
+        }
+        (void)hipFree(dn);
+        (void)hipFree(scr);
+      } else {
+        double *dn = nullptr, *scr = nullptr;
+        (void)hipMalloc(&dn, sizeof(double) * 8);
+        (void)hipMalloc(&scr, sizeof(double2) * 1024);
+        for (int r = 0; r < nrhs; ++r) {
+          ems::launch_norm2(R + r * vec, h->ncoef, dn, scr, st);
+          (void)hipMemcpyAsync(&nb[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
+          (void)hipStreamSynchronize(st);
+        }
+        (void)hipFree(dn);
+        (void)hipFree(scr);
+      }
+      for (int r = 0; r < nrhs; ++r)
+        if (bn[r] > 0) relres = std::max(relres, nb[r] / bn[r]);
+      if (relres <= o->tol || iters >= o->maxit || outer >= 50) break;
+      ++outer;
+      int it = 0;
+      double rr = 0;
+      std::vector<double> tmp;
+      HIPCHK(h, hipMemsetAsync(D, 0, sizeof(double2) * vec * nrhs, st));
+      rc = gmres_run(h, op32, R, D, nrhs, itol, restart, o->maxit - iters, true, st, it, rr, tmp);
+      if (rc) break;
+      iters += it;
+      for (int r = 0; r < nrhs; ++r) ems::launch_axpy(X + r * vec, D + r * vec, h->ncoef, 1.0, st);
+    }
+    (void)hipFree(R);
+    (void)hipFree(D);
+    if (rc) return rc;
+  }
+  HIPCHK(h, hipStreamSynchronize(st));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->iters = iters;
+    info->outer_iters = outer;
+    info->relres = relres;
+    info->converged = relres <= o->tol * 1.0000001 ? 1 : 0;
+    info->seconds = secs;
+  }
+  return relres <= o->tol * 1.0000001 ? EMS_OK : EMS_NOT_CONVERGED;
+}
+
+extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
+                                  const double *pts, void *u, ems_stream_t stream) {
+  (void)gamma;
+  (void)nrhs;
+  (void)npts;
+  (void)pts;
+  (void)u;
+  (void)stream;
+  return fail(h, EMS_ERR_UNIMPLEMENTED, "ems_eval_scattered is not built yet");
+}

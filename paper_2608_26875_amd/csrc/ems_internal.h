@@ -1,0 +1,166 @@
+// Internal declarations of the ems library: handle state, host set-up helpers
+// and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ems.h"
+
+namespace ems {
+
+using cd = std::complex<double>;
+
+// Largest truncation order the kernels are built for: one wavefront (64
+// lanes) holds the 2(2p+1) <= 62 coefficients of one particle.
+constexpr int kMaxP = 15;
+constexpr int kMaxModes = 2 * kMaxP + 1;
+
+struct Media {
+  double lam_h, mu_h, rho_h, lam_b, mu_b, rho_b, omega;
+  double kp, ks, kpb, ksb;
+};
+
+Media make_media(const ems_media &m);
+
+// Sommerfeld node table (host copy).  xi and w are complex in general
+// (the paper's tanh contour); real for the graded real-axis rule.
+// Nodes of a branch-point substitution panel (xi = bp + d, d = +-u^2) keep
+// bp and d so that s for the wavenumber |bp| is formed as sqrt(d (2 bp + d))
+// without cancellation; bp = 0 marks an ordinary node.
+struct NodeTable {
+  std::vector<cd> xi, w;
+  std::vector<double> bp, d;
+  double t_max = 0.0;
+};
+
+struct SommerfeldSpec {
+  int kind = 1;
+  int q = 0;
+  double t_max = 0.0;
+  double delta = 0.5;
+  double panel_scale = 1.0;
+  int panel_order = 64;
+  std::vector<double> user;  // kind 2: [q][4]
+};
+
+// s(xi; k): decaying branch, Re s >= 0.  Real xi split by cases; complex xi
+// with Im(k^2 - xi^2) >= 0 uses the principal root of k^2 - xi^2.
+cd branch_s(cd xi, double k);
+
+// Build the node table for the given cloud.
+int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<double> &xy,
+                const std::vector<int> &p, NodeTable &out, std::string &err);
+
+// s(xi; k) for every wavenumber of the media at node (xi, bp, d):
+// out = {s_p, s_s, s_pb, s_sb}.
+void node_s(cd xi, double bp, double d, const Media &md, cd out[4]);
+
+// 2x2 reflection R(xi) of upgoing P/S potentials at the welded interface,
+// with the four branch values s given (node_s) or formed from xi.
+int reflection(cd xi, const Media &md, cd R[4]);
+int reflection_s(cd xi, const cd s[4], const Media &md, cd R[4]);
+
+// Closed-form disk scattering matrix, row-major (4p+2)^2.
+int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S);
+
+struct Workspace;
+
+}  // namespace ems
+
+// Device buffers and sizes owned by a handle.
+struct ems_handle {
+  std::string err;
+  int device = 0;
+  bool have_media = false, have_particles = false, have_s = false, built = false;
+  ems::Media md{};
+  ems::SommerfeldSpec somm;
+
+  int n = 0, pmax = 0;
+  int64_t ncoef = 0;
+  std::vector<double> xy, R;
+  std::vector<int> p;
+  std::vector<int64_t> off;      // [n+1] complex offsets in the ABI layout
+  std::vector<ems::cd> S_host;   // ABI order, row-major per particle
+  std::vector<int64_t> S_off;    // [n+1]
+
+  // node table
+  ems::NodeTable nodes;
+  int q = 0;
+
+  // device state
+  double *d_xy = nullptr;        // [n][2]
+  int *d_p = nullptr;            // [n]
+  int64_t *d_off = nullptr;      // [n+1]
+  double2 *d_S = nullptr;        // packed S, transposed per particle (column-major)
+  float2 *d_S32 = nullptr;       // complex64 copy for the mixed form
+  int64_t *d_Soff = nullptr;     // [n+1]
+  // node table on device (structure of arrays)
+  double2 *d_xi = nullptr, *d_w = nullptr, *d_sp = nullptr, *d_ss = nullptr;
+  double2 *d_R = nullptr;        // [q][4]
+  double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 pmax + 1]: (-i zeta)^n, n = -pmax..pmax
+  // workspaces (sized for ws_nrhs right-hand sides)
+  int ws_nrhs = 0;
+  int agg_chunks = 0, dis_chunks = 0;
+  double2 *d_agg = nullptr;      // [nrhs][2 waves][agg_chunks][q]
+  double2 *d_refl = nullptr;     // [nrhs][2][q] reflected amplitudes (weights folded in)
+  double2 *d_dis = nullptr;      // [nrhs][dis_chunks][ncoef] partial local coefficients
+  double2 *d_free = nullptr;     // [nrhs][ncoef]
+  int64_t n_pairs = 0;
+
+  // GMRES workspace
+  double2 *d_V = nullptr;        // Krylov basis
+  size_t V_bytes = 0;
+  double2 *d_tmp = nullptr;      // scratch vectors
+  size_t tmp_bytes = 0;
+  double *d_red = nullptr;       // reduction partials
+  size_t red_bytes = 0;
+};
+
+namespace ems {
+
+// ---- kernel launchers (defined in the .hip files) --------------------------
+hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
+                              bool adjoint, bool mixed, hipStream_t st);
+hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
+                                 bool mixed, hipStream_t st);
+hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
+hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
+                                    hipStream_t st);
+// y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags.
+hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs,
+                          int flags, bool adjoint, hipStream_t st);
+// plane-wave local coefficients (before S): c [nrhs][ncoef]
+hipError_t launch_incident(const ems_handle *h, const int *wave, const double *angle,
+                           const double2 *Rinc, int nrhs, double2 *c, hipStream_t st);
+hipError_t launch_s_multiply(const ems_handle *h, const double2 *c, double2 *y, int nrhs,
+                             hipStream_t st);
+
+// ---- small BLAS-like kernels for GMRES -------------------------------------
+// partial[i][b] = sum over chunk b of conj(V_i) . w   (i < k)
+hipError_t launch_mdot(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                       double2 *out_dev, double *scratch, hipStream_t st);
+// w -= sum_i V_i c_i
+hipError_t launch_mupdate(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                          int64_t n, hipStream_t st);
+hipError_t launch_norm2(const double2 *w, int64_t n, double *out_dev, double *scratch,
+                        hipStream_t st);
+hipError_t launch_scale(double2 *w, int64_t n, double s, hipStream_t st);
+hipError_t launch_copy_scaled(const double2 *src, double2 *dst, int64_t n, double s,
+                              hipStream_t st);
+// y += sum_i V_i c_i
+hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
+                         int64_t n, hipStream_t st);
+hipError_t launch_axpy(double2 *y, const double2 *x, int64_t n, double a, hipStream_t st);
+
+// field evaluation
+hipError_t launch_field_direct(const ems_handle *h, const double2 *gamma, int nrhs, int npts,
+                               const double *pts, double2 *u, hipStream_t st);
+hipError_t launch_field_refl(const ems_handle *h, int nrhs, int npts, const double *pts,
+                             double2 *u, hipStream_t st);
+
+}  // namespace ems

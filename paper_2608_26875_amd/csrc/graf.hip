@@ -1,0 +1,169 @@
+// Free-space particle-particle translations (Section 3.2, Graf's addition
+// theorem), evaluated directly for every pair.
+//
+// Incoming coefficients of the target m collect from every source l != m
+//   a^m_i += sum_j t_{i-j} alpha^l_j,  t_nu = H_nu(k |x_m - x_l|) e^{-i nu (th_ml - pi)},
+// with th_ml the polar angle of x_m - x_l, k = kp for alpha and ks for beta.
+// The adjoint (conjugate transpose) maps target-side vectors back to the
+// sources with conj(t_{-nu}).
+//
+// One 64-lane workgroup per output particle: lanes 0..31 own the P modes,
+// lanes 32..63 the S modes of that particle.  Partners are taken 16 at a
+// time; 32 lanes build the 16 x 2 Toeplitz symbols in LDS (Hankel functions
+// by forward recurrence from H_0, H_1, stable because |Y_nu| dominates), then
+// every lane runs its row of the Toeplitz product against the partner
+// coefficients staged in LDS.
+#include "dev.h"
+#include "ems_internal.h"
+
+namespace ems {
+
+template <bool MIXED> struct CT;
+template <> struct CT<false> {
+  using T = double2;
+  __device__ static T from(double2 v) { return v; }
+};
+template <> struct CT<true> {
+  using T = float2;
+  __device__ static T from(double2 v) { return make_float2((float)v.x, (float)v.y); }
+};
+
+__device__ __forceinline__ void cfma_any(double2 &a, double2 x, double2 y) { cfma(a, x, y); }
+__device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(a, x, y); }
+__device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
+__device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
+
+template <int PM, bool MIXED>
+__global__ __launch_bounds__(64) void graf_direct_kernel(
+    int n, const double *__restrict__ xy, const int *__restrict__ p,
+    const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
+    double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint) {
+  using T = typename CT<MIXED>::T;
+  constexpr int NT = 4 * PM + 1;
+  constexpr int NM = 2 * PM + 1;
+  constexpr int SB = 16;
+  __shared__ T t_lds[2][SB][NT];
+  __shared__ T c_lds[SB][2][NM];
+
+  const int b = blockIdx.x;
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x;
+  const double bx = xy[2 * b], by = xy[2 * b + 1];
+  const int pb = p[b];
+  const int w = lane >> 5;
+  const int i = (lane & 31) - PM;
+  const double2 *xr = x + (int64_t)r * ldx;
+  T acc;
+  acc.x = 0;
+  acc.y = 0;
+
+  for (int base = 0; base < n; base += SB) {
+    if (lane < 2 * SB) {
+      const int s = lane >> 1, ww = lane & 1, l = base + s;
+      T *t = t_lds[ww][s];
+      if (l < n && l != b) {
+        // th_ml: angle of x_m - x_l (m target, l source of the forward map)
+        double dx = bx - xy[2 * l], dy = by - xy[2 * l + 1];
+        if (adjoint) {
+          dx = -dx;
+          dy = -dy;
+        }
+        const double d = sqrt(dx * dx + dy * dy);
+        const double th = atan2(dy, dx);
+        const double z = (ww ? ks : kp) * d;
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        const double2 e1 = make_double2(-cs, sn);  // e^{-i (th - pi)}
+        double2 hm = make_double2(j0(z), y0(z));
+        double2 h = make_double2(j1(z), y1(z));
+        t[2 * PM] = CT<MIXED>::from(hm);
+        double2 ph = e1;
+        {
+          const double2 v = cmul(h, ph);
+          t[2 * PM + 1] = CT<MIXED>::from(v);
+          // t_{-nu} = (-1)^nu H_nu conj(e^{-i nu (th - pi)})
+          t[2 * PM - 1] = CT<MIXED>::from(cscale(cmul(h, cconj(ph)), -1.0));
+        }
+        const double iz = 2.0 / z;
+#pragma unroll
+        for (int nu = 2; nu <= 2 * PM; ++nu) {
+          const double2 hn = csub(cscale(h, (nu - 1) * iz), hm);
+          hm = h;
+          h = hn;
+          ph = cmul(ph, e1);
+          t[2 * PM + nu] = CT<MIXED>::from(cmul(h, ph));
+          const double sg = (nu & 1) ? -1.0 : 1.0;
+          t[2 * PM - nu] = CT<MIXED>::from(cscale(cmul(h, cconj(ph)), sg));
+        }
+      } else {
+        for (int k = 0; k < NT; ++k) {
+          t[k].x = 0;
+          t[k].y = 0;
+        }
+      }
+    }
+    for (int e = lane; e < SB * 2 * NM; e += 64) {
+      const int s = e / (2 * NM), rem = e - s * (2 * NM);
+      const int ww = rem / NM, jj = rem - ww * NM - PM;
+      const int l = base + s;
+      double2 v = make_double2(0.0, 0.0);
+      if (l < n && l != b) {
+        const int pl = p[l];
+        if (jj >= -pl && jj <= pl) v = xr[off[l] + ww * (2 * pl + 1) + jj + pl];
+      }
+      c_lds[s][ww][jj + PM] = CT<MIXED>::from(v);
+    }
+    __syncthreads();
+    if (i <= PM) {
+      for (int s = 0; s < SB; ++s) {
+#pragma unroll
+        for (int jj = 0; jj < NM; ++jj) {
+          const int nu = i - (jj - PM);
+          T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
+          cfma_any(acc, tv, c_lds[s][w][jj]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (i >= -pb && i <= pb)
+    out[(int64_t)r * ldo + off[b] + w * (2 * pb + 1) + i + pb] =
+        make_double2((double)acc.x, (double)acc.y);
+}
+
+#define EMS_GRAF_CASE(PMV)                                                                   \
+  case PMV:                                                                                  \
+    if (mixed)                                                                               \
+      hipLaunchKernelGGL((graf_direct_kernel<PMV, true>), grid, dim3(64), 0, st, h->n,       \
+                         h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
+                         h->md.ks, adjoint ? 1 : 0);                                          \
+    else                                                                                     \
+      hipLaunchKernelGGL((graf_direct_kernel<PMV, false>), grid, dim3(64), 0, st, h->n,      \
+                         h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
+                         h->md.ks, adjoint ? 1 : 0);                                          \
+    break;
+
+int pm_bucket(int pmax) {
+  if (pmax <= 4) return 4;
+  if (pmax <= 8) return 8;
+  if (pmax <= 10) return 10;
+  if (pmax <= 12) return 12;
+  return 15;
+}
+
+hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
+                              bool adjoint, bool mixed, hipStream_t st) {
+  dim3 grid(h->n, nrhs);
+  switch (pm_bucket(h->pmax)) {
+    EMS_GRAF_CASE(4)
+    EMS_GRAF_CASE(8)
+    EMS_GRAF_CASE(10)
+    EMS_GRAF_CASE(12)
+    EMS_GRAF_CASE(15)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ems

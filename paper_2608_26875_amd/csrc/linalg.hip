@@ -1,0 +1,290 @@
+// S-matrix apply and the final combination of the operator (Section 3.2 and
+// 4.2: y_m = x_m - S_m (T_free x + T_refl x)_m), the plane-wave right-hand
+// side (Section 6.3), and the vector kernels of the GMRES driver.
+//
+// The S store is packed per particle column-major (S^T row-major), so the
+// 4p+2 lanes of one wavefront read one column of S_m in a single coalesced
+// 16-byte-per-lane transaction while the input coefficient is broadcast from
+// LDS.
+#include "dev.h"
+#include "ems_internal.h"
+
+namespace ems {
+
+// One wavefront per particle; lane = row of the particle block.
+__global__ __launch_bounds__(64) void combine_kernel(
+    const int *__restrict__ p, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ Soff, const double2 *__restrict__ St,
+    const double2 *__restrict__ x, double2 *__restrict__ y, const double2 *__restrict__ fre,
+    const double2 *__restrict__ dis, int chunks, int64_t ncoef, int flags, int sign) {
+  __shared__ double2 v[64];
+  const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int pm = p[m];
+  const int N = 2 * pm + 1, K = 2 * N;
+  const int64_t base = (int64_t)r * ncoef + off[m];
+  if (lane < K) {
+    double2 val = make_double2(0.0, 0.0);
+    if (flags & EMS_PART_FREE) val = fre[base + lane];
+    if (flags & EMS_PART_REFL) {
+      double2 s = make_double2(0.0, 0.0);
+      const double2 *dr = dis + (int64_t)r * chunks * ncoef + off[m] + lane;
+      for (int c = 0; c < chunks; ++c) s = cadd(s, dr[(int64_t)c * ncoef]);
+      const int nn = (lane < N ? lane : lane - N) - pm;
+      if (sign && (nn & 1)) s = cscale(s, -1.0);
+      val = cadd(val, s);
+    }
+    v[lane] = val;
+  }
+  __syncthreads();
+  if (lane < K) {
+    double2 u;
+    if (flags & EMS_PART_S) {
+      u = make_double2(0.0, 0.0);
+      const double2 *Sm = St + Soff[m];
+      for (int c = 0; c < K; ++c) cfma(u, Sm[(int64_t)c * K + lane], v[c]);
+    } else {
+      u = v[lane];
+    }
+    if (flags & EMS_PART_IDENTITY) u = csub(x[base + lane], u);
+    y[base + lane] = u;
+  }
+}
+
+// y_m = S_m c_m (adjoint = 0) or S_m^H c_m (adjoint = 1)
+__global__ __launch_bounds__(64) void s_apply_kernel(
+    const int *__restrict__ p, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ Soff, const double2 *__restrict__ St,
+    const double2 *__restrict__ c, double2 *__restrict__ y, int64_t ncoef, int adjoint) {
+  __shared__ double2 v[64];
+  const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int pm = p[m];
+  const int K = 2 * (2 * pm + 1);
+  const int64_t base = (int64_t)r * ncoef + off[m];
+  if (lane < K) v[lane] = c[base + lane];
+  __syncthreads();
+  if (lane < K) {
+    double2 u = make_double2(0.0, 0.0);
+    const double2 *Sm = St + Soff[m];
+    if (!adjoint) {
+      for (int k = 0; k < K; ++k) cfma(u, Sm[(int64_t)k * K + lane], v[k]);
+    } else {
+      for (int k = 0; k < K; ++k) cfma(u, cconj(Sm[(int64_t)lane * K + k]), v[k]);
+    }
+    y[base + lane] = u;
+  }
+}
+
+hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
+                          bool adjoint, hipStream_t st) {
+  hipLaunchKernelGGL(combine_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->d_p, h->d_off,
+                     h->d_Soff, h->d_S, x, y, h->d_free, h->d_dis, h->dis_chunks, h->ncoef,
+                     flags, adjoint ? 0 : 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_s_apply(const ems_handle *h, const double2 *c, double2 *y, int nrhs,
+                          bool adjoint, hipStream_t st) {
+  hipLaunchKernelGGL(s_apply_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->d_p, h->d_off,
+                     h->d_Soff, h->d_S, c, y, h->ncoef, adjoint ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_s_multiply(const ems_handle *h, const double2 *c, double2 *y, int nrhs,
+                             hipStream_t st) {
+  return launch_s_apply(h, c, y, nrhs, false, st);
+}
+
+// ---------------------------------------------------------------------------
+// Plane-wave local coefficients (Section 6.3 background field; Jacobi-Anger).
+// Per right-hand side r the host supplies pw[r] = {xi0, s_p, s_s, Ain_p,
+// Ain_s, Ar_p, Ar_s} (complex), and
+//   a_n = Ar_p e^{i xi0 x + s_p y} (i (xi0 - s_p)/kp)^n + Ain_p e^{i xi0 x - s_p y} (i (xi0 + s_p)/kp)^n
+//   b_n = the same with (s_s, ks, Ar_s, Ain_s).
+__device__ double2 cpow_int(double2 z, int n) {
+  double2 r = make_double2(1.0, 0.0);
+  const int an = n < 0 ? -n : n;
+  for (int k = 0; k < an; ++k) r = cmul(r, z);
+  if (n < 0) {
+    const double d = r.x * r.x + r.y * r.y;
+    r = make_double2(r.x / d, -r.y / d);
+  }
+  return r;
+}
+
+__global__ void incident_kernel(int n, const double *__restrict__ xy, const int *__restrict__ p,
+                                 const int64_t *__restrict__ off, const double2 *__restrict__ pw,
+                                 double kp, double ks, double2 *__restrict__ c, int64_t ncoef) {
+  const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int pm = p[m];
+  const int N = 2 * pm + 1;
+  if (lane >= 2 * N) return;
+  const int wave = lane < N ? 0 : 1;
+  const int nn = (wave ? lane - N : lane) - pm;
+  const double2 *P = pw + 7 * r;
+  const double2 xi0 = P[0];
+  const double2 s = wave ? P[2] : P[1];
+  const double2 Ain = wave ? P[4] : P[3];
+  const double2 Ar = wave ? P[6] : P[5];
+  const double k = wave ? ks : kp;
+  const double x = xy[2 * m], y = xy[2 * m + 1];
+  const double2 I = make_double2(0.0, 1.0);
+  const double2 ixi = cmul(I, xi0);
+  // reflected: e^{i xi0 x + s y} (i (xi0 - s)/k)^n
+  const double2 er = cexp(cadd(cscale(ixi, x), cscale(s, y)));
+  const double2 br = cscale(cmul(I, csub(xi0, s)), 1.0 / k);
+  const double2 ei = cexp(csub(cscale(ixi, x), cscale(s, y)));
+  const double2 bi = cscale(cmul(I, cadd(xi0, s)), 1.0 / k);
+  double2 v = cmul(cmul(Ar, er), cpow_int(br, nn));
+  v = cadd(v, cmul(cmul(Ain, ei), cpow_int(bi, nn)));
+  c[(int64_t)r * ncoef + off[m] + lane] = v;
+}
+
+hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, double2 *c,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(incident_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->n, h->d_xy, h->d_p,
+                     h->d_off, pw, h->md.kp, h->md.ks, c, h->ncoef);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// GMRES vector kernels.  Reductions write one partial per block and are
+// finished by a single-block kernel in a fixed order (reproducible).
+constexpr int kRedBlocks = 512;
+
+__device__ __forceinline__ double2 warp_reduce(double2 v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_down(v.x, o, 64);
+    v.y += __shfl_down(v.y, o, 64);
+  }
+  return v;
+}
+
+__device__ double2 block_reduce(double2 v) {
+  __shared__ double2 sh[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = warp_reduce(v);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = cadd(r, sh[k]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// partial[i][b] = sum_{rows in block b's stripe} conj(V_i[row]) w[row]
+__global__ __launch_bounds__(256) void mdot_kernel(const double2 *__restrict__ V, int64_t ldv,
+                                                  int k, const double2 *__restrict__ w,
+                                                  int64_t n, double2 *__restrict__ part) {
+  const int i = blockIdx.y;
+  const double2 *Vi = V + (int64_t)i * ldv;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    cfma(acc, cconj(Vi[row]), w[row]);
+  }
+  acc = block_reduce(acc);
+  if (threadIdx.x == 0) part[(int64_t)i * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void finish_kernel(const double2 *__restrict__ part, int nb, int k,
+                              double2 *__restrict__ out) {
+  const int i = blockIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc = cadd(acc, part[(int64_t)i * nb + b]);
+  acc = block_reduce(acc);
+  if (threadIdx.x == 0) out[i] = acc;
+}
+
+hipError_t launch_mdot(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                       double2 *out_dev, double *scratch, hipStream_t st) {
+  double2 *part = reinterpret_cast<double2 *>(scratch);
+  hipLaunchKernelGGL(mdot_kernel, dim3(kRedBlocks, k), dim3(256), 0, st, V, ldv, k, w, n, part);
+  hipLaunchKernelGGL(finish_kernel, dim3(k), dim3(256), 0, st, part, kRedBlocks, k, out_dev);
+  return hipGetLastError();
+}
+
+// w -= sum_i V_i c_i  (c on device)
+__global__ __launch_bounds__(256) void mupdate_kernel(const double2 *__restrict__ V, int64_t ldv,
+                                                     int k, const double2 *__restrict__ c,
+                                                     double2 *__restrict__ w, int64_t n,
+                                                     double sgn) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = 0; i < k; ++i) cfma(acc, V[(int64_t)i * ldv + row], c[i]);
+    w[row] = make_double2(w[row].x + sgn * acc.x, w[row].y + sgn * acc.y);
+  }
+}
+
+hipError_t launch_mupdate(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                          int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(mupdate_kernel, dim3(2048), dim3(256), 0, st, V, ldv, k, c, w, n, -1.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
+                         int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(mupdate_kernel, dim3(2048), dim3(256), 0, st, V, ldv, k, c, y, n, 1.0);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void norm2_kernel(const double2 *__restrict__ w, int64_t n,
+                                                   double2 *__restrict__ part) {
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = w[row];
+    acc.x = fma(v.x, v.x, fma(v.y, v.y, acc.x));
+  }
+  acc = block_reduce(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void finish_norm_kernel(const double2 *__restrict__ part, int nb, double *out) {
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc = cadd(acc, part[b]);
+  acc = block_reduce(acc);
+  if (threadIdx.x == 0) out[0] = sqrt(acc.x);
+}
+
+hipError_t launch_norm2(const double2 *w, int64_t n, double *out_dev, double *scratch,
+                        hipStream_t st) {
+  double2 *part = reinterpret_cast<double2 *>(scratch);
+  hipLaunchKernelGGL(norm2_kernel, dim3(kRedBlocks), dim3(256), 0, st, w, n, part);
+  hipLaunchKernelGGL(finish_norm_kernel, dim3(1), dim3(256), 0, st, part, kRedBlocks, out_dev);
+  return hipGetLastError();
+}
+
+__global__ void scale_kernel(double2 *w, int64_t n, double s) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x)
+    w[row] = cscale(w[row], s);
+}
+__global__ void copy_scaled_kernel(const double2 *src, double2 *dst, int64_t n, double s) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x)
+    dst[row] = cscale(src[row], s);
+}
+__global__ void axpy_kernel(double2 *y, const double2 *x, int64_t n, double a) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x)
+    y[row] = make_double2(y[row].x + a * x[row].x, y[row].y + a * x[row].y);
+}
+
+hipError_t launch_scale(double2 *w, int64_t n, double s, hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(2048), dim3(256), 0, st, w, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_copy_scaled(const double2 *src, double2 *dst, int64_t n, double s,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(copy_scaled_kernel, dim3(2048), dim3(256), 0, st, src, dst, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double2 *y, const double2 *x, int64_t n, double a, hipStream_t st) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(2048), dim3(256), 0, st, y, x, n, a);
+  return hipGetLastError();
+}
+
+}  // namespace ems

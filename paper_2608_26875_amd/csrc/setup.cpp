@@ -1,0 +1,409 @@
+// Host set-up of the operator: wavenumbers, Sommerfeld node tables, the
+// per-node welded-interface reflection, closed-form disk scattering matrices.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+#include "ems_internal.h"
+
+namespace ems {
+
+static const double kPi = 3.14159265358979323846;
+
+Media make_media(const ems_media &m) {
+  Media d{};
+  d.lam_h = m.host.lambda;
+  d.mu_h = m.host.mu;
+  d.rho_h = m.host.rho;
+  d.lam_b = m.substrate.lambda;
+  d.mu_b = m.substrate.mu;
+  d.rho_b = m.substrate.rho;
+  d.omega = m.omega;
+  // Helmholtz split (Section 2) with the density kept.
+  d.kp = m.omega * std::sqrt(d.rho_h / (d.lam_h + 2.0 * d.mu_h));
+  d.ks = m.omega * std::sqrt(d.rho_h / d.mu_h);
+  d.kpb = m.omega * std::sqrt(d.rho_b / (d.lam_b + 2.0 * d.mu_b));
+  d.ksb = m.omega * std::sqrt(d.rho_b / d.mu_b);
+  return d;
+}
+
+cd branch_s(cd xi, double k) {
+  if (xi.imag() == 0.0) {
+    const double x = xi.real();
+    const double v = (x - k) * (x + k);
+    if (v > 0) return cd(std::sqrt(v), 0.0);
+    return cd(0.0, -std::sqrt(-v));
+  }
+  return cd(0.0, -1.0) * std::sqrt(cd(k * k, 0.0) - xi * xi);
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j + 1.0) * z * p2 - j * p3) / (j + 1.0);
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double z1 = z;
+      z = z1 - p1 / pp;
+      if (std::fabs(z - z1) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// Decay bound of the Sommerfeld integrand tail: exp(-t D) (2t/k + 1)^(2p).
+static double auto_tmax(double dmin, int pmax, double kmin, double kmax) {
+  double peak = -1e300;
+  for (double t = 0.0; t < 4000.0; t += 0.01)
+    peak = std::max(peak, -t * dmin + 2.0 * pmax * std::log(2.0 * t / kmin + 1.0));
+  for (double t = kmax + 2.0; t < 4000.0; t += 0.01) {
+    const double v = -t * dmin + 2.0 * pmax * std::log(2.0 * t / kmin + 1.0);
+    if (v < peak + std::log(1e-18)) return t;
+  }
+  return 4000.0;
+}
+
+namespace {
+struct PanelRule {
+  std::vector<double> gx, gw;   // bulk rule
+  int n = 0;
+};
+
+void push(NodeTable &out, cd xi, cd w, double bp, double d) {
+  out.xi.push_back(xi);
+  out.w.push_back(w);
+  out.bp.push_back(bp);
+  out.d.push_back(d);
+}
+
+void add_panel(const PanelRule &r, double a, double b, NodeTable &out) {
+  const double c = 0.5 * (a + b), hl = 0.5 * (b - a);
+  for (int i = 0; i < r.n; ++i) push(out, cd(c + hl * r.gx[i], 0.0), cd(hl * r.gw[i], 0.0), 0.0, 0.0);
+}
+
+// Panel next to a branch point at `bp`, extending by `len` towards `dir`
+// (+1 right, -1 left): xi = bp + dir u^2, u in [0, sqrt(len)].
+void add_sub_panel(const PanelRule &r, double bp, double len, int dir, NodeTable &out) {
+  const double U = std::sqrt(len), c = 0.5 * U, hl = 0.5 * U;
+  for (int i = 0; i < r.n; ++i) {
+    const double u = c + hl * r.gx[i];
+    push(out, cd(bp + dir * u * u, 0.0), cd(hl * r.gw[i] * 2.0 * u, 0.0), bp, dir * u * u);
+  }
+}
+
+// Half interval from a singular end `bp` towards `mid` (dir = sign(mid - bp)):
+// substitution panel, geometrically graded panels, then uniform panels.
+void graded_half(const PanelRule &r, double bp, double mid, double Lb, double Losc,
+                 NodeTable &out) {
+  const int dir = mid > bp ? 1 : -1;
+  const double span = std::fabs(mid - bp);
+  double Lsub = std::min(Lb, 0.5 * span);
+  add_sub_panel(r, bp, Lsub, dir, out);
+  double pos = Lsub, len = Lsub;
+  while (pos < span) {
+    double nl = std::min(2.0 * len, Losc);
+    if (nl >= Losc) break;
+    if (pos + nl > span) break;
+    add_panel(r, std::min(bp + dir * pos, bp + dir * (pos + nl)),
+              std::max(bp + dir * pos, bp + dir * (pos + nl)), out);
+    pos += nl;
+    len = nl;
+  }
+  const double rest = span - pos;
+  if (rest > 1e-15) {
+    const int np = std::max(1, (int)std::ceil(rest / Losc - 1e-9));
+    const double h = rest / np;
+    for (int i = 0; i < np; ++i) {
+      const double a = bp + dir * (pos + i * h), b = bp + dir * (pos + (i + 1) * h);
+      add_panel(r, std::min(a, b), std::max(a, b), out);
+    }
+  }
+}
+}  // namespace
+
+int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<double> &xy,
+                const std::vector<int> &p, NodeTable &out, std::string &err) {
+  out.xi.clear();
+  out.w.clear();
+  out.bp.clear();
+  out.d.clear();
+  const int n = (int)p.size();
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  int pmax = 0;
+  for (int i = 0; i < n; ++i) {
+    xmin = std::min(xmin, xy[2 * i]);
+    xmax = std::max(xmax, xy[2 * i]);
+    ymin = std::min(ymin, -xy[2 * i + 1]);
+    ymax = std::max(ymax, -xy[2 * i + 1]);
+    pmax = std::max(pmax, p[i]);
+  }
+  const double X = std::max(xmax - xmin, 1e-3);
+  const double Dmin = 2.0 * ymin, Dmax = 2.0 * ymax;
+  const double kmin = std::min(md.kp, md.ks);
+  const double kmax = std::max(std::max(md.kp, md.ks), std::max(md.kpb, md.ksb));
+  double T = spec.t_max > 0 ? spec.t_max : auto_tmax(Dmin, pmax, kmin, kmax);
+  out.t_max = T;
+  if (spec.kind == 2) {
+    if ((int)spec.user.size() != 4 * spec.q || spec.q <= 0) {
+      err = "sommerfeld kind 2 needs q > 0 user nodes";
+      return EMS_ERR_ARG;
+    }
+    for (int j = 0; j < spec.q; ++j)
+      push(out, cd(spec.user[4 * j], spec.user[4 * j + 1]),
+           cd(spec.user[4 * j + 2], spec.user[4 * j + 3]), 0.0, 0.0);
+    return EMS_OK;
+  }
+  if (spec.kind == 0) {
+    // Section 4.1: xi(t) = t - i delta tanh(t), trapezoidal rule in t.
+    const int q = spec.q > 1 ? spec.q : 512;
+    const double h = 2.0 * T / (q - 1);
+    for (int j = 0; j < q; ++j) {
+      const double t = -T + j * h;
+      const double th = std::tanh(t);
+      const double sech2 = 1.0 - th * th;
+      const double wt = (j == 0 || j == q - 1) ? 0.5 * h : h;
+      push(out, cd(t, -spec.delta * th), wt * cd(1.0, -spec.delta * sech2), 0.0, 0.0);
+    }
+    return EMS_OK;
+  }
+  if (spec.kind != 1) {
+    err = "unknown sommerfeld kind";
+    return EMS_ERR_ARG;
+  }
+  // Real axis, composite Gauss-Legendre with graded panels at branch points.
+  PanelRule r;
+  r.n = spec.panel_order;
+  gauss_legendre(r.n, r.gx, r.gw);
+  // A panel of n Gauss points is exact to degree 2n - 1.  The integrand is a
+  // plane wave of frequency sqrt(X^2 + D^2) (horizontal spread X, depth sum
+  // D) times powers zeta^(n + n') of degree up to 2 p_max.  Measured against
+  // the multipole-to-Sommerfeld lemma at orders +-2p, 64-point panels stay at
+  // the rounding floor while (half-length) x (frequency) <= ~75 for p <= 15;
+  // the default keeps 0.9 n.
+  const double wmax = 0.9 * r.n;
+  const double freq = std::sqrt(X * X + Dmax * Dmax);
+  double Losc = std::min(2.0, 2.0 * wmax / freq) * spec.panel_scale;
+  std::vector<double> bps = {md.kp, md.ks, md.kpb, md.ksb};
+  std::sort(bps.begin(), bps.end());
+  bps.erase(std::unique(bps.begin(), bps.end(),
+                        [](double a, double b) { return std::fabs(a - b) < 1e-12; }),
+            bps.end());
+  std::vector<double> pts;
+  for (auto it = bps.rbegin(); it != bps.rend(); ++it) pts.push_back(-*it);
+  for (double b : bps) pts.push_back(b);
+  if (T <= pts.back() + 0.5) T = pts.back() + 0.5;
+  out.t_max = T;
+  // Substitution panel [bp, bp + L] in u = sqrt(|xi - bp|): the chirp
+  // e^{i X u^2} gives u-frequency 2 X u and the depth factor e^{-sqrt(2k) u D}
+  // a rate sqrt(2k) D; over half the u-interval sqrt(L)/2 the combined
+  // (X L)^2 + (k L / 2) D^2 must stay below wsub^2.
+  const double wsub = 18.0;
+  auto Lb_of = [&](double b) {
+    const double kb = std::max(std::fabs(b), 1e-3);
+    const double bq = 0.5 * kb * Dmax * Dmax;
+    const double L = (-bq + std::sqrt(bq * bq + 4.0 * X * X * wsub * wsub)) / (2.0 * X * X);
+    return std::min(0.5 * Losc, L);
+  };
+  // left tail [-T, pts[0]]: singular at pts[0] only
+  {
+    const double bp = pts.front();
+    graded_half(r, bp, -T, Lb_of(bp), Losc, out);
+  }
+  for (size_t i = 0; i + 1 < pts.size(); ++i) {
+    const double a = pts[i], b = pts[i + 1], mid = 0.5 * (a + b);
+    graded_half(r, a, mid, Lb_of(a), Losc, out);
+    graded_half(r, b, mid, Lb_of(b), Losc, out);
+  }
+  {
+    const double bp = pts.back();
+    graded_half(r, bp, T, Lb_of(bp), Losc, out);
+  }
+  // sort by xi (helps locality; the sum is order independent up to rounding)
+  std::vector<size_t> idx(out.xi.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(),
+            [&](size_t a, size_t b) { return out.xi[a].real() < out.xi[b].real(); });
+  NodeTable s;
+  s.t_max = out.t_max;
+  for (size_t i : idx) push(s, out.xi[i], out.w[i], out.bp[i], out.d[i]);
+  out = s;
+  return EMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Welded interface, one Fourier mode (Section 2.2, written for potentials).
+// A potential e^{i xi x + q y} in (lambda, mu) gives (u1, u2, t1, t2) with
+// t = T_y u: P: (i xi, q, 2 mu i xi q, (lambda + 2 mu) q^2 - lambda xi^2),
+//            S: (-q, i xi, -mu (q^2 + xi^2), 2 mu i xi q).
+static void pcol(cd xi, cd q, double lam, double mu, cd c[4]) {
+  const cd I(0.0, 1.0);
+  c[0] = I * xi;
+  c[1] = q;
+  c[2] = 2.0 * mu * I * xi * q;
+  c[3] = (lam + 2.0 * mu) * q * q - lam * xi * xi;
+}
+static void scol(cd xi, cd q, double lam, double mu, cd c[4]) {
+  const cd I(0.0, 1.0);
+  c[0] = -q;
+  c[1] = I * xi;
+  c[2] = -mu * (q * q + xi * xi);
+  c[3] = 2.0 * mu * I * xi * q;
+}
+
+void node_s(cd xi, double bp, double d, const Media &md, cd out[4]) {
+  const double ks_[4] = {md.kp, md.ks, md.kpb, md.ksb};
+  for (int i = 0; i < 4; ++i) {
+    const double k = ks_[i];
+    if (bp != 0.0 && std::fabs(std::fabs(bp) - k) <= 1e-14 * k) {
+      const double v = d * (2.0 * bp + d);
+      out[i] = v > 0 ? cd(std::sqrt(v), 0.0) : cd(0.0, -std::sqrt(-v));
+    } else {
+      out[i] = branch_s(xi, k);
+    }
+  }
+}
+
+int reflection(cd xi, const Media &md, cd R[4]) {
+  cd s[4];
+  node_s(xi, 0.0, 0.0, md, s);
+  return reflection_s(xi, s, md, R);
+}
+
+int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
+  const cd sp = s4[0], ss = s4[1], spb = s4[2], ssb = s4[3];
+  cd M[4][6];
+  cd c[4];
+  pcol(xi, sp, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) M[r][0] = c[r];
+  scol(xi, ss, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) M[r][1] = c[r];
+  pcol(xi, -spb, md.lam_b, md.mu_b, c);
+  for (int r = 0; r < 4; ++r) M[r][2] = -c[r];
+  scol(xi, -ssb, md.lam_b, md.mu_b, c);
+  for (int r = 0; r < 4; ++r) M[r][3] = -c[r];
+  pcol(xi, -sp, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) M[r][4] = -c[r];
+  scol(xi, -ss, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) M[r][5] = -c[r];
+  // Gaussian elimination with partial pivoting on the 4x4 block, 2 RHS.
+  for (int k = 0; k < 4; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < 4; ++r)
+      if (std::abs(M[r][k]) > std::abs(M[piv][k])) piv = r;
+    if (std::abs(M[piv][k]) == 0.0) return EMS_ERR_NUMERIC;
+    if (piv != k)
+      for (int cc = 0; cc < 6; ++cc) std::swap(M[k][cc], M[piv][cc]);
+    for (int r = k + 1; r < 4; ++r) {
+      const cd f = M[r][k] / M[k][k];
+      for (int cc = k; cc < 6; ++cc) M[r][cc] -= f * M[k][cc];
+    }
+  }
+  cd X[4][2];
+  for (int col = 0; col < 2; ++col)
+    for (int k = 3; k >= 0; --k) {
+      cd s = M[k][4 + col];
+      for (int cc = k + 1; cc < 4; ++cc) s -= M[k][cc] * X[cc][col];
+      X[k][col] = s / M[k][k];
+    }
+  R[0] = X[0][0];
+  R[1] = X[0][1];
+  R[2] = X[1][0];
+  R[3] = X[1][1];
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(R[i].real()) || !std::isfinite(R[i].imag())) return EMS_ERR_NUMERIC;
+  return EMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Closed-form disk scattering matrix (Section 3.1, boundary condition imposed
+// mode by mode).  Z in {J, H}; f(r) = Z_n(kp r), g(r) = Z_n(ks r).
+// Rigid: rows (u_r, u_theta): grad phi -> (f', (i n / a) f),
+//        grad^perp psi -> (-(i n / a) g, g').
+// Traction-free: rows (sigma_rr, sigma_rtheta):
+//   P: (-lambda kp^2 f + 2 mu f'', 2 mu (i n / a)(f' - f / a))
+//   S: (-2 mu (i n / a)(g' - g / a), mu (g'' - g' / a + n^2 g / a^2)).
+static void bessel_jy(int n, double x, double &J, double &Y) {
+  const int an = std::abs(n);
+  J = ::jn(an, x);
+  Y = ::yn(an, x);
+  if (n < 0 && (an & 1)) {
+    J = -J;
+    Y = -Y;
+  }
+}
+
+static void zfun(bool hankel, int n, double z, cd &f0, cd &f1, cd &f2) {
+  double Jm, Ym, J0, Y0, Jp, Yp;
+  bessel_jy(n - 1, z, Jm, Ym);
+  bessel_jy(n, z, J0, Y0);
+  bessel_jy(n + 1, z, Jp, Yp);
+  if (hankel) {
+    f0 = cd(J0, Y0);
+    f1 = 0.5 * (cd(Jm, Ym) - cd(Jp, Yp));
+  } else {
+    f0 = cd(J0, 0.0);
+    f1 = cd(0.5 * (Jm - Jp), 0.0);
+  }
+  f2 = -f1 / z - (1.0 - double(n) * n / (z * z)) * f0;
+}
+
+static void bc_matrix(bool hankel, int n, double a, const Media &md, int bc, cd M[4]) {
+  const cd I(0.0, 1.0);
+  cd fp0, fp1, fp2, fs0, fs1, fs2;
+  zfun(hankel, n, md.kp * a, fp0, fp1, fp2);
+  zfun(hankel, n, md.ks * a, fs0, fs1, fs2);
+  const cd f = fp0, df = md.kp * fp1, d2f = md.kp * md.kp * fp2;
+  const cd g = fs0, dg = md.ks * fs1, d2g = md.ks * md.ks * fs2;
+  const double nn = n;
+  if (bc == 0) {
+    M[0] = df;
+    M[1] = -(I * nn / a) * g;
+    M[2] = (I * nn / a) * f;
+    M[3] = dg;
+  } else {
+    const double lam = md.lam_h, mu = md.mu_h;
+    M[0] = -lam * md.kp * md.kp * f + 2.0 * mu * d2f;
+    M[1] = -2.0 * mu * (I * nn / a) * (dg - g / a);
+    M[2] = 2.0 * mu * (I * nn / a) * (df - f / a);
+    M[3] = mu * (d2g - dg / a + nn * nn * g / (a * a));
+  }
+}
+
+int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S) {
+  const int N = 2 * p + 1, K = 2 * N;
+  S.assign((size_t)K * K, cd(0.0, 0.0));
+  for (int n = -p; n <= p; ++n) {
+    cd J[4], H[4];
+    bc_matrix(false, n, a, md, bc, J);
+    bc_matrix(true, n, a, md, bc, H);
+    const cd det = H[0] * H[3] - H[1] * H[2];
+    if (std::abs(det) == 0.0) return EMS_ERR_NUMERIC;
+    // -H^{-1} J
+    const cd Hi[4] = {H[3] / det, -H[1] / det, -H[2] / det, H[0] / det};
+    cd B[4];
+    B[0] = -(Hi[0] * J[0] + Hi[1] * J[2]);
+    B[1] = -(Hi[0] * J[1] + Hi[1] * J[3]);
+    B[2] = -(Hi[2] * J[0] + Hi[3] * J[2]);
+    B[3] = -(Hi[2] * J[1] + Hi[3] * J[3]);
+    const int k = n + p;
+    S[(size_t)k * K + k] = B[0];
+    S[(size_t)k * K + N + k] = B[1];
+    S[(size_t)(N + k) * K + k] = B[2];
+    S[(size_t)(N + k) * K + N + k] = B[3];
+  }
+  return EMS_OK;
+}
+
+}  // namespace ems
