@@ -207,6 +207,20 @@ int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_sol
 int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
                        const double *pts, void *u, ems_stream_t stream);
 
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel the library queues.  ems_profile(h, 1) clears and starts
+ * recording, ems_profile(h, 0) stops.  ems_profile_read synchronizes on the
+ * recorded events and fills up to cap entries (one per kernel name) with the
+ * launch count and total milliseconds; *count receives the number of names. */
+typedef struct {
+  char name[40];
+  int32_t launches;
+  double total_ms;
+} ems_kernel_time;
+
+int ems_profile(ems_handle *h, int32_t enable);
+int ems_profile_read(ems_handle *h, ems_kernel_time *out, int32_t cap, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

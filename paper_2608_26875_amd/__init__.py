@@ -63,6 +63,11 @@ class SolveInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32),
+                ("total_ms", ctypes.c_double)]
+
+
 class BuildInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("p_max", ctypes.c_int32), ("n_coeff", ctypes.c_int64),
                 ("q", ctypes.c_int32), ("t_max", ctypes.c_double), ("n_pairs", ctypes.c_int64),
@@ -95,6 +100,8 @@ def _load():
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
                                   ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
         "ems_reflection": ([ctypes.POINTER(Media), D, D, P], I32),
+        "ems_profile": ([P, I32], I32),
+        "ems_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -107,7 +114,8 @@ _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
-            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection")
+            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
+            "ems_profile_read")
 
 
 def lib():
@@ -278,6 +286,16 @@ class Operator:
         if rc < 0:
             self._check(rc)
         return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+
+    def profile(self, enable: bool):
+        self._check(_lib.ems_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (launches, total_ms)} from the HIP events recorded so far."""
+        arr = (KernelTime * 64)()
+        cnt = ctypes.c_int32(0)
+        self._check(_lib.ems_profile_read(self.h, arr, 64, ctypes.byref(cnt)))
+        return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms) for k in range(cnt.value)}
 
     def _check(self, rc):
         if rc < 0:

@@ -41,7 +41,16 @@ void dfree(T *&p) {
   p = nullptr;
 }
 
+void clear_prof(ems_handle *h) {
+  for (auto &r : h->prof_recs) {
+    if (r.a) (void)hipEventDestroy(r.a);
+    if (r.b) (void)hipEventDestroy(r.b);
+  }
+  h->prof_recs.clear();
+}
+
 void free_device(ems_handle *h) {
+  clear_prof(h);
   dfree(h->d_xy);
   dfree(h->d_p);
   dfree(h->d_off);
@@ -167,17 +176,31 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
   if (adjoint && (parts & EMS_PART_S)) {
     rc = ensure_tmp(h, sizeof(double2) * (size_t)nrhs * h->ncoef);
     if (rc) return rc;
+    ems::ProfScope ps(h, "s_apply_adjoint", st);
     HIPCHK(h, ems::launch_s_apply(h, x, h->d_tmp, nrhs, true, st));
     src = h->d_tmp;
   }
-  if (parts & EMS_PART_FREE) HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+  if (parts & EMS_PART_FREE) {
+    ems::ProfScope ps(h, "graf_direct", st);
+    HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+  }
   if (parts & EMS_PART_REFL) {
-    HIPCHK(h, ems::launch_somm_aggregate(h, src, nrhs, adjoint, mixed, st));
-    HIPCHK(h, ems::launch_somm_reflect(h, nrhs, adjoint, st));
-    HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, adjoint, mixed, st));
+    {
+      ems::ProfScope ps(h, "somm_aggregate", st);
+      HIPCHK(h, ems::launch_somm_aggregate(h, src, nrhs, adjoint, mixed, st));
+    }
+    {
+      ems::ProfScope ps(h, "somm_reflect", st);
+      HIPCHK(h, ems::launch_somm_reflect(h, nrhs, adjoint, st));
+    }
+    {
+      ems::ProfScope ps(h, "somm_disaggregate", st);
+      HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, adjoint, mixed, st));
+    }
   }
   int cflags = parts;
   if (adjoint) cflags &= ~EMS_PART_S;
+  ems::ProfScope ps(h, "combine_s_apply", st);
   HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, st));
   return EMS_OK;
 }
@@ -204,6 +227,43 @@ void ems_destroy(ems_handle *h) {
 }
 
 const char *ems_last_error(const ems_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int ems_profile(ems_handle *h, int32_t enable) {
+  if (!h) return EMS_ERR_ARG;
+  if (enable) clear_prof(h);
+  h->prof = enable != 0;
+  return EMS_OK;
+}
+
+int ems_profile_read(ems_handle *h, ems_kernel_time *out, int32_t cap, int32_t *count) {
+  if (!h || !count || (cap > 0 && !out)) return EMS_ERR_ARG;
+  std::vector<std::string> names;
+  std::vector<int> launches;
+  std::vector<double> ms;
+  for (auto &r : h->prof_recs) {
+    HIPCHK(h, hipEventSynchronize(r.b));
+    float t = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&t, r.a, r.b));
+    size_t k = 0;
+    for (; k < names.size(); ++k)
+      if (names[k] == r.name) break;
+    if (k == names.size()) {
+      names.push_back(r.name);
+      launches.push_back(0);
+      ms.push_back(0.0);
+    }
+    launches[k] += 1;
+    ms[k] += t;
+  }
+  *count = (int32_t)names.size();
+  for (int k = 0; k < (int)names.size() && k < cap; ++k) {
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, names[k].c_str(), sizeof(out[k].name) - 1);
+    out[k].launches = launches[k];
+    out[k].total_ms = ms[k];
+  }
+  return EMS_OK;
+}
 
 int ems_set_media(ems_handle *h, const ems_media *m) {
   if (!h || !m) return EMS_ERR_ARG;

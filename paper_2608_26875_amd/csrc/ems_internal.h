@@ -112,6 +112,14 @@ struct ems_handle {
   double2 *d_free = nullptr;     // [nrhs][ncoef]
   int64_t n_pairs = 0;
 
+  // kernel timing (ems_profile)
+  bool prof = false;
+  struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_recs;
+
   // GMRES workspace
   double2 *d_V = nullptr;        // Krylov basis
   size_t V_bytes = 0;
@@ -122,6 +130,25 @@ struct ems_handle {
 };
 
 namespace ems {
+
+// Records HIP events around one launch when profiling is on.
+struct ProfScope {
+  ems_handle *h;
+  hipStream_t st;
+  size_t idx;
+  ProfScope(ems_handle *h_, const char *name, hipStream_t s) : h(h_), st(s), idx(0) {
+    if (!h->prof) return;
+    ems_handle::ProfRec r{name, nullptr, nullptr};
+    (void)hipEventCreate(&r.a);
+    (void)hipEventCreate(&r.b);
+    (void)hipEventRecord(r.a, st);
+    h->prof_recs.push_back(r);
+    idx = h->prof_recs.size();
+  }
+  ~ProfScope() {
+    if (idx) (void)hipEventRecord(h->prof_recs[idx - 1].b, st);
+  }
+};
 
 // ---- kernel launchers (defined in the .hip files) --------------------------
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
