@@ -112,6 +112,8 @@ typedef struct {
   int32_t q;            /* Sommerfeld nodes                                   */
   double t_max;
   int64_t n_pairs;      /* free-space particle pairs evaluated directly       */
+  int32_t fmm_levels;   /* 0 = direct sum                                     */
+  int64_t fmm_m2l;      /* multipole-to-local translations per apply          */
   double kp, ks, kpb, ksb;
 } ems_build_info;
 
@@ -167,6 +169,22 @@ int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
  * welded interface (Section 2.2, the 4x4 continuity system per Fourier mode,
  * density kept), row-major complex128 into R_out[8]. */
 int ems_reflection(const ems_media *m, double xi_re, double xi_im, double *R_out);
+
+/* Free-space part (Section 3.2 gives the Graf translations and names the
+ * FMM; the library builds a uniform-quadtree Graf FMM).
+ *  mode 0: automatic (FMM when n > 1500), 1: direct sum over all pairs,
+ *  2: FMM.  leaf: target particles per leaf box (0 = 20); top_boxes: the
+ *  coarsest level kept has at most this many occupied boxes, all of whose
+ *  non-adjacent pairs interact directly (0 = 64); digits: accuracy target of
+ *  the expansion orders (0 = 13). */
+typedef struct {
+  int32_t mode;
+  int32_t leaf;
+  int32_t top_boxes;
+  double digits;
+} ems_fmm;
+
+int ems_set_fmm(ems_handle *h, const ems_fmm *f);
 
 /* Validate, build the node table and the per-node 2x2 reflection R(xi_j)
  * (the 4x4 interface system of Section 2.2 solved per node), pack the S

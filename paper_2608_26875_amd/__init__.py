@@ -63,6 +63,11 @@ class SolveInfo(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class Fmm(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("leaf", ctypes.c_int32), ("top_boxes", ctypes.c_int32),
+                ("digits", ctypes.c_double)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32),
                 ("total_ms", ctypes.c_double)]
@@ -71,6 +76,7 @@ class KernelTime(ctypes.Structure):
 class BuildInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("p_max", ctypes.c_int32), ("n_coeff", ctypes.c_int64),
                 ("q", ctypes.c_int32), ("t_max", ctypes.c_double), ("n_pairs", ctypes.c_int64),
+                ("fmm_levels", ctypes.c_int32), ("fmm_m2l", ctypes.c_int64),
                 ("kp", ctypes.c_double), ("ks", ctypes.c_double), ("kpb", ctypes.c_double),
                 ("ksb", ctypes.c_double)]
 
@@ -101,6 +107,7 @@ def _load():
                                   ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
         "ems_reflection": ([ctypes.POINTER(Media), D, D, P], I32),
         "ems_profile": ([P, I32], I32),
+        "ems_set_fmm": ([P, ctypes.POINTER(Fmm)], I32),
         "ems_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], I32),
     }
     for name, (args, res) in sig.items():
@@ -115,7 +122,7 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
-            "ems_profile_read")
+            "ems_profile_read", "ems_set_fmm")
 
 
 def lib():
@@ -175,6 +182,8 @@ def reflection(media: Media, xi: complex) -> np.ndarray:
 
 def _stream_ptr(stream=None):
     import torch
+    if stream is None and not torch.cuda.is_available():
+        return None
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
 
@@ -182,7 +191,8 @@ def _stream_ptr(stream=None):
 class Operator:
     """Handle around one particle cloud, its media, S-matrices and node table."""
 
-    def __init__(self, xy, radius, p, media: Media, S_blocks=None, bc=None, sommerfeld=None):
+    def __init__(self, xy, radius, p, media: Media, S_blocks=None, bc=None, sommerfeld=None,
+                 fmm=None):
         self.h = ctypes.c_void_p()
         self._check(_lib.ems_create(ctypes.byref(self.h)))
         self.media = media
@@ -200,6 +210,14 @@ class Operator:
         self.set_smatrices(S_blocks)
         if sommerfeld is not None:
             self.set_sommerfeld(**sommerfeld)
+        if fmm is not None:
+            self.set_fmm(**fmm)
+        self.built = False
+
+    def set_fmm(self, mode=0, leaf=0, top_boxes=0, digits=0.0):
+        """mode 0 automatic, 1 direct sum, 2 FMM."""
+        f = Fmm(int(mode), int(leaf), int(top_boxes), float(digits))
+        self._check(_lib.ems_set_fmm(self.h, ctypes.byref(f)))
         self.built = False
 
     def disk_blocks(self, bc):

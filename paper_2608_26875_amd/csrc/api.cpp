@@ -71,6 +71,26 @@ void free_device(ems_handle *h) {
   dfree(h->d_V);
   dfree(h->d_tmp);
   dfree(h->d_red);
+  dfree(h->d_pool);
+  dfree(h->d_mult);
+  dfree(h->d_loc);
+  dfree(h->d_nbr_ptr);
+  dfree(h->d_nbr_idx);
+  dfree(h->d_adj1);
+  dfree(h->d_adj2);
+  for (auto &D : h->fmm_dev) {
+    dfree(D.ptr);
+    dfree(D.in_P);
+    dfree(D.sym_L);
+    dfree(D.sgn);
+    dfree(D.out_P);
+    dfree(D.item_out);
+    dfree(D.item_row0);
+    dfree(D.in_base);
+    dfree(D.sym_base);
+    dfree(D.out_base);
+  }
+  h->fmm_dev.clear();
   h->ws_nrhs = 0;
   h->V_bytes = h->tmp_bytes = h->red_bytes = 0;
 }
@@ -108,6 +128,14 @@ int ensure_ws(ems_handle *h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_refl, sizeof(double2) * (size_t)nrhs * 2 * h->q));
   HIPCHK(h, hipMalloc(&h->d_dis, sizeof(double2) * (size_t)nrhs * h->dis_chunks * nc));
   HIPCHK(h, hipMalloc(&h->d_free, sizeof(double2) * (size_t)nrhs * nc));
+  dfree(h->d_mult);
+  dfree(h->d_loc);
+  dfree(h->d_adj1);
+  dfree(h->d_adj2);
+  if (h->fmm_on) {
+    HIPCHK(h, hipMalloc(&h->d_mult, sizeof(double2) * (size_t)nrhs * h->fmm.exp_len));
+    HIPCHK(h, hipMalloc(&h->d_loc, sizeof(double2) * (size_t)nrhs * h->fmm.exp_len));
+  }
   h->ws_nrhs = nrhs;
   return EMS_OK;
 }
@@ -181,8 +209,33 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
     src = h->d_tmp;
   }
   if (parts & EMS_PART_FREE) {
-    ems::ProfScope ps(h, "graf_direct", st);
-    HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+    if (!h->fmm_on) {
+      ems::ProfScope ps(h, "graf_direct", st);
+      HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+    } else if (!adjoint) {
+      {
+        ems::ProfScope ps(h, "graf_near", st);
+        HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, false, mixed, st));
+      }
+      HIPCHK(h, ems::launch_fmm(h, src, h->d_free, nrhs, st));
+    } else {
+      // reciprocity: T^H v = P conj(T conj(P v))
+      const size_t bytes = sizeof(double2) * (size_t)nrhs * h->ncoef;
+      if (h->adj_bytes < bytes) {
+        dfree(h->d_adj1);
+        dfree(h->d_adj2);
+        HIPCHK(h, hipMalloc(&h->d_adj1, bytes));
+        HIPCHK(h, hipMalloc(&h->d_adj2, bytes));
+        h->adj_bytes = bytes;
+      }
+      HIPCHK(h, ems::launch_conj_flip(h, src, h->d_adj1, nrhs, st));
+      {
+        ems::ProfScope ps(h, "graf_near", st);
+        HIPCHK(h, ems::launch_graf_direct(h, h->d_adj1, h->d_adj2, nrhs, false, mixed, st));
+      }
+      HIPCHK(h, ems::launch_fmm(h, h->d_adj1, h->d_adj2, nrhs, st));
+      HIPCHK(h, ems::launch_conj_flip(h, h->d_adj2, h->d_free, nrhs, st));
+    }
   }
   if (parts & EMS_PART_REFL) {
     {
@@ -410,6 +463,19 @@ int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s) {
   return EMS_OK;
 }
 
+int ems_set_fmm(ems_handle *h, const ems_fmm *f) {
+  if (!h || !f) return EMS_ERR_ARG;
+  if (f->mode < 0 || f->mode > 2) return fail(h, EMS_ERR_ARG, "fmm mode must be 0, 1 or 2");
+  if (f->leaf < 0 || f->top_boxes < 0 || f->digits < 0 || f->digits > 15.5)
+    return fail(h, EMS_ERR_ARG, "bad fmm parameters");
+  h->fmm_mode = f->mode;
+  h->fmm_leaf = f->leaf > 0 ? f->leaf : 20;
+  h->fmm_top = f->top_boxes > 0 ? f->top_boxes : 64;
+  h->fmm_digits = f->digits > 0 ? f->digits : 13.0;
+  h->built = false;
+  return EMS_OK;
+}
+
 int ems_build(ems_handle *h, ems_stream_t stream) {
   (void)stream;
   if (!h) return EMS_ERR_ARG;
@@ -417,7 +483,6 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
     return fail(h, EMS_ERR_STATE, "set media, particles and S-matrices before build");
   int rc = check_geometry(h);
   if (rc) return rc;
-  if (h->device < 0) return fail(h, EMS_ERR_HIP, "no HIP device");
   free_device(h);
   // node table and per-node reflection
   ems::NodeTable nt;
@@ -471,6 +536,15 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   }
   std::vector<float2> St32(St.size());
   for (size_t k = 0; k < St.size(); ++k) St32[k] = make_float2((float)St[k].x, (float)St[k].y);
+  // free-space part: direct sum or FMM (host plan, bounds-checked)
+  h->fmm_on = h->fmm_mode == 2 || (h->fmm_mode == 0 && h->n > 1500);
+  h->n_pairs = (int64_t)h->n * (h->n - 1);
+  if (h->fmm_on) {
+    rc = ems::build_fmm(h, h->fmm, h->err);
+    if (rc) return rc;
+    h->n_pairs = (int64_t)h->fmm.nbr_idx.size();
+  }
+  if (h->device < 0) return fail(h, EMS_ERR_HIP, "no HIP device (host set-up completed)");
   if ((rc = upload(h, h->d_xy, h->xy.data(), h->xy.size()))) return rc;
   std::vector<int> pv(h->p.begin(), h->p.end());
   if ((rc = upload(h, h->d_p, pv.data(), pv.size()))) return rc;
@@ -485,7 +559,32 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if ((rc = upload(h, h->d_R, R.data(), R.size()))) return rc;
   if ((rc = upload(h, h->d_Vp, Vp.data(), Vp.size()))) return rc;
   if ((rc = upload(h, h->d_Vs, Vs.data(), Vs.size()))) return rc;
-  h->n_pairs = (int64_t)h->n * (h->n - 1);
+  if (h->fmm_on) {
+    ems::FmmPlan &F = h->fmm;
+    std::vector<double2> pool(F.pool.size());
+    for (size_t k = 0; k < pool.size(); ++k) pool[k] = make_double2(F.pool[k].real(), F.pool[k].imag());
+    if ((rc = upload(h, h->d_pool, pool.data(), pool.size()))) return rc;
+    if ((rc = upload(h, h->d_nbr_ptr, F.nbr_ptr.data(), F.nbr_ptr.size()))) return rc;
+    if ((rc = upload(h, h->d_nbr_idx, F.nbr_idx.data(), std::max<size_t>(1, F.nbr_idx.size())))) return rc;
+    h->fmm_dev.assign(F.launches.size(), ems::FmmDev());
+    static const char *names[] = {"fmm_p2m", "fmm_m2m", "fmm_m2l_l2l", "fmm_l2p"};
+    for (size_t i = 0; i < F.launches.size(); ++i) {
+      ems::FmmLaunch &L = F.launches[i];
+      L.name = L.in_kind == 0 ? names[0]
+                              : (L.out_kind == 1 ? names[1] : (L.out_kind == 2 ? names[2] : names[3]));
+      ems::FmmDev &D = h->fmm_dev[i];
+      if ((rc = upload(h, D.ptr, L.ptr.data(), L.ptr.size()))) return rc;
+      if ((rc = upload(h, D.in_P, L.in_P.data(), L.in_P.size()))) return rc;
+      if ((rc = upload(h, D.sym_L, L.sym_L.data(), L.sym_L.size()))) return rc;
+      if ((rc = upload(h, D.sgn, L.sgn.data(), L.sgn.size()))) return rc;
+      if ((rc = upload(h, D.out_P, L.out_P.data(), L.out_P.size()))) return rc;
+      if ((rc = upload(h, D.item_out, L.item_out.data(), L.item_out.size()))) return rc;
+      if ((rc = upload(h, D.item_row0, L.item_row0.data(), L.item_row0.size()))) return rc;
+      if ((rc = upload(h, D.in_base, L.in_base.data(), L.in_base.size()))) return rc;
+      if ((rc = upload(h, D.sym_base, L.sym_base.data(), L.sym_base.size()))) return rc;
+      if ((rc = upload(h, D.out_base, L.out_base.data(), L.out_base.size()))) return rc;
+    }
+  }
   if ((rc = ensure_ws(h, 1))) return rc;
   HIPCHK(h, hipDeviceSynchronize());
   h->built = true;
@@ -500,6 +599,8 @@ int ems_get_info(const ems_handle *h, ems_build_info *out) {
   out->q = h->q;
   out->t_max = h->nodes.t_max;
   out->n_pairs = h->n_pairs;
+  out->fmm_levels = h->fmm_on ? h->fmm.Lf - h->fmm.Lt + 1 : 0;
+  out->fmm_m2l = h->fmm_on ? h->fmm.n_m2l : 0;
   out->kp = h->md.kp;
   out->ks = h->md.ks;
   out->kpb = h->md.kpb;

@@ -68,7 +68,45 @@ int reflection_s(cd xi, const cd s[4], const Media &md, cd R[4]);
 // Closed-form disk scattering matrix, row-major (4p+2)^2.
 int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S);
 
-struct Workspace;
+// Free-space FMM plan (fmm.cpp): tree levels, expansion orders, near lists
+// and the task lists of the batched Toeplitz kernel.
+struct FmmLevel {
+  std::vector<int> bx, by;
+  int P[2] = {0, 0};
+  int64_t off[2] = {0, 0};  // start of this level's expansions (per wave)
+  double side = 0.0;
+};
+
+// One launch of the Toeplitz task kernel.  in_kind: 0 particle coefficients,
+// 1 multipoles, 2 locals; out_kind: 1 multipoles, 2 locals, 3 free-part
+// output.  Tasks with sgn = 2 read from the locals (L2L inside an M2L launch);
+// sgn = -1 flips the odd symbol entries (L2P).
+struct FmmLaunch {
+  const char *name = "fmm";
+  int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0;
+  std::vector<int> ptr, in_P, sym_L, sgn, out_P, item_out, item_row0;
+  std::vector<int64_t> in_base, sym_base, out_base;
+};
+
+struct FmmDev {
+  int *ptr = nullptr, *in_P = nullptr, *sym_L = nullptr, *sgn = nullptr, *out_P = nullptr;
+  int *item_out = nullptr, *item_row0 = nullptr;
+  int64_t *in_base = nullptr, *sym_base = nullptr, *out_base = nullptr;
+};
+
+struct FmmPlan {
+  int Lf = 0, Lt = 0;
+  double S0 = 0.0;
+  std::vector<FmmLevel> levels;  // index 0 = top level Lt
+  int64_t exp_len = 0;           // complex elements of all expansions (per RHS)
+  std::vector<int> nbr_ptr, nbr_idx;
+  std::vector<int64_t> part_sym;
+  std::vector<FmmLaunch> launches;
+  std::vector<cd> pool;
+  int64_t n_m2l = 0;
+};
+
+int fmm_order(double k, double side, int p, double digits);
 
 }  // namespace ems
 
@@ -112,6 +150,18 @@ struct ems_handle {
   double2 *d_free = nullptr;     // [nrhs][ncoef]
   int64_t n_pairs = 0;
 
+  // free-space FMM
+  int fmm_mode = 0;            // 0 auto, 1 direct, 2 FMM
+  int fmm_leaf = 20, fmm_top = 64;
+  double fmm_digits = 13.0;
+  bool fmm_on = false;
+  ems::FmmPlan fmm;
+  std::vector<ems::FmmDev> fmm_dev;
+  double2 *d_pool = nullptr, *d_mult = nullptr, *d_loc = nullptr;
+  int *d_nbr_ptr = nullptr, *d_nbr_idx = nullptr;
+  double2 *d_adj1 = nullptr, *d_adj2 = nullptr;  // adjoint free-part scratch
+  size_t adj_bytes = 0;
+
   // kernel timing (ems_profile)
   bool prof = false;
   struct ProfRec {
@@ -153,6 +203,11 @@ struct ProfScope {
 // ---- kernel launchers (defined in the .hip files) --------------------------
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
                               bool adjoint, bool mixed, hipStream_t st);
+int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err);
+hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs,
+                      hipStream_t st);
+hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out, int nrhs,
+                            hipStream_t st);
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);

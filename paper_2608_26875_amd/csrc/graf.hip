@@ -37,7 +37,8 @@ template <int PM, bool MIXED>
 __global__ __launch_bounds__(64) void graf_direct_kernel(
     int n, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
-    double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint) {
+    double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint,
+    const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx) {
   using T = typename CT<MIXED>::T;
   constexpr int NT = 4 * PM + 1;
   constexpr int NM = 2 * PM + 1;
@@ -56,10 +57,14 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
   T acc;
   acc.x = 0;
   acc.y = 0;
+  // partners: every other particle, or the near list of b
+  const int np = nbr_ptr ? nbr_ptr[b + 1] - nbr_ptr[b] : n;
+  const int *nl = nbr_ptr ? nbr_idx + nbr_ptr[b] : nullptr;
 
-  for (int base = 0; base < n; base += SB) {
+  for (int base = 0; base < np; base += SB) {
     if (lane < 2 * SB) {
-      const int s = lane >> 1, ww = lane & 1, l = base + s;
+      const int s = lane >> 1, ww = lane & 1;
+      const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
       T *t = t_lds[ww][s];
       if (l < n && l != b) {
         // th_ml: angle of x_m - x_l (m target, l source of the forward map)
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
     for (int e = lane; e < SB * 2 * NM; e += 64) {
       const int s = e / (2 * NM), rem = e - s * (2 * NM);
       const int ww = rem / NM, jj = rem - ww * NM - PM;
-      const int l = base + s;
+      const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
       double2 v = make_double2(0.0, 0.0);
       if (l < n && l != b) {
         const int pl = p[l];
@@ -136,11 +141,11 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
     if (mixed)                                                                               \
       hipLaunchKernelGGL((graf_direct_kernel<PMV, true>), grid, dim3(64), 0, st, h->n,       \
                          h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
-                         h->md.ks, adjoint ? 1 : 0);                                          \
+                         h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
     else                                                                                     \
       hipLaunchKernelGGL((graf_direct_kernel<PMV, false>), grid, dim3(64), 0, st, h->n,      \
                          h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
-                         h->md.ks, adjoint ? 1 : 0);                                          \
+                         h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
     break;
 
 int pm_bucket(int pmax) {
@@ -154,6 +159,8 @@ int pm_bucket(int pmax) {
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
                               bool adjoint, bool mixed, hipStream_t st) {
   dim3 grid(h->n, nrhs);
+  const int *nptr = h->fmm_on ? h->d_nbr_ptr : nullptr;
+  const int *nidx = h->fmm_on ? h->d_nbr_idx : nullptr;
   switch (pm_bucket(h->pmax)) {
     EMS_GRAF_CASE(4)
     EMS_GRAF_CASE(8)
