@@ -61,15 +61,19 @@ typedef struct {
 /* Sommerfeld quadrature on the xi axis (Section 4.1).
  *  kind 0: the paper's hyperbolic-tangent contour xi(t) = t - i delta tanh t,
  *          t in [-t_max, t_max], trapezoidal rule with q nodes;
- *  kind 1: real axis, composite Gauss-Legendre panels with a xi = k +- u^2
- *          substitution on the panel next to each branch point (+-kp, +-ks of
- *          both layers), panel length from the horizontal extent of the
- *          particle cloud, tails to +-t_max; q is an output (node count);
- *  kind 2: user nodes: q entries of nodes = [Re xi, Im xi, Re w, Im w].
+ *  kind 1: real axis; around the branch points (+-kp, +-ks of both layers)
+ *          composite Gauss-Legendre panels graded towards each branch point
+ *          with a xi = k +- u^2 substitution panel next to it, panel length
+ *          from the horizontal extent and depth of the particle cloud; the
+ *          tails out to +-t_max by the trapezoidal rule on a smooth (erfc)
+ *          partition of unity; q is an output (node count);
+ *  kind 2: user nodes: q entries of nodes = [Re xi, Im xi, Re w, Im w];
+ *  kind 3: as kind 1 but Gauss-Legendre panels on the tails too.
  * t_max <= 0 asks the library to choose it from the depth of the shallowest
  * particle and the largest p (decay of exp(-|xi| D)(2|xi|/k)^(2p)).
  * panel_scale multiplies the default panel length of kind 1 (1 = default);
- * panel_order is the Gauss-Legendre order of the kind 1 panels (0 = 64). */
+ * panel_order is the Gauss-Legendre order of the kind 1 panels (0 = 64);
+ * tail_factor scales the trapezoidal density of the kind 1 tails (0 = 1). */
 typedef struct {
   int32_t kind;
   int32_t q;
@@ -78,6 +82,7 @@ typedef struct {
   double panel_scale;
   const double *nodes; /* host, kind 2 only */
   int32_t panel_order;
+  double tail_factor;
 } ems_sommerfeld;
 
 /* Plane wave sent from the particle side towards the interface, direction

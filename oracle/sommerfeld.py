@@ -178,7 +178,13 @@ def apply_refl(w, m: Media, x: np.ndarray, targets=None, S_blocks=None, R_fun=No
     else:
         user_R = R_fun
         R_fun = lambda xi, sv: user_R(xi)  # noqa: E731
-    f, out_len, tgt = _integrand_factory(w, m, np.asarray(x, complex), targets, S_blocks, R_fun)
+    f0, out_len, tgt = _integrand_factory(w, m, np.asarray(x, complex), targets, S_blocks, R_fun)
+    neval = [0]
+
+    def f(*a):
+        neval[0] += 1
+        return f0(*a)
+
     if T is None:
         T = tail_extent(w, m)
     pieces = _pieces(m, T)
@@ -192,6 +198,6 @@ def apply_refl(w, m: Media, x: np.ndarray, targets=None, S_blocks=None, R_fun=No
             y[off[l]: off[l] + blk] = v[pos: pos + blk]
             pos += blk
     if return_info:
-        return y, {"err": err, "scale": scale, "T": T, "pieces": len(pieces)}
+        return y, {"err": err, "scale": scale, "T": T, "pieces": len(pieces), "neval": neval[0]}
     return y
 

@@ -45,7 +45,8 @@ class Media(ctypes.Structure):
 class Sommerfeld(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("q", ctypes.c_int32), ("t_max", ctypes.c_double),
                 ("delta", ctypes.c_double), ("panel_scale", ctypes.c_double),
-                ("nodes", ctypes.POINTER(ctypes.c_double)), ("panel_order", ctypes.c_int32)]
+                ("nodes", ctypes.POINTER(ctypes.c_double)), ("panel_order", ctypes.c_int32),
+                ("tail_factor", ctypes.c_double)]
 
 
 class PlaneWave(ctypes.Structure):
@@ -150,12 +151,12 @@ def smatrix_disk(media: Media, a: float, p: int, bc: int) -> np.ndarray:
 
 
 def sommerfeld_nodes(media: Media, xy, p, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0,
-                     panel_order=0):
+                     panel_order=0, tail_factor=0.0):
     """Host-only node table [q, 6] = (Re xi, Im xi, Re w, Im w, bp, d) and the tail extent."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     p = np.ascontiguousarray(p, dtype=np.int32)
     s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), None,
-                   int(panel_order))
+                   int(panel_order), float(tail_factor))
     cnt = ctypes.c_int32(0)
     tm = ctypes.c_double(0)
     rc = _lib.ems_sommerfeld_nodes(ctypes.byref(media), ctypes.byref(s), len(p), xy.ctypes.data,
@@ -239,14 +240,14 @@ class Operator:
         self.built = False
 
     def set_sommerfeld(self, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0, nodes=None,
-                       panel_order=0):
+                       panel_order=0, tail_factor=0.0):
         ptr = None
         if nodes is not None:
             self._nodes_keep = np.ascontiguousarray(nodes, dtype=np.float64)
             ptr = self._nodes_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             q = self._nodes_keep.shape[0]
         s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), ptr,
-                       int(panel_order))
+                       int(panel_order), float(tail_factor))
         self._check(_lib.ems_set_sommerfeld(self.h, ctypes.byref(s)))
         self.built = False
 

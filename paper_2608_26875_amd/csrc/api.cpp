@@ -388,8 +388,8 @@ int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double
 }
 
 static int spec_from(const ems_sommerfeld *s, ems::SommerfeldSpec &o, std::string &err) {
-  if (s->kind < 0 || s->kind > 2) {
-    err = "sommerfeld kind must be 0, 1, 2";
+  if (s->kind < 0 || s->kind > 3) {
+    err = "sommerfeld kind must be 0, 1, 2, 3";
     return EMS_ERR_ARG;
   }
   o.kind = s->kind;
@@ -398,6 +398,7 @@ static int spec_from(const ems_sommerfeld *s, ems::SommerfeldSpec &o, std::strin
   o.delta = s->delta > 0 ? s->delta : 0.5;
   o.panel_scale = s->panel_scale > 0 ? s->panel_scale : 1.0;
   o.panel_order = s->panel_order > 0 ? s->panel_order : 64;
+  o.tail_factor = s->tail_factor > 0 ? s->tail_factor : 1.0;
   if (o.panel_order < 8 || o.panel_order > 256) {
     err = "panel_order must be in [8, 256]";
     return EMS_ERR_ARG;

@@ -45,6 +45,7 @@ struct SommerfeldSpec {
   double delta = 0.5;
   double panel_scale = 1.0;
   int panel_order = 64;
+  double tail_factor = 1.0;
   std::vector<double> user;  // kind 2: [q][4]
 };
 

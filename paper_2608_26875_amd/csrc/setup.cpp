@@ -178,21 +178,30 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
     }
     return EMS_OK;
   }
-  if (spec.kind != 1) {
+  if (spec.kind != 1 && spec.kind != 3) {
     err = "unknown sommerfeld kind";
     return EMS_ERR_ARG;
   }
-  // Real axis, composite Gauss-Legendre with graded panels at branch points.
+  // Real axis.  Core |xi| <= K + b around the branch points: composite
+  // Gauss-Legendre panels, graded towards every branch point with a
+  // xi = k +- u^2 panel next to it.  With spec.kind == 1 the tails
+  // |xi| >= K use the trapezoidal rule on a smooth partition of unity:
+  // chi = 1 on |xi| <= K, chi = erfc(beta (2t - 1)) / 2 for t = (|xi| - K)/b
+  // in [0, 1], 0 beyond.  The core panels carry chi, the tail nodes 1 - chi;
+  // f (1 - chi) is smooth and vanishes at |xi| = K, so the trapezoidal rule
+  // is spectrally accurate there once 2 pi / h exceeds the horizontal
+  // spread X plus the width of the window's and f's spectra.  kind 3 keeps
+  // Gauss-Legendre panels everywhere.
   PanelRule r;
   r.n = spec.panel_order;
   gauss_legendre(r.n, r.gx, r.gw);
   // A panel of n Gauss points is exact to degree 2n - 1.  The integrand is a
   // plane wave of frequency sqrt(X^2 + D^2) (horizontal spread X, depth sum
   // D) times powers zeta^(n + n') of degree up to 2 p_max.  Measured against
-  // the multipole-to-Sommerfeld lemma at orders +-2p, 64-point panels stay at
-  // the rounding floor while (half-length) x (frequency) <= ~75 for p <= 15;
-  // the default keeps 0.9 n.
-  const double wmax = 0.9 * r.n;
+  // the multipole-to-Sommerfeld lemma at orders +-2p and against the
+  // oracle at the 20000-particle cloud, (half-length) x (frequency) must
+  // stay below about 1.2 n - 2 p_max - 8.
+  const double wmax = std::max(8.0, 1.2 * r.n - 2.0 * pmax - 8.0);
   const double freq = std::sqrt(X * X + Dmax * Dmax);
   double Losc = std::min(2.0, 2.0 * wmax / freq) * spec.panel_scale;
   std::vector<double> bps = {md.kp, md.ks, md.kpb, md.ksb};
@@ -203,7 +212,11 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
   std::vector<double> pts;
   for (auto it = bps.rbegin(); it != bps.rend(); ++it) pts.push_back(-*it);
   for (double b : bps) pts.push_back(b);
-  if (T <= pts.back() + 0.5) T = pts.back() + 0.5;
+  const bool hybrid = spec.kind == 1;
+  const double a_margin = 1.5, b_win = 2.5, beta = 6.0;
+  const double K = pts.back() + a_margin;
+  const double core_end = hybrid ? K + b_win : T;
+  if (T <= core_end + 0.5) T = core_end + 0.5;
   out.t_max = T;
   // Substitution panel [bp, bp + L] in u = sqrt(|xi - bp|): the chirp
   // e^{i X u^2} gives u-frequency 2 X u and the depth factor e^{-sqrt(2k) u D}
@@ -216,19 +229,31 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
     const double L = (-bq + std::sqrt(bq * bq + 4.0 * X * X * wsub * wsub)) / (2.0 * X * X);
     return std::min(0.5 * Losc, L);
   };
-  // left tail [-T, pts[0]]: singular at pts[0] only
-  {
-    const double bp = pts.front();
-    graded_half(r, bp, -T, Lb_of(bp), Losc, out);
-  }
+  graded_half(r, pts.front(), -core_end, Lb_of(pts.front()), Losc, out);
   for (size_t i = 0; i + 1 < pts.size(); ++i) {
     const double a = pts[i], b = pts[i + 1], mid = 0.5 * (a + b);
     graded_half(r, a, mid, Lb_of(a), Losc, out);
     graded_half(r, b, mid, Lb_of(b), Losc, out);
   }
-  {
-    const double bp = pts.back();
-    graded_half(r, bp, T, Lb_of(bp), Losc, out);
+  graded_half(r, pts.back(), core_end, Lb_of(pts.back()), Losc, out);
+  if (hybrid) {
+    auto chi = [&](double x) {
+      const double t = (std::fabs(x) - K) / b_win;
+      if (t <= 0) return 1.0;
+      if (t >= 1) return 0.0;
+      return 0.5 * std::erfc(beta * (2.0 * t - 1.0));
+    };
+    for (size_t j = 0; j < out.xi.size(); ++j) out.w[j] *= chi(out.xi[j].real());
+    // tail step: 2 pi / h >= tail_factor (X + 16 beta / b + 40)
+    const double nu = spec.tail_factor * (X + 16.0 * beta / b_win + 40.0);
+    const double h = 2.0 * kPi / nu;
+    for (int side = -1; side <= 1; side += 2)
+      for (int j = 1;; ++j) {
+        const double x = K + j * h;
+        if (x > T) break;
+        const double wgt = h * (1.0 - chi(x));
+        push(out, cd(side * x, 0.0), cd(wgt, 0.0), 0.0, 0.0);
+      }
   }
   // sort by xi (helps locality; the sum is order independent up to rounding)
   std::vector<size_t> idx(out.xi.size());

@@ -50,7 +50,8 @@ def make(name):
     np.savez(os.path.join(HERE, f"{name}_sampled.npz"), targets=np.array(tg), rows=rows,
              free=tf[rows], s_free=sf[rows], s_refl=sr[rows], z=(sf + sr)[rows],
              x_digest=np.array(digest(x)), xy_digest=np.array(digest(w.xy)),
-             refl_err=np.array(info["err"]), refl_scale=np.array(info["scale"]))
+             refl_err=np.array(info["err"]), refl_scale=np.array(info["scale"]),
+             refl_neval=np.array(info["neval"]), refl_seconds=np.array(t2 - t1))
     print(f"{name}: free {t1 - t0:.1f}s refl {t2 - t1:.1f}s {info}", flush=True)
 
 
