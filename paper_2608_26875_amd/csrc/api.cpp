@@ -64,6 +64,8 @@ void free_device(ems_handle *h) {
   dfree(h->d_R);
   dfree(h->d_Vp);
   dfree(h->d_Vs);
+  dfree(h->d_Eagg);
+  dfree(h->d_Edis);
   dfree(h->d_agg);
   dfree(h->d_refl);
   dfree(h->d_dis);
@@ -584,6 +586,28 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
       if ((rc = upload(h, D.in_base, L.in_base.data(), L.in_base.size()))) return rc;
       if ((rc = upload(h, D.sym_base, L.sym_base.data(), L.sym_base.size()))) return rc;
       if ((rc = upload(h, D.out_base, L.out_base.data(), L.out_base.size()))) return rc;
+    }
+  }
+  // uniform truncation order: the kernels skip the per-mode range tests
+  h->p_uniform = true;
+  for (int i = 0; i < h->n; ++i)
+    if (h->p[i] != h->pmax) h->p_uniform = false;
+  // tabulated exponentials when they fit the budget and free memory
+  {
+    const double gb = 4.0 * (double)h->q * (double)h->n * sizeof(double2) / 1e9;
+    size_t fre = 0, tot = 0;
+    (void)hipMemGetInfo(&fre, &tot);
+    if (gb <= h->etab_budget_gb && gb * 1e9 < 0.6 * (double)fre && h->q <= 65535 &&
+        h->n <= 65535) {
+      const size_t half = (size_t)2 * h->q * h->n;
+      if (hipMalloc(&h->d_Eagg, sizeof(double2) * half) != hipSuccess ||
+          hipMalloc(&h->d_Edis, sizeof(double2) * half) != hipSuccess) {
+        (void)hipGetLastError();
+        dfree(h->d_Eagg);
+        dfree(h->d_Edis);
+      } else {
+        HIPCHK(h, ems::launch_etables(h, 0));
+      }
     }
   }
   if ((rc = ensure_ws(h, 1))) return rc;

@@ -142,6 +142,9 @@ struct ems_handle {
   double2 *d_xi = nullptr, *d_w = nullptr, *d_sp = nullptr, *d_ss = nullptr;
   double2 *d_R = nullptr;        // [q][4]
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 pmax + 1]: (-i zeta)^n, n = -pmax..pmax
+  double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
+  bool p_uniform = false;
+  double etab_budget_gb = 96.0;
   // workspaces (sized for ws_nrhs right-hand sides)
   int ws_nrhs = 0;
   int agg_chunks = 0, dis_chunks = 0;
@@ -212,6 +215,7 @@ hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
+hipError_t launch_etables(ems_handle *h, hipStream_t st);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st);
 // y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags.

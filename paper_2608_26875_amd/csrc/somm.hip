@@ -29,14 +29,14 @@ namespace ems {
 
 int pm_bucket(int pmax);
 
-template <int PM>
+template <int PM, bool UNI, bool TAB>
 __global__ __launch_bounds__(256) void somm_aggregate_kernel(
     int n, int q, int pmax, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
     const double2 *__restrict__ ss_t, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
-    int adjoint) {
+    int adjoint, const double2 *__restrict__ Etab) {
   constexpr int NM = 2 * PM + 1;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
@@ -72,18 +72,25 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
   const int m0 = c * per_chunk;
   const int m1 = min(n, m0 + per_chunk);
   const double2 *xr = x + (int64_t)r * ldx;
+  // tabulated exponentials E[wave][m][j] (forward only)
+  const double2 *Ew = TAB ? Etab + (int64_t)wave * n * q + jj : nullptr;
   for (int m = m0; m < m1; ++m) {
-    const double xm = xy[2 * m], ym = xy[2 * m + 1];
-    const int pm = p[m];
-    const double2 *cm = xr + off[m] + wave * (2 * pm + 1) + pm;
+    const int pm = UNI ? PM : p[m];
+    const double2 *cm = xr + (UNI ? (int64_t)m * 2 * (2 * PM + 1) : off[m]) + wave * (2 * pm + 1) + pm;
     double2 W = make_double2(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
       const int nn = k - PM;
-      if (nn >= -pm && nn <= pm) cfma(W, v[k], cm[nn]);
+      if (UNI || (nn >= -pm && nn <= pm)) cfma(W, v[k], cm[nn]);
     }
-    const double2 arg = make_double2(a.x * ym + bb.x * xm, a.y * ym + bb.y * xm);
-    cfma(acc, cexp(arg), W);
+    double2 E;
+    if (TAB) {
+      E = Ew[(int64_t)m * q];
+    } else {
+      const double xm = xy[2 * m], ym = xy[2 * m + 1];
+      E = cexp(make_double2(a.x * ym + bb.x * xm, a.y * ym + bb.y * xm));
+    }
+    cfma(acc, E, W);
   }
   if (j < q) agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = acc;
 }
@@ -126,14 +133,14 @@ __global__ void somm_reflect_kernel(int q, int chunks, const double2 *__restrict
   g[(int64_t)(r * 2 + 1) * q + j] = os;
 }
 
-template <int PM>
+template <int PM, bool TAB>
 __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
     int n, int q, int pmax, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ xi_t,
     const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
-    int per_chunk, int adjoint) {
+    int per_chunk, int adjoint, const double2 *__restrict__ Etab) {
   constexpr int NM = 2 * PM + 1;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
@@ -151,19 +158,26 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
   for (int k = 0; k < NM; ++k) acc[k] = make_double2(0.0, 0.0);
   const int j0 = c * per_chunk;
   const int j1 = min(q, j0 + per_chunk);
+  // tabulated exponentials E[wave][j][l] (forward only)
+  const double2 *Ew = TAB ? Etab + (int64_t)wave * q * n + ll : nullptr;
   for (int j = j0; j < j1; ++j) {
-    const double2 xi = xi_t[j];
-    const double2 s = st[j];
-    double2 a, bb;
-    if (!adjoint) {
-      a = s;
-      bb = make_double2(-xi.y, xi.x);  // i xi
+    double2 E;
+    if (TAB) {
+      E = Ew[(int64_t)j * n];
     } else {
-      a = cconj(s);
-      bb = make_double2(xi.y, xi.x);   // conj(-i xi)
+      const double2 xi = xi_t[j];
+      const double2 s = st[j];
+      double2 a, bb;
+      if (!adjoint) {
+        a = s;
+        bb = make_double2(-xi.y, xi.x);  // i xi
+      } else {
+        a = cconj(s);
+        bb = make_double2(xi.y, xi.x);   // conj(-i xi)
+      }
+      E = cexp(make_double2(a.x * yl + bb.x * xl, a.y * yl + bb.y * xl));
     }
-    const double2 arg = make_double2(a.x * yl + bb.x * xl, a.y * yl + bb.y * xl);
-    const double2 F = cmul(cexp(arg), gr[j]);
+    const double2 F = cmul(E, gr[j]);
     const double2 *Vj = Vt + (int64_t)j * ld + pmax;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
@@ -185,11 +199,17 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
   }
 }
 
+#define EMS_AGG_LAUNCH(PMV, UNIV, TABV)                                                    \
+  hipLaunchKernelGGL((somm_aggregate_kernel<PMV, UNIV, TABV>), grid, dim3(256), 0, st, h->n,  \
+                     h->q, h->pmax, h->d_xy, h->d_p, h->d_off, x, h->ncoef, h->d_xi, h->d_sp,  \
+                     h->d_ss, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, adjoint ? 1 : 0,  \
+                     h->d_Eagg)
 #define EMS_AGG_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    hipLaunchKernelGGL((somm_aggregate_kernel<PMV>), grid, dim3(256), 0, st, h->n, h->q,   \
-                       h->pmax, h->d_xy, h->d_p, h->d_off, x, h->ncoef, h->d_xi, h->d_sp,  \
-                       h->d_ss, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, adjoint ? 1 : 0); \
+    if (tab && uni) EMS_AGG_LAUNCH(PMV, true, true);                                       \
+    else if (tab) EMS_AGG_LAUNCH(PMV, false, true);                                        \
+    else if (uni) EMS_AGG_LAUNCH(PMV, true, false);                                        \
+    else EMS_AGG_LAUNCH(PMV, false, false);                                                \
     break;
 
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
@@ -197,7 +217,10 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   (void)mixed;
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
-  switch (pm_bucket(h->pmax)) {
+  const int pb = pm_bucket(h->pmax);
+  const bool tab = h->d_Eagg != nullptr && !adjoint;
+  const bool uni = h->p_uniform && pb == h->pmax;
+  switch (pb) {
     EMS_AGG_CASE(4)
     EMS_AGG_CASE(8)
     EMS_AGG_CASE(10)
@@ -216,12 +239,15 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
   return hipGetLastError();
 }
 
+#define EMS_DIS_LAUNCH(PMV, TABV)                                                          \
+  hipLaunchKernelGGL((somm_disaggregate_kernel<PMV, TABV>), grid, dim3(256), 0, st, h->n, h->q, \
+                     h->pmax, h->d_xy, h->d_p, h->d_off, h->d_xi, h->d_sp, h->d_ss, h->d_Vp,    \
+                     h->d_Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per,               \
+                     adjoint ? 1 : 0, h->d_Edis)
 #define EMS_DIS_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    hipLaunchKernelGGL((somm_disaggregate_kernel<PMV>), grid, dim3(256), 0, st, h->n, h->q, \
-                       h->pmax, h->d_xy, h->d_p, h->d_off, h->d_xi, h->d_sp, h->d_ss,       \
-                       h->d_Vp, h->d_Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, \
-                       adjoint ? 1 : 0);                                                    \
+    if (tab) EMS_DIS_LAUNCH(PMV, true);                                                    \
+    else EMS_DIS_LAUNCH(PMV, false);                                                       \
     break;
 
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
@@ -229,6 +255,7 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
   (void)mixed;
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
+  const bool tab = h->d_Edis != nullptr && !adjoint;
   switch (pm_bucket(h->pmax)) {
     EMS_DIS_CASE(4)
     EMS_DIS_CASE(8)
@@ -238,6 +265,47 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Tables of the geometry-dependent exponentials (set-up, once per geometry
+// and frequency):  Eagg[w][m][j] = e^{s_w(j) y_m - i xi_j x_m},
+// Edis[w][j][l] = e^{i xi_j x_l + s_w(j) y_l}.
+__global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
+                                const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
+                                const double2 *__restrict__ ss_t, double2 *__restrict__ E) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  const int w = blockIdx.z;
+  if (j >= q) return;
+  const double2 xi = xi_t[j];
+  const double2 s = w ? ss_t[j] : sp_t[j];
+  const double xm = xy[2 * m], ym = xy[2 * m + 1];
+  // s y - i xi x
+  E[((int64_t)w * n + m) * q + j] = cexp(make_double2(s.x * ym + xi.y * xm, s.y * ym - xi.x * xm));
+}
+
+__global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
+                                const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
+                                const double2 *__restrict__ ss_t, double2 *__restrict__ E) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int w = blockIdx.z;
+  if (l >= n) return;
+  const double2 xi = xi_t[j];
+  const double2 s = w ? ss_t[j] : sp_t[j];
+  const double xl = xy[2 * l], yl = xy[2 * l + 1];
+  // i xi x + s y
+  E[((int64_t)w * q + j) * n + l] = cexp(make_double2(s.x * yl - xi.y * xl, s.y * yl + xi.x * xl));
+}
+
+hipError_t launch_etables(ems_handle *h, hipStream_t st) {
+  hipLaunchKernelGGL(etab_agg_kernel, dim3((h->q + 255) / 256, h->n, 2), dim3(256), 0, st, h->n,
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(etab_dis_kernel, dim3((h->n + 255) / 256, h->q, 2), dim3(256), 0, st, h->n,
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis);
   return hipGetLastError();
 }
 
