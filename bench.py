@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--solve", action="store_true", help="also time a GMRES solve to 1e-9")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2)
+    ap.add_argument("--fmm-leaf", type=int, default=0, help="particles per FMM leaf (0 = library default)")
     return ap.parse_args()
 
 
@@ -134,6 +135,8 @@ def main():
     media = E.make_media(w.host, w.substrate, w.omega)
     t0 = time.perf_counter()
     op = E.Operator(w.xy, w.radius, w.p, media, bc=w.bc)
+    if args.fmm_leaf:
+        op.set_fmm(mode=0, leaf=args.fmm_leaf)
     info = op.build()
     setup_s = time.perf_counter() - t0
     x = torch.from_numpy(W.random_coeffs(w.n_coeff, 1002)).cuda()

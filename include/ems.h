@@ -178,7 +178,7 @@ int ems_reflection(const ems_media *m, double xi_re, double xi_im, double *R_out
 /* Free-space part (Section 3.2 gives the Graf translations and names the
  * FMM; the library builds a uniform-quadtree Graf FMM).
  *  mode 0: automatic (FMM when n > 1500), 1: direct sum over all pairs,
- *  2: FMM.  leaf: target particles per leaf box (0 = 20); top_boxes: the
+ *  2: FMM.  leaf: target particles per leaf box (0 = 6); top_boxes: the
  *  coarsest level kept has at most this many occupied boxes, all of whose
  *  non-adjacent pairs interact directly (0 = 64); digits: accuracy target of
  *  the expansion orders (0 = 13). */

@@ -472,7 +472,7 @@ int ems_set_fmm(ems_handle *h, const ems_fmm *f) {
   if (f->leaf < 0 || f->top_boxes < 0 || f->digits < 0 || f->digits > 15.5)
     return fail(h, EMS_ERR_ARG, "bad fmm parameters");
   h->fmm_mode = f->mode;
-  h->fmm_leaf = f->leaf > 0 ? f->leaf : 20;
+  h->fmm_leaf = f->leaf > 0 ? f->leaf : 6;
   h->fmm_top = f->top_boxes > 0 ? f->top_boxes : 64;
   h->fmm_digits = f->digits > 0 ? f->digits : 13.0;
   h->built = false;
@@ -493,7 +493,9 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if (rc) return rc;
   h->nodes = nt;
   h->q = (int)nt.xi.size();
-  const int q = h->q, ld = 2 * h->pmax + 1;
+  // power tables padded to the kernels' compile-time order (zeros beyond pmax)
+  const int pmb = ems::pm_bucket(h->pmax);
+  const int q = h->q, ld = 2 * pmb + 1;
   std::vector<double2> xi(q), w(q), sp(q), ss(q), R(4 * (size_t)q), Vp((size_t)q * ld),
       Vs((size_t)q * ld);
   const cd I(0.0, 1.0);
@@ -514,17 +516,17 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
     const cd zp = -I * (x - s1) / h->md.kp, zs = -I * (x - s2) / h->md.ks;
     cd ap = 1.0, as = 1.0, bp = 1.0, bs = 1.0;
     const cd izp = 1.0 / zp, izs = 1.0 / zs;
-    Vp[(size_t)j * ld + h->pmax] = make_double2(1.0, 0.0);
-    Vs[(size_t)j * ld + h->pmax] = make_double2(1.0, 0.0);
+    Vp[(size_t)j * ld + pmb] = make_double2(1.0, 0.0);
+    Vs[(size_t)j * ld + pmb] = make_double2(1.0, 0.0);
     for (int n = 1; n <= h->pmax; ++n) {
       ap *= zp;
       as *= zs;
       bp *= izp;
       bs *= izs;
-      Vp[(size_t)j * ld + h->pmax + n] = make_double2(ap.real(), ap.imag());
-      Vs[(size_t)j * ld + h->pmax + n] = make_double2(as.real(), as.imag());
-      Vp[(size_t)j * ld + h->pmax - n] = make_double2(bp.real(), bp.imag());
-      Vs[(size_t)j * ld + h->pmax - n] = make_double2(bs.real(), bs.imag());
+      Vp[(size_t)j * ld + pmb + n] = make_double2(ap.real(), ap.imag());
+      Vs[(size_t)j * ld + pmb + n] = make_double2(as.real(), as.imag());
+      Vp[(size_t)j * ld + pmb - n] = make_double2(bp.real(), bp.imag());
+      Vs[(size_t)j * ld + pmb - n] = make_double2(bs.real(), bs.imag());
     }
   }
   // packed S store: per particle column-major

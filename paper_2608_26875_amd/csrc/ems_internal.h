@@ -108,6 +108,8 @@ struct FmmPlan {
 };
 
 int fmm_order(double k, double side, int p, double digits);
+// compile-time order bucket of the kernels for a largest order pmax
+int pm_bucket(int pmax);
 
 }  // namespace ems
 
@@ -141,7 +143,7 @@ struct ems_handle {
   // node table on device (structure of arrays)
   double2 *d_xi = nullptr, *d_w = nullptr, *d_sp = nullptr, *d_ss = nullptr;
   double2 *d_R = nullptr;        // [q][4]
-  double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 pmax + 1]: (-i zeta)^n, n = -pmax..pmax
+  double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
   bool p_uniform = false;
   double etab_budget_gb = 96.0;
@@ -156,7 +158,7 @@ struct ems_handle {
 
   // free-space FMM
   int fmm_mode = 0;            // 0 auto, 1 direct, 2 FMM
-  int fmm_leaf = 20, fmm_top = 64;
+  int fmm_leaf = 6, fmm_top = 64;
   double fmm_digits = 13.0;
   bool fmm_on = false;
   ems::FmmPlan fmm;

@@ -29,15 +29,20 @@ namespace ems {
 
 int pm_bucket(int pmax);
 
-template <int PM, bool UNI, bool TAB>
+// MODE 0: forward with tabulated exponentials, 1: forward, exponentials
+// formed on the fly, 2: adjoint (on the fly).
+template <int PM, bool UNI, int MODE>
 __global__ __launch_bounds__(256) void somm_aggregate_kernel(
     int n, int q, int pmax, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
     const double2 *__restrict__ ss_t, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
-    int adjoint, const double2 *__restrict__ Etab) {
+    int adjoint_unused, const double2 *__restrict__ Etab) {
   constexpr int NM = 2 * PM + 1;
+  constexpr bool TAB = MODE == 0;
+  constexpr bool adjoint = MODE == 2;
+  (void)adjoint_unused;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   const int wave = blockIdx.z & 1;
@@ -46,7 +51,9 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
   const double2 *Vt = wave ? Vs_t : Vp_t;
   const double2 xi = xi_t[jj];
   const double2 s = wave ? ss_t[jj] : sp_t[jj];
-  const int ld = 2 * pmax + 1;
+  // power tables are padded to the kernel order PM (zeros beyond pmax)
+  const int ld = 2 * PM + 1;
+  (void)pmax;
   // exponent a y + b x
   double2 a, bb;
   if (!adjoint) {
@@ -60,15 +67,19 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
 #pragma unroll
   for (int k = 0; k < NM; ++k) {
     const int nn = k - PM;
-    double2 t = make_double2(0.0, 0.0);
-    if (nn >= -pmax && nn <= pmax) t = Vt[(int64_t)jj * ld + nn + pmax];
+    double2 t = Vt[(int64_t)jj * ld + k];
     if (adjoint) {
       t = cconj(t);
       if (nn & 1) t = cscale(t, -1.0);
     }
     v[k] = t;
   }
-  double2 acc = make_double2(0.0, 0.0);
+  // acc_n = sum_m E(j, m) c^m_n, then I = sum_n V[j][n] acc_n: the 2p+1
+  // accumulators are independent chains (same flop count as contracting the
+  // modes first).
+  double2 acc[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) acc[k] = make_double2(0.0, 0.0);
   const int m0 = c * per_chunk;
   const int m1 = min(n, m0 + per_chunk);
   const double2 *xr = x + (int64_t)r * ldx;
@@ -77,12 +88,6 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
   for (int m = m0; m < m1; ++m) {
     const int pm = UNI ? PM : p[m];
     const double2 *cm = xr + (UNI ? (int64_t)m * 2 * (2 * PM + 1) : off[m]) + wave * (2 * pm + 1) + pm;
-    double2 W = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < NM; ++k) {
-      const int nn = k - PM;
-      if (UNI || (nn >= -pm && nn <= pm)) cfma(W, v[k], cm[nn]);
-    }
     double2 E;
     if (TAB) {
       E = Ew[(int64_t)m * q];
@@ -90,9 +95,16 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
       const double xm = xy[2 * m], ym = xy[2 * m + 1];
       E = cexp(make_double2(a.x * ym + bb.x * xm, a.y * ym + bb.y * xm));
     }
-    cfma(acc, E, W);
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      const int nn = k - PM;
+      if (UNI || (nn >= -pm && nn <= pm)) cfma(acc[k], E, cm[nn]);
+    }
   }
-  if (j < q) agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = acc;
+  double2 res = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < NM; ++k) cfma(res, v[k], acc[k]);
+  if (j < q) agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = res;
 }
 
 __global__ void somm_reflect_kernel(int q, int chunks, const double2 *__restrict__ agg,
@@ -133,15 +145,18 @@ __global__ void somm_reflect_kernel(int q, int chunks, const double2 *__restrict
   g[(int64_t)(r * 2 + 1) * q + j] = os;
 }
 
-template <int PM, bool TAB>
+template <int PM, int MODE>
 __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
     int n, int q, int pmax, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ xi_t,
     const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
-    int per_chunk, int adjoint, const double2 *__restrict__ Etab) {
+    int per_chunk, int adjoint_unused, const double2 *__restrict__ Etab) {
   constexpr int NM = 2 * PM + 1;
+  constexpr bool TAB = MODE == 0;
+  constexpr bool adjoint = MODE == 2;
+  (void)adjoint_unused;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   const int wave = blockIdx.z & 1;
@@ -149,7 +164,8 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
   const int ll = l < n ? l : n - 1;
   const double xl = xy[2 * ll], yl = xy[2 * ll + 1];
   const int pl = p[ll];
-  const int ld = 2 * pmax + 1;
+  const int ld = 2 * PM + 1;
+  (void)pmax;
   const double2 *Vt = wave ? Vs_t : Vp_t;
   const double2 *st = wave ? ss_t : sp_t;
   const double2 *gr = g + (int64_t)(r * 2 + wave) * q;
@@ -178,15 +194,12 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
       E = cexp(make_double2(a.x * yl + bb.x * xl, a.y * yl + bb.y * xl));
     }
     const double2 F = cmul(E, gr[j]);
-    const double2 *Vj = Vt + (int64_t)j * ld + pmax;
+    const double2 *Vj = Vt + (int64_t)j * ld;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
-      const int nn = k - PM;
-      if (nn >= -pmax && nn <= pmax) {
-        double2 u = Vj[nn];
-        if (adjoint) u = cconj(u);
-        cfma(acc[k], F, u);
-      }
+      double2 u = Vj[k];
+      if (adjoint) u = cconj(u);
+      cfma(acc[k], F, u);
     }
   }
   if (l < n) {
@@ -206,10 +219,11 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
                      h->d_Eagg)
 #define EMS_AGG_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    if (tab && uni) EMS_AGG_LAUNCH(PMV, true, true);                                       \
-    else if (tab) EMS_AGG_LAUNCH(PMV, false, true);                                        \
-    else if (uni) EMS_AGG_LAUNCH(PMV, true, false);                                        \
-    else EMS_AGG_LAUNCH(PMV, false, false);                                                \
+    if (mode == 0 && uni) EMS_AGG_LAUNCH(PMV, true, 0);                                    \
+    else if (mode == 0) EMS_AGG_LAUNCH(PMV, false, 0);                                     \
+    else if (mode == 1 && uni) EMS_AGG_LAUNCH(PMV, true, 1);                               \
+    else if (mode == 1) EMS_AGG_LAUNCH(PMV, false, 1);                                     \
+    else EMS_AGG_LAUNCH(PMV, false, 2);                                                    \
     break;
 
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
@@ -218,7 +232,7 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int pb = pm_bucket(h->pmax);
-  const bool tab = h->d_Eagg != nullptr && !adjoint;
+  const int mode = adjoint ? 2 : (h->d_Eagg != nullptr ? 0 : 1);
   const bool uni = h->p_uniform && pb == h->pmax;
   switch (pb) {
     EMS_AGG_CASE(4)
@@ -246,8 +260,9 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
                      adjoint ? 1 : 0, h->d_Edis)
 #define EMS_DIS_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    if (tab) EMS_DIS_LAUNCH(PMV, true);                                                    \
-    else EMS_DIS_LAUNCH(PMV, false);                                                       \
+    if (mode == 0) EMS_DIS_LAUNCH(PMV, 0);                                                 \
+    else if (mode == 1) EMS_DIS_LAUNCH(PMV, 1);                                            \
+    else EMS_DIS_LAUNCH(PMV, 2);                                                           \
     break;
 
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
@@ -255,7 +270,7 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
   (void)mixed;
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
-  const bool tab = h->d_Edis != nullptr && !adjoint;
+  const int mode = adjoint ? 2 : (h->d_Edis != nullptr ? 0 : 1);
   switch (pm_bucket(h->pmax)) {
     EMS_DIS_CASE(4)
     EMS_DIS_CASE(8)
