@@ -293,6 +293,17 @@ class Operator:
                                       _stream_ptr(stream)))
         return out
 
+    def scattered_field(self, gamma, pts, stream=None):
+        """Scattered displacement [nrhs, npts, 2] complex128 at host points pts [npts, 2]."""
+        import torch
+        nrhs = self._vec_check(gamma)
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+        out = torch.empty((nrhs, p.shape[0], 2), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_eval_scattered(self.h, ctypes.c_void_p(gamma.data_ptr()), nrhs,
+                                            int(p.shape[0]), ctypes.c_void_p(p.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-6,
               stream=None):
         import torch

@@ -985,11 +985,39 @@ extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
 
 extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
                                   const double *pts, void *u, ems_stream_t stream) {
-  (void)gamma;
-  (void)nrhs;
-  (void)npts;
-  (void)pts;
-  (void)u;
-  (void)stream;
-  return fail(h, EMS_ERR_UNIMPLEMENTED, "ems_eval_scattered is not built yet");
+  if (!h || !gamma || !pts || !u || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad field arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  // receivers must lie in the host layer and outside every enclosing disk
+  std::vector<double> hp(2 * (size_t)npts);
+  HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  for (int i = 0; i < npts; ++i) {
+    const double x = hp[2 * i], y = hp[2 * i + 1];
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(h, EMS_ERR_NUMERIC, "non-finite receiver");
+    if (!(y < 0)) return fail(h, EMS_ERR_GEOMETRY, "receiver not in the host layer (y < 0)");
+    for (int m = 0; m < h->n; ++m) {
+      const double dx = x - h->xy[2 * m], dy = y - h->xy[2 * m + 1];
+      if (dx * dx + dy * dy <= h->R[m] * h->R[m])
+        return fail(h, EMS_ERR_GEOMETRY,
+                    "receiver " + std::to_string(i) + " inside the enclosing disk of particle " +
+                        std::to_string(m));
+    }
+  }
+  int rc = ensure_ws(h, nrhs);
+  if (rc) return rc;
+  const double2 *g = (const double2 *)gamma;
+  double2 *uo = (double2 *)u;
+  {
+    ems::ProfScope ps(h, "field_direct", st);
+    HIPCHK(h, ems::launch_field_direct(h, g, nrhs, npts, pts, uo, st));
+  }
+  HIPCHK(h, ems::launch_somm_aggregate(h, g, nrhs, false, false, st));
+  HIPCHK(h, ems::launch_somm_reflect(h, nrhs, false, st));
+  {
+    ems::ProfScope ps(h, "field_refl", st);
+    HIPCHK(h, ems::launch_field_refl(h, nrhs, npts, pts, uo, st));
+  }
+  return EMS_OK;
 }

@@ -1,0 +1,145 @@
+// Scattered displacement at host points (Section 4, coupled representation):
+//   u(x) = sum_m sum_n alpha^m_n grad v_n^{kp}(x - x_m) + beta^m_n grad^perp v_n^{ks}(x - x_m)
+//          + grad phi_R + grad^perp psi_R,
+// v_n^k = H_n(k r) e^{i n theta}, d_x v_n = (k/2)(v_{n-1} - v_{n+1}),
+// d_y v_n = (i k/2)(v_{n-1} + v_{n+1}); phi_R = sum_j e^{i xi_j x + s_p y} RP_j and
+// psi_R likewise with RS (the reflected amplitudes of the aggregate/reflect
+// stages, quadrature weights included), so grad -> (i xi, s_p) and
+// grad^perp -> (-s_s, i xi).
+#include "dev.h"
+#include "ems_internal.h"
+
+namespace ems {
+
+// lane = receiver point; every particle is visited (direct sum).
+template <int PM>
+__global__ __launch_bounds__(256) void field_direct_kernel(
+    int n, int npts, const double *__restrict__ xy, const int *__restrict__ p,
+    const int64_t *__restrict__ off, const double2 *__restrict__ gam, int64_t ldg,
+    const double *__restrict__ pts, double2 *__restrict__ u, double kp, double ks) {
+  constexpr int L = PM + 1;  // orders -L..L of v_k are needed
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int ipc = ip < npts ? ip : npts - 1;
+  const double px = pts[2 * ipc], py = pts[2 * ipc + 1];
+  const double2 *g = gam + (int64_t)r * ldg;
+  double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
+  for (int m = 0; m < n; ++m) {
+    const double dx = px - xy[2 * m], dy = py - xy[2 * m + 1];
+    const double rr = sqrt(dx * dx + dy * dy);
+    const double th = atan2(dy, dx);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double2 e1 = make_double2(cs, sn);  // e^{i theta}
+    const int pm = p[m];
+    const double2 *al = g + off[m] + pm;            // alpha_n at al[n]
+    const double2 *be = g + off[m] + 2 * pm + 1 + pm;  // beta_n at be[n]
+    for (int w = 0; w < 2; ++w) {
+      const double k = w ? ks : kp;
+      const double z = k * rr;
+      // v_k for k = 0..L: H_k e^{i k theta}; v_{-k} = (-1)^k H_k e^{-i k theta}
+      double2 vp[L + 1], vn[L + 1];
+      double2 hm = make_double2(j0(z), y0(z)), h = make_double2(j1(z), y1(z));
+      vp[0] = hm;
+      vn[0] = hm;
+      double2 ph = e1;
+      vp[1] = cmul(h, ph);
+      vn[1] = cscale(cmul(h, cconj(ph)), -1.0);
+      const double iz = 2.0 / z;
+#pragma unroll
+      for (int kk = 2; kk <= L; ++kk) {
+        const double2 hn = csub(cscale(h, (kk - 1) * iz), hm);
+        hm = h;
+        h = hn;
+        ph = cmul(ph, e1);
+        vp[kk] = cmul(h, ph);
+        vn[kk] = cscale(cmul(h, cconj(ph)), (kk & 1) ? -1.0 : 1.0);
+      }
+      // sum_n c_n (v_{n-1} -+ v_{n+1})
+      double2 dif = make_double2(0.0, 0.0), sum = make_double2(0.0, 0.0);
+      const double2 *c = w ? be : al;
+#pragma unroll
+      for (int nn = -PM; nn <= PM; ++nn) {
+        if (nn < -pm || nn > pm) continue;
+        const int a1 = nn - 1, a2 = nn + 1;
+        const double2 v1 = a1 >= 0 ? vp[a1] : vn[-a1];
+        const double2 v2 = a2 >= 0 ? vp[a2] : vn[-a2];
+        const double2 cn = c[nn];
+        cfma(dif, cn, csub(v1, v2));
+        cfma(sum, cn, cadd(v1, v2));
+      }
+      // d_x part (k/2) dif, d_y part (i k/2) sum
+      const double2 gx = cscale(dif, 0.5 * k);
+      const double2 gy = make_double2(-0.5 * k * sum.y, 0.5 * k * sum.x);
+      if (w == 0) {
+        ux = cadd(ux, gx);
+        uy = cadd(uy, gy);
+      } else {  // grad^perp = (-d_y, d_x)
+        ux = csub(ux, gy);
+        uy = cadd(uy, gx);
+      }
+    }
+  }
+  if (ip < npts) {
+    double2 *o = u + ((int64_t)r * npts + ip) * 2;
+    o[0] = ux;
+    o[1] = uy;
+  }
+}
+
+// lane = receiver; sum over the Sommerfeld nodes of the reflected potentials.
+__global__ __launch_bounds__(256) void field_refl_kernel(
+    int q, int npts, const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
+    const double2 *__restrict__ ss_t, const double2 *__restrict__ g, const double *__restrict__ pts,
+    double2 *__restrict__ u) {
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (ip >= npts) return;
+  const double px = pts[2 * ip], py = pts[2 * ip + 1];
+  const double2 *RP = g + (int64_t)(r * 2 + 0) * q;
+  const double2 *RS = g + (int64_t)(r * 2 + 1) * q;
+  double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
+  for (int j = 0; j < q; ++j) {
+    const double2 xi = xi_t[j], sp = sp_t[j], ss = ss_t[j];
+    const double2 ixi = make_double2(-xi.y, xi.x);
+    // e^{i xi x + s y}
+    const double2 ep = cmul(cexp(make_double2(-xi.y * px + sp.x * py, xi.x * px + sp.y * py)), RP[j]);
+    const double2 es = cmul(cexp(make_double2(-xi.y * px + ss.x * py, xi.x * px + ss.y * py)), RS[j]);
+    ux = cadd(ux, csub(cmul(ixi, ep), cmul(ss, es)));
+    uy = cadd(uy, cadd(cmul(sp, ep), cmul(ixi, es)));
+  }
+  double2 *o = u + ((int64_t)r * npts + ip) * 2;
+  o[0] = cadd(o[0], ux);
+  o[1] = cadd(o[1], uy);
+}
+
+#define EMS_FIELD_CASE(PMV)                                                                   \
+  case PMV:                                                                                   \
+    hipLaunchKernelGGL((field_direct_kernel<PMV>), grid, dim3(256), 0, st, h->n, npts, h->d_xy, \
+                       h->d_p, h->d_off, gamma, h->ncoef, pts, u, h->md.kp, h->md.ks);       \
+    break;
+
+hipError_t launch_field_direct(const ems_handle *h, const double2 *gamma, int nrhs, int npts,
+                               const double *pts, double2 *u, hipStream_t st) {
+  dim3 grid((npts + 255) / 256, nrhs);
+  switch (pm_bucket(h->pmax)) {
+    EMS_FIELD_CASE(4)
+    EMS_FIELD_CASE(8)
+    EMS_FIELD_CASE(10)
+    EMS_FIELD_CASE(12)
+    EMS_FIELD_CASE(15)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_field_refl(const ems_handle *h, int nrhs, int npts, const double *pts,
+                             double2 *u, hipStream_t st) {
+  dim3 grid((npts + 255) / 256, nrhs);
+  hipLaunchKernelGGL(field_refl_kernel, grid, dim3(256), 0, st, h->q, npts, h->d_xi, h->d_sp,
+                     h->d_ss, h->d_refl, pts, u);
+  return hipGetLastError();
+}
+
+}  // namespace ems

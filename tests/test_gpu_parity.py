@@ -180,3 +180,36 @@ def test_geometry_and_argument_errors():
     with pytest.raises(E.EmsError) as ei:
         op.build()
     assert ei.value.code == -2
+
+
+def test_scattered_field_parity():
+    """Scattered displacement (direct outgoing fields + reflected Sommerfeld
+    field) at receivers between the interface and the particles and among
+    them, against the oracle."""
+    from oracle import field
+    w = W.small_cloud(12, seed=6, p=6, omega=4.0, width=14.0, depth=(1.0, 4.0))
+    m = oracle_media(w)
+    op = product_operator(w)
+    op.build()
+    g = W.random_coeffs(w.n_coeff, 77, nrhs=2)
+    pts = np.stack([np.linspace(-2.0, 16.0, 23), np.full(23, -0.3)], 1)
+    pts = np.concatenate([pts, np.array([[7.1, -6.5], [3.3, -5.9]])])
+    far = np.min(np.hypot(pts[:, None, 0] - w.xy[None, :, 0], pts[:, None, 1] - w.xy[None, :, 1])
+                 - w.radius[None, :], axis=1)
+    pts = pts[far > 0.05]
+    u = to_np(op.scattered_field(to_gpu(g), pts))
+    for r in range(2):
+        ref = field.scattered(w, m, g[r], pts, tol=1e-13)
+        e = rel(u[r], ref)
+        print("field rel err", e, flush=True)
+        assert e <= 1e-11
+
+
+def test_scattered_field_rejects_receiver_inside_disk():
+    w = W.small_cloud(3, seed=6, p=3, omega=4.0, width=8.0, depth=(1.0, 4.0))
+    op = product_operator(w)
+    op.build()
+    g = to_gpu(W.random_coeffs(w.n_coeff, 1))
+    with pytest.raises(E.EmsError) as ei:
+        op.scattered_field(g, w.xy[:1] + 0.01)
+    assert ei.value.code == -2
