@@ -53,19 +53,25 @@ def workload(name):
     return W.c2_cloud()
 
 
-def algorithmic_flops(kernel, w, info):
-    """Flops one launch must do by the method's definition (complex MAC = 8)."""
+def section8d_flops(kernel, w, info):
+    """Algorithmic flops of one launch by the scope table's per-unit figures
+    (complex multiply-add = 8): a cross-check of the library's own count."""
     import numpy as np
-    modes = np.sum(2 * w.p.astype(np.int64) + 1)           # per wave type
-    if kernel == "graf_direct":
-        # every ordered pair (m, l), both wave types, (2p_m+1)(2p_l+1) MACs each
-        s = float(np.sum(2 * w.p + 1))
-        return 8.0 * 2.0 * (s * s - float(np.sum((2 * w.p + 1) ** 2)))
     if kernel in ("somm_aggregate", "somm_disaggregate"):
-        return 8.0 * info["q"] * 2.0 * float(modes)
+        # one complex MAC per (node, coefficient)
+        return 8.0 * info["q"] * float(w.n_coeff)
     if kernel == "combine_s_apply":
         return 8.0 * float(np.sum((4 * w.p.astype(np.int64) + 2) ** 2))
-    return 0.0
+    return None
+
+
+def kernel_unit(kernel, mixed):
+    """(bound, peak FLOP/s) of the unit a kernel runs on."""
+    if kernel in ("somm_aggregate", "somm_disaggregate"):
+        return "mfma", (PEAK_FP32 if mixed else PEAK_FP64)      # 16x16x4 MFMA
+    if kernel.startswith("graf") and mixed:
+        return "alu", PEAK_FP32
+    return "alu", PEAK_FP64
 
 
 def source_hash(*names):
@@ -193,15 +199,28 @@ def main():
     op.profile(False)
     ms = e0.elapsed_time(e1) / args.steps
     kt = op.profile_read()
-    per_kernel = {k: {"launches": v[0], "avg_ms": v[1] / max(v[0], 1)} for k, v in kt.items()}
+    mixed = args.precision == "mixed"
+    per_kernel = {}
+    for k, (nl, tot_ms, fl) in kt.items():
+        bound, peak = kernel_unit(k, mixed)
+        d = {"launches": nl, "avg_ms": tot_ms / max(nl, 1)}
+        if fl > 0:
+            d["flops_per_launch"] = fl / nl
+            d["tflops"] = fl / (tot_ms * 1e-3) / 1e12
+            d["frac_of_peak"] = d["tflops"] * 1e12 / peak
+        per_kernel[k] = d
     dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
-    dom_avg_s = kt[dom][1] / kt[dom][0] / 1e3
-    fl = algorithmic_flops(dom, w, info)
-    peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    nl, tot_ms, fl = kt[dom]
+    dom_avg_s = tot_ms / nl / 1e3
+    fl_launch = fl / nl
+    check = section8d_flops(dom, w, info)
+    if check is not None and abs(check - fl_launch) > 1e-9 * check:
+        raise SystemExit(f"flop count mismatch for {dom}: library {fl_launch} vs {check}")
+    bound, peak = kernel_unit(dom, mixed)
     traffic = traffic_from_profiles(dom, w.name)
-    roof = {"bound": "alu", "achieved": fl / dom_avg_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": fl / dom_avg_s / peak, "traffic": traffic, "kernel": dom,
-            "flops_per_launch": fl}
+    roof = {"bound": bound, "achieved": fl_launch / dom_avg_s / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": fl_launch / dom_avg_s / peak, "traffic": traffic,
+            "kernel": dom, "flops_per_launch": fl_launch}
     out = {
         "metric": "operator applies/s & GMRES solve s at N=20k 2D, FP64 vs mixed @1e-9",
         "value": 1e3 / ms, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,

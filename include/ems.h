@@ -219,9 +219,20 @@ int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void 
 
 /* GMRES on the operator (Sections 3.2 and 4.2): x0 = 0, nrhs independent
  * systems advanced in lock-step.  b, x device memory [nrhs][n_coeff].
- * Returns EMS_NOT_CONVERGED when maxit is reached.  Synchronous. */
+ * precision 0: every apply in FP64.  precision 1 (mixed): iterative
+ * refinement, i.e. an FP64 outer residual b - A x and update x += d, with d
+ * from an inner GMRES to inner_tol (default 1e-5) whose applies run the
+ * contractions in FP32 (EMS_MIXED); tol is met on the FP64 residual.
+ * Returns EMS_NOT_CONVERGED when maxit (total inner iterations) is reached,
+ * EMS_ERR_ARG for tol <= 0, maxit <= 0 or another precision.  Synchronous. */
 int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_solver_opts *o,
               ems_solve_info *info, ems_stream_t stream);
+
+/* The same solver on the conjugate-transpose operator A^H (the adjoint
+ * system of a misfit gradient: A^H lambda = (d u / d gamma)^H r).  Same
+ * arguments, options and return codes as ems_solve. */
+int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
+                      const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream);
 
 /* Scattered displacement at npts host points (Section 4, coupled
  * representation: outgoing particle fields plus the reflected Sommerfeld
@@ -234,11 +245,15 @@ int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t n
  * every kernel the library queues.  ems_profile(h, 1) clears and starts
  * recording, ems_profile(h, 0) stops.  ems_profile_read synchronizes on the
  * recorded events and fills up to cap entries (one per kernel name) with the
- * launch count and total milliseconds; *count receives the number of names. */
+ * launch count, total milliseconds and the algorithmic floating-point
+ * operations of those launches (a complex multiply-add counts 8; taken from
+ * the build's own plan: pair lists, FMM task lists, node count; 0 where no
+ * count is defined); *count receives the number of names. */
 typedef struct {
   char name[40];
   int32_t launches;
   double total_ms;
+  double flops;
 } ems_kernel_time;
 
 int ems_profile(ems_handle *h, int32_t enable);

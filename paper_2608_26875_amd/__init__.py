@@ -71,7 +71,7 @@ class Fmm(ctypes.Structure):
 
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class BuildInfo(ctypes.Structure):
@@ -103,6 +103,8 @@ def _load():
         "ems_apply_adjoint": ([P, P, P, I32, I32, P], I32),
         "ems_incident": ([P, ctypes.POINTER(PlaneWave), I32, P, P], I32),
         "ems_solve": ([P, P, P, I32, ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveInfo), P], I32),
+        "ems_solve_adjoint": ([P, P, P, I32, ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveInfo),
+                               P], I32),
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
                                   ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
@@ -122,6 +124,7 @@ _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
+            "ems_solve_adjoint",
             "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
@@ -304,15 +307,17 @@ class Operator:
                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
-    def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-6,
-              stream=None):
+    def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-5,
+              stream=None, adjoint=False):
+        """GMRES on A (or A^H with adjoint=True); precision 1 = mixed iterative refinement."""
         import torch
         nrhs = self._vec_check(b)
         x = torch.empty_like(b)
         o = SolverOpts(float(tol), int(restart), int(maxit), int(precision), float(inner_tol))
         info = SolveInfo()
-        rc = _lib.ems_solve(self.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                            nrhs, ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+        fn = _lib.ems_solve_adjoint if adjoint else _lib.ems_solve
+        rc = fn(self.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                nrhs, ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
         if rc < 0:
             self._check(rc)
         return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
@@ -321,11 +326,13 @@ class Operator:
         self._check(_lib.ems_profile(self.h, 1 if enable else 0))
 
     def profile_read(self) -> dict:
-        """{kernel name: (launches, total_ms)} from the HIP events recorded so far."""
+        """{kernel name: (launches, total_ms, algorithmic flops)} from the HIP
+        events recorded so far (flops summed over those launches)."""
         arr = (KernelTime * 64)()
         cnt = ctypes.c_int32(0)
         self._check(_lib.ems_profile_read(self.h, arr, 64, ctypes.byref(cnt)))
-        return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms) for k in range(cnt.value)}
+        return {arr[k].name.decode(): (arr[k].launches, arr[k].total_ms, arr[k].flops)
+                for k in range(cnt.value)}
 
     def _check(self, rc):
         if rc < 0:

@@ -66,6 +66,11 @@ void free_device(ems_handle *h) {
   dfree(h->d_Vs);
   dfree(h->d_Eagg);
   dfree(h->d_Edis);
+  dfree(h->d_Eagg32);
+  dfree(h->d_Edis32);
+  dfree(h->d_irR);
+  dfree(h->d_irD);
+  h->ir_bytes = 0;
   dfree(h->d_agg);
   dfree(h->d_refl);
   dfree(h->d_dis);
@@ -206,17 +211,17 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
   if (adjoint && (parts & EMS_PART_S)) {
     rc = ensure_tmp(h, sizeof(double2) * (size_t)nrhs * h->ncoef);
     if (rc) return rc;
-    ems::ProfScope ps(h, "s_apply_adjoint", st);
+    ems::ProfScope ps(h, "s_apply_adjoint", st, h->flops_s * nrhs);
     HIPCHK(h, ems::launch_s_apply(h, x, h->d_tmp, nrhs, true, st));
     src = h->d_tmp;
   }
   if (parts & EMS_PART_FREE) {
     if (!h->fmm_on) {
-      ems::ProfScope ps(h, "graf_direct", st);
+      ems::ProfScope ps(h, "graf_direct", st, h->flops_graf * nrhs);
       HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
     } else if (!adjoint) {
       {
-        ems::ProfScope ps(h, "graf_near", st);
+        ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
         HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, false, mixed, st));
       }
       HIPCHK(h, ems::launch_fmm(h, src, h->d_free, nrhs, st));
@@ -232,7 +237,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
       }
       HIPCHK(h, ems::launch_conj_flip(h, src, h->d_adj1, nrhs, st));
       {
-        ems::ProfScope ps(h, "graf_near", st);
+        ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
         HIPCHK(h, ems::launch_graf_direct(h, h->d_adj1, h->d_adj2, nrhs, false, mixed, st));
       }
       HIPCHK(h, ems::launch_fmm(h, h->d_adj1, h->d_adj2, nrhs, st));
@@ -240,8 +245,10 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
     }
   }
   if (parts & EMS_PART_REFL) {
+    // one complex multiply-add per (node, coefficient) in each contraction
+    const double fc = 8.0 * (double)h->q * (double)h->ncoef * nrhs;
     {
-      ems::ProfScope ps(h, "somm_aggregate", st);
+      ems::ProfScope ps(h, "somm_aggregate", st, fc);
       HIPCHK(h, ems::launch_somm_aggregate(h, src, nrhs, adjoint, mixed, st));
     }
     {
@@ -249,13 +256,13 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
       HIPCHK(h, ems::launch_somm_reflect(h, nrhs, adjoint, st));
     }
     {
-      ems::ProfScope ps(h, "somm_disaggregate", st);
+      ems::ProfScope ps(h, "somm_disaggregate", st, fc);
       HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, adjoint, mixed, st));
     }
   }
   int cflags = parts;
   if (adjoint) cflags &= ~EMS_PART_S;
-  ems::ProfScope ps(h, "combine_s_apply", st);
+  ems::ProfScope ps(h, "combine_s_apply", st, (cflags & EMS_PART_S) ? h->flops_s * nrhs : 0.0);
   HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, st));
   return EMS_OK;
 }
@@ -294,7 +301,7 @@ int ems_profile_read(ems_handle *h, ems_kernel_time *out, int32_t cap, int32_t *
   if (!h || !count || (cap > 0 && !out)) return EMS_ERR_ARG;
   std::vector<std::string> names;
   std::vector<int> launches;
-  std::vector<double> ms;
+  std::vector<double> ms, fl;
   for (auto &r : h->prof_recs) {
     HIPCHK(h, hipEventSynchronize(r.b));
     float t = 0.f;
@@ -306,9 +313,11 @@ int ems_profile_read(ems_handle *h, ems_kernel_time *out, int32_t cap, int32_t *
       names.push_back(r.name);
       launches.push_back(0);
       ms.push_back(0.0);
+      fl.push_back(0.0);
     }
     launches[k] += 1;
     ms[k] += t;
+    fl[k] += r.flops;
   }
   *count = (int32_t)names.size();
   for (int k = 0; k < (int)names.size() && k < cap; ++k) {
@@ -316,6 +325,7 @@ int ems_profile_read(ems_handle *h, ems_kernel_time *out, int32_t cap, int32_t *
     std::strncpy(out[k].name, names[k].c_str(), sizeof(out[k].name) - 1);
     out[k].launches = launches[k];
     out[k].total_ms = ms[k];
+    out[k].flops = fl[k];
   }
   return EMS_OK;
 }
@@ -544,10 +554,28 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   // free-space part: direct sum or FMM (host plan, bounds-checked)
   h->fmm_on = h->fmm_mode == 2 || (h->fmm_mode == 0 && h->n > 1500);
   h->n_pairs = (int64_t)h->n * (h->n - 1);
+  {
+    // algorithmic work: per ordered pair both wave types, (2p_m+1)(2p_l+1)
+    // complex multiply-adds each; S blocks (4p+2)^2 each
+    double s1 = 0.0, s2 = 0.0;
+    h->flops_s = 0.0;
+    for (int m = 0; m < h->n; ++m) {
+      const double k = 2.0 * h->p[m] + 1.0;
+      s1 += k;
+      s2 += k * k;
+      h->flops_s += 8.0 * (2.0 * k) * (2.0 * k);
+    }
+    h->flops_graf = 16.0 * (s1 * s1 - s2);
+  }
   if (h->fmm_on) {
     rc = ems::build_fmm(h, h->fmm, h->err);
     if (rc) return rc;
     h->n_pairs = (int64_t)h->fmm.nbr_idx.size();
+    double f = 0.0;
+    for (int m = 0; m < h->n; ++m)
+      for (int t = h->fmm.nbr_ptr[m]; t < h->fmm.nbr_ptr[m + 1]; ++t)
+        f += 16.0 * (2.0 * h->p[m] + 1.0) * (2.0 * h->p[h->fmm.nbr_idx[t]] + 1.0);
+    h->flops_graf = f;
   }
   if (h->device < 0) return fail(h, EMS_ERR_HIP, "no HIP device (host set-up completed)");
   if ((rc = upload(h, h->d_xy, h->xy.data(), h->xy.size()))) return rc;
@@ -608,6 +636,14 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
         dfree(h->d_Eagg);
         dfree(h->d_Edis);
       } else {
+        // complex64 copies for the mixed form when they fit as well
+        if (1.5 * gb <= h->etab_budget_gb && 1.5 * gb * 1e9 < 0.6 * (double)fre &&
+            (hipMalloc(&h->d_Eagg32, sizeof(float2) * half) != hipSuccess ||
+             hipMalloc(&h->d_Edis32, sizeof(float2) * half) != hipSuccess)) {
+          (void)hipGetLastError();
+          dfree(h->d_Eagg32);
+          dfree(h->d_Edis32);
+        }
         HIPCHK(h, ems::launch_etables(h, 0));
       }
     }
@@ -875,11 +911,58 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
 
 }  // namespace
 
-extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
-                         const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream) {
+namespace {
+
+// Euclidean norms of nrhs stacked vectors (device) into host memory.
+int norms(ems_handle *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t st) {
+  int rc = ensure_red(h, sizeof(double) * 1024);
+  if (rc) return rc;
+  double *d_nrm = reinterpret_cast<double *>(h->d_red);
+  double *scratch = d_nrm + 8;
+  out.assign(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    HIPCHK(h, ems::launch_norm2(v + (size_t)r * h->ncoef, h->ncoef, d_nrm, scratch, st));
+    HIPCHK(h, hipMemcpyAsync(&out[r], d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+  }
+  return EMS_OK;
+}
+
+// R = b - A x for nrhs systems.
+template <typename Op>
+int residual(ems_handle *h, Op op, const double2 *x, const double2 *b, double2 *R, int nrhs,
+             hipStream_t st) {
+  int rc = op(x, R);
+  if (rc) return rc;
+  for (int r = 0; r < nrhs; ++r) {
+    const size_t o = (size_t)r * h->ncoef;
+    HIPCHK(h, ems::launch_scale(R + o, h->ncoef, -1.0, st));
+    HIPCHK(h, ems::launch_axpy(R + o, b + o, h->ncoef, 1.0, st));
+  }
+  return EMS_OK;
+}
+
+// Buffers of the mixed-precision refinement (residual and correction).
+int ensure_ir(ems_handle *h, int nrhs) {
+  const size_t bytes = sizeof(double2) * (size_t)h->ncoef * nrhs;
+  if (h->ir_bytes >= bytes) return EMS_OK;
+  dfree(h->d_irR);
+  dfree(h->d_irD);
+  h->ir_bytes = 0;
+  HIPCHK(h, hipMalloc(&h->d_irR, bytes));
+  HIPCHK(h, hipMalloc(&h->d_irD, bytes));
+  h->ir_bytes = bytes;
+  return EMS_OK;
+}
+
+// GMRES on A (adjoint = false) or A^H, FP64 or mixed (FP32 contractions in an
+// inner GMRES on the residual equation, FP64 outer residual and update).
+int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_solver_opts *o,
+               ems_solve_info *info, ems_stream_t stream, bool adjoint) {
   if (!h || !b || !x || !o || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad solve arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   if (!(o->tol > 0) || o->maxit <= 0) return fail(h, EMS_ERR_ARG, "need tol > 0 and maxit > 0");
+  if (o->precision != 0 && o->precision != 1) return fail(h, EMS_ERR_ARG, "precision must be 0 or 1");
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vec = (size_t)h->ncoef;
@@ -889,72 +972,32 @@ extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
   const int restart = o->restart > 0 ? o->restart : 200;
   int iters = 0, outer = 1;
   double relres = 0;
-  std::vector<double> bn;
   int rc;
-  // The operator buffer passed to GMRES must not alias its internal W; the
-  // apply writes into y = W, reads x = the basis vector (distinct buffers).
+  // the operator never aliases GMRES's internal buffers: it reads a basis
+  // vector or the iterate and writes the work vector
   auto op64 = [&](const double2 *in, double2 *out) {
-    return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL, false, st);
+    return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL, adjoint, st);
+  };
+  auto op32 = [&](const double2 *in, double2 *out) {
+    return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL | EMS_MIXED, adjoint, st);
   };
   if (o->precision == 0) {
+    std::vector<double> bn;
     rc = gmres_run(h, op64, B, X, nrhs, o->tol, restart, o->maxit, true, st, iters, relres, bn);
     if (rc) return rc;
   } else {
-    // Mixed form: inner GMRES with FP32 contractions on the residual
-    // equation, outer FP64 residual and update (iterative refinement).
-    double2 *R = nullptr, *D = nullptr;
-    HIPCHK(h, hipMalloc(&R, sizeof(double2) * vec * nrhs));
-    HIPCHK(h, hipMalloc(&D, sizeof(double2) * vec * nrhs));
-    auto op32 = [&](const double2 *in, double2 *out) {
-      return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL | EMS_MIXED, false, st);
-    };
-    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-6;
+    if ((rc = ensure_ir(h, nrhs))) return rc;
+    double2 *R = h->d_irR, *D = h->d_irD;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    std::vector<double> bn, rn;
+    if ((rc = norms(h, B, nrhs, bn, st))) return rc;
     outer = 0;
-    rc = EMS_OK;
     while (true) {
-      // R = b - A64 x
-      rc = op64(X, R);
-      if (rc) break;
+      if ((rc = residual(h, op64, X, B, R, nrhs, st))) return rc;
+      if ((rc = norms(h, R, nrhs, rn, st))) return rc;
       relres = 0;
-      std::vector<double> nb(nrhs);
-      for (int r = 0; r < nrhs; ++r) {
-        ems::launch_scale(R + r * vec, h->ncoef, -1.0, st);
-        ems::launch_axpy(R + r * vec, B + r * vec, h->ncoef, 1.0, st);
-      }
-      if (bn.empty()) {
-        bn.resize(nrhs);
-        double *dn = nullptr;
-        (void)hipMalloc(&dn, sizeof(double) * 8);
-        double *scr = nullptr;
-        (void)hipMalloc(&scr, sizeof(double2) * 1024);
-        for (int r = 0; r < nrhs; ++r) {
-          ems::launch_norm2(B + r * vec, h->ncoef, dn, scr, st);
-          (void)hipMemcpyAsync(&bn[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
-          (void)hipStreamSynchronize(st);
-        }
-        double *dd = nullptr;
-        (void)dd;
-        for (int r = 0; r < nrhs; ++r) {
-          ems::launch_norm2(R + r * vec, h->ncoef, dn, scr, st);
-          (void)hipMemcpyAsync(&nb[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
-          (void)hipStreamSynchronize(st);
-        }
-        (void)hipFree(dn);
-        (void)hipFree(scr);
-      } else {
-        double *dn = nullptr, *scr = nullptr;
-        (void)hipMalloc(&dn, sizeof(double) * 8);
-        (void)hipMalloc(&scr, sizeof(double2) * 1024);
-        for (int r = 0; r < nrhs; ++r) {
-          ems::launch_norm2(R + r * vec, h->ncoef, dn, scr, st);
-          (void)hipMemcpyAsync(&nb[r], dn, sizeof(double), hipMemcpyDeviceToHost, st);
-          (void)hipStreamSynchronize(st);
-        }
-        (void)hipFree(dn);
-        (void)hipFree(scr);
-      }
       for (int r = 0; r < nrhs; ++r)
-        if (bn[r] > 0) relres = std::max(relres, nb[r] / bn[r]);
+        if (bn[r] > 0) relres = std::max(relres, rn[r] / bn[r]);
       if (relres <= o->tol || iters >= o->maxit || outer >= 50) break;
       ++outer;
       int it = 0;
@@ -962,25 +1005,37 @@ extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
       std::vector<double> tmp;
       HIPCHK(h, hipMemsetAsync(D, 0, sizeof(double2) * vec * nrhs, st));
       rc = gmres_run(h, op32, R, D, nrhs, itol, restart, o->maxit - iters, true, st, it, rr, tmp);
-      if (rc) break;
+      if (rc) return rc;
       iters += it;
-      for (int r = 0; r < nrhs; ++r) ems::launch_axpy(X + r * vec, D + r * vec, h->ncoef, 1.0, st);
+      for (int r = 0; r < nrhs; ++r)
+        HIPCHK(h, ems::launch_axpy(X + r * vec, D + r * vec, h->ncoef, 1.0, st));
     }
-    (void)hipFree(R);
-    (void)hipFree(D);
-    if (rc) return rc;
   }
   HIPCHK(h, hipStreamSynchronize(st));
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  const bool conv = relres <= o->tol * 1.0000001;
   if (info) {
     info->iters = iters;
     info->outer_iters = outer;
     info->relres = relres;
-    info->converged = relres <= o->tol * 1.0000001 ? 1 : 0;
+    info->converged = conv ? 1 : 0;
     info->seconds = secs;
   }
-  return relres <= o->tol * 1.0000001 ? EMS_OK : EMS_NOT_CONVERGED;
+  return conv ? EMS_OK : EMS_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
+                         const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream) {
+  return solve_impl(h, b, x, nrhs, o, info, stream, false);
+}
+
+extern "C" int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
+                                 const ems_solver_opts *o, ems_solve_info *info,
+                                 ems_stream_t stream) {
+  return solve_impl(h, b, x, nrhs, o, info, stream, true);
 }
 
 extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,

@@ -85,6 +85,7 @@ struct FmmLevel {
 struct FmmLaunch {
   const char *name = "fmm";
   int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0;
+  double flops = 0.0;  // 8 (2 P_out + 1)(2 P_in + 1) summed over the tasks, per right-hand side
   std::vector<int> ptr, in_P, sym_L, sgn, out_P, item_out, item_row0;
   std::vector<int64_t> in_base, sym_base, out_base;
 };
@@ -145,6 +146,7 @@ struct ems_handle {
   double2 *d_R = nullptr;        // [q][4]
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
+  float2 *d_Eagg32 = nullptr, *d_Edis32 = nullptr;  // complex64 copies for the mixed form (optional)
   bool p_uniform = false;
   double etab_budget_gb = 96.0;
   // workspaces (sized for ws_nrhs right-hand sides)
@@ -155,6 +157,9 @@ struct ems_handle {
   double2 *d_dis = nullptr;      // [nrhs][dis_chunks][ncoef] partial local coefficients
   double2 *d_free = nullptr;     // [nrhs][ncoef]
   int64_t n_pairs = 0;
+  // algorithmic flops per right-hand side (complex multiply-add = 8)
+  double flops_graf = 0.0;   // direct Graf sum over the pairs the kernel visits
+  double flops_s = 0.0;      // S multiply, 8 sum (4 p_m + 2)^2
 
   // free-space FMM
   int fmm_mode = 0;            // 0 auto, 1 direct, 2 FMM
@@ -173,6 +178,7 @@ struct ems_handle {
   struct ProfRec {
     const char *name;
     hipEvent_t a, b;
+    double flops;  // algorithmic floating-point operations of the launch
   };
   std::vector<ProfRec> prof_recs;
 
@@ -183,6 +189,9 @@ struct ems_handle {
   size_t tmp_bytes = 0;
   double *d_red = nullptr;       // reduction partials
   size_t red_bytes = 0;
+  // mixed-precision refinement: residual and correction [nrhs][ncoef]
+  double2 *d_irR = nullptr, *d_irD = nullptr;
+  size_t ir_bytes = 0;
 };
 
 namespace ems {
@@ -192,9 +201,10 @@ struct ProfScope {
   ems_handle *h;
   hipStream_t st;
   size_t idx;
-  ProfScope(ems_handle *h_, const char *name, hipStream_t s) : h(h_), st(s), idx(0) {
+  ProfScope(ems_handle *h_, const char *name, hipStream_t s, double flops = 0.0)
+      : h(h_), st(s), idx(0) {
     if (!h->prof) return;
-    ems_handle::ProfRec r{name, nullptr, nullptr};
+    ems_handle::ProfRec r{name, nullptr, nullptr, flops};
     (void)hipEventCreate(&r.a);
     (void)hipEventCreate(&r.b);
     (void)hipEventRecord(r.a, st);

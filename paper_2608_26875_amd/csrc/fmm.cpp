@@ -382,6 +382,10 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
       }
     }
     for (int t = 0; t < (int)L.in_P.size(); ++t) L.max_in_P = std::max(L.max_in_P, L.in_P[t]);
+    L.flops = 0.0;
+    for (int o = 0; o < L.nout; ++o)
+      for (int t = L.ptr[o]; t < L.ptr[o + 1]; ++t)
+        L.flops += 8.0 * (2 * L.out_P[o] + 1) * (2 * L.in_P[t] + 1);
   }
   F.pool = std::move(pool);
   // Bounds of every task against the buffers the kernel will touch.

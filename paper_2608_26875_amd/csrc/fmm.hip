@@ -70,7 +70,7 @@ hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int n
     double2 *out = L.out_kind == 1 ? h->d_mult : (L.out_kind == 2 ? h->d_loc : fre);
     const int64_t out_stride = L.out_kind == 3 ? h->ncoef : F.exp_len;
     const size_t lds = sizeof(double2) * (size_t)(4 * L.max_in_P + 257);
-    ProfScope ps(const_cast<ems_handle *>(h), L.name, st);
+    ProfScope ps(const_cast<ems_handle *>(h), L.name, st, L.flops * nrhs);
     hipLaunchKernelGGL(toep_task_kernel, dim3((unsigned)L.item_out.size(), nrhs), dim3(256), lds, st,
                        D.ptr, D.in_base, D.in_P, D.sym_base, D.sym_L, D.sgn, D.out_base, D.out_P,
                        D.item_out, D.item_row0, in, in_stride, h->d_loc, F.exp_len, h->d_pool, out,

@@ -15,10 +15,14 @@
 // factors), the reflect kernel applies conj(w) R^H conj(1/(i pi s)), the
 // disaggregate kernel evaluates A^H.
 //
-// Layout: lanes own nodes (aggregate) or particles (disaggregate); the other
-// index is swept in a wave-uniform loop, so the coefficient or power-table
-// operand is the same for every lane.  Per (node, particle) pair one complex
-// exponential is formed in FP64 and (2p+1) complex multiply-adds follow.
+// Two implementations of the aggregate and disaggregate:
+//  * with the geometry exponentials tabulated at set-up (the default when the
+//    tables fit in memory), both are skinny complex matrix products on the
+//    matrix cores (FP64 MFMA for the FP64 form, FP32 MFMA on complex64
+//    tables for the mixed form);
+//  * otherwise, and for the adjoint, vector-ALU kernels form each exponential
+//    on the fly: lanes own nodes (aggregate) or particles (disaggregate) and
+//    the other index is swept in a wave-uniform loop.
 // Partial sums over particle chunks (aggregate) and node chunks
 // (disaggregate) are written separately and reduced in a fixed order, so
 // results are reproducible run to run.
@@ -29,8 +33,8 @@ namespace ems {
 
 int pm_bucket(int pmax);
 
-// MODE 0: forward with tabulated exponentials, 1: forward, exponentials
-// formed on the fly, 2: adjoint (on the fly).
+// Vector-ALU forms with the exponentials formed on the fly (used when the
+// tables do not fit, and for the adjoint).  MODE 1: forward, 2: adjoint.
 template <int PM, bool UNI, int MODE>
 __global__ __launch_bounds__(256) void somm_aggregate_kernel(
     int n, int q, int pmax, const double *__restrict__ xy, const int *__restrict__ p,
@@ -38,9 +42,8 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
     const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
     const double2 *__restrict__ ss_t, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
-    int adjoint_unused, const double2 *__restrict__ Etab) {
+    int adjoint_unused) {
   constexpr int NM = 2 * PM + 1;
-  constexpr bool TAB = MODE == 0;
   constexpr bool adjoint = MODE == 2;
   (void)adjoint_unused;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,17 +66,6 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
     a = cconj(s);
     bb = make_double2(-xi.y, -xi.x);  // conj(i xi)
   }
-  double2 v[NM];
-#pragma unroll
-  for (int k = 0; k < NM; ++k) {
-    const int nn = k - PM;
-    double2 t = Vt[(int64_t)jj * ld + k];
-    if (adjoint) {
-      t = cconj(t);
-      if (nn & 1) t = cscale(t, -1.0);
-    }
-    v[k] = t;
-  }
   // acc_n = sum_m E(j, m) c^m_n, then I = sum_n V[j][n] acc_n: the 2p+1
   // accumulators are independent chains (same flop count as contracting the
   // modes first).
@@ -83,27 +75,33 @@ __global__ __launch_bounds__(256) void somm_aggregate_kernel(
   const int m0 = c * per_chunk;
   const int m1 = min(n, m0 + per_chunk);
   const double2 *xr = x + (int64_t)r * ldx;
-  // tabulated exponentials E[wave][m][j] (forward only)
-  const double2 *Ew = TAB ? Etab + (int64_t)wave * n * q + jj : nullptr;
-  for (int m = m0; m < m1; ++m) {
+  auto step = [&](int m, double2 E) {
     const int pm = UNI ? PM : p[m];
-    const double2 *cm = xr + (UNI ? (int64_t)m * 2 * (2 * PM + 1) : off[m]) + wave * (2 * pm + 1) + pm;
-    double2 E;
-    if (TAB) {
-      E = Ew[(int64_t)m * q];
-    } else {
-      const double xm = xy[2 * m], ym = xy[2 * m + 1];
-      E = cexp(make_double2(a.x * ym + bb.x * xm, a.y * ym + bb.y * xm));
-    }
+    const double2 *cm =
+        xr + (UNI ? (int64_t)m * 2 * (2 * PM + 1) : off[m]) + wave * (2 * pm + 1) + pm;
 #pragma unroll
     for (int k = 0; k < NM; ++k) {
       const int nn = k - PM;
       if (UNI || (nn >= -pm && nn <= pm)) cfma(acc[k], E, cm[nn]);
     }
-  }
+  };
+  auto expo = [&](int m) {
+    const double xm = xy[2 * m], ym = xy[2 * m + 1];
+    return cexp(make_double2(a.x * ym + bb.x * xm, a.y * ym + bb.y * xm));
+  };
+  for (int m = m0; m < m1; ++m) step(m, expo(m));
+  // the power table is read only now, so it holds no registers in the loop
   double2 res = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int k = 0; k < NM; ++k) cfma(res, v[k], acc[k]);
+  for (int k = 0; k < NM; ++k) {
+    const int nn = k - PM;
+    double2 t = Vt[(int64_t)jj * ld + k];
+    if (adjoint) {
+      t = cconj(t);
+      if (nn & 1) t = cscale(t, -1.0);
+    }
+    cfma(res, t, acc[k]);
+  }
   if (j < q) agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = res;
 }
 
@@ -152,9 +150,8 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
     const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
-    int per_chunk, int adjoint_unused, const double2 *__restrict__ Etab) {
+    int per_chunk, int adjoint_unused) {
   constexpr int NM = 2 * PM + 1;
-  constexpr bool TAB = MODE == 0;
   constexpr bool adjoint = MODE == 2;
   (void)adjoint_unused;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,25 +171,20 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
   for (int k = 0; k < NM; ++k) acc[k] = make_double2(0.0, 0.0);
   const int j0 = c * per_chunk;
   const int j1 = min(q, j0 + per_chunk);
-  // tabulated exponentials E[wave][j][l] (forward only)
-  const double2 *Ew = TAB ? Etab + (int64_t)wave * q * n + ll : nullptr;
-  for (int j = j0; j < j1; ++j) {
-    double2 E;
-    if (TAB) {
-      E = Ew[(int64_t)j * n];
+  auto expo = [&](int j) {
+    const double2 xi = xi_t[j];
+    const double2 s = st[j];
+    double2 a, bb;
+    if (!adjoint) {
+      a = s;
+      bb = make_double2(-xi.y, xi.x);  // i xi
     } else {
-      const double2 xi = xi_t[j];
-      const double2 s = st[j];
-      double2 a, bb;
-      if (!adjoint) {
-        a = s;
-        bb = make_double2(-xi.y, xi.x);  // i xi
-      } else {
-        a = cconj(s);
-        bb = make_double2(xi.y, xi.x);   // conj(-i xi)
-      }
-      E = cexp(make_double2(a.x * yl + bb.x * xl, a.y * yl + bb.y * xl));
+      a = cconj(s);
+      bb = make_double2(xi.y, xi.x);   // conj(-i xi)
     }
+    return cexp(make_double2(a.x * yl + bb.x * xl, a.y * yl + bb.y * xl));
+  };
+  auto step = [&](int j, double2 E) {
     const double2 F = cmul(E, gr[j]);
     const double2 *Vj = Vt + (int64_t)j * ld;
 #pragma unroll
@@ -201,7 +193,8 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
       if (adjoint) u = cconj(u);
       cfma(acc[k], F, u);
     }
-  }
+  };
+  for (int j = j0; j < j1; ++j) step(j, expo(j));
   if (l < n) {
     double2 *o = dis + ((int64_t)r * chunks + c) * ncoef + off[l] + wave * (2 * pl + 1) + pl;
 #pragma unroll
@@ -212,28 +205,261 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Matrix-core form of the tabulated forward contractions.
+//
+// Aggregate: for one wave type and one chunk of particles,
+//   A[j][k] = sum_m E(j, m) c^m_{k-PM}        (nodes x modes, contracted over m)
+//   I_j     = sum_k V[j][k] A[j][k],
+// Disaggregate: for one wave type and one chunk of nodes,
+//   a^l_{k-PM} = sum_j E(j, l) (RW_j V[j][k])  (particles x modes, contracted over j).
+// Both are skinny complex products whose long operand (the exponential
+// table, 16 B per (node, particle)) streams from HBM exactly once.  A wave
+// owns 16*NT rows x 16*NU modes; each step contracts 4 indices (lane group
+// kq = lane / 16 supplies index base + kq) with 16x16x4 MFMAs, a complex
+// product being four real ones (re*re - im*im, re*im + im*re).  The operands
+// of the next step are fetched before the products of the current one.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using Acc = mf_d4;
+  using C = double2;
+  __device__ static Acc op(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output row held in accumulator element v by lane group kq (column = lane % 16)
+  __device__ static int row(int kq, int v) { return kq + 4 * v; }
+};
+template <> struct Mfma<float> {
+  using Acc = mf_f4;
+  using C = float2;
+  __device__ static Acc op(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int kq, int v) { return 4 * kq + v; }
+};
+
+template <typename T, int NT, int NU>
+__device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NU],
+                                           typename Mfma<T>::Acc (&ai)[NT][NU],
+                                           const T (&er)[NT], const T (&ei)[NT], const T (&br)[NU],
+                                           const T (&bi)[NU]) {
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const T nb = -bi[u];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      ar[t][u] = Mfma<T>::op(er[t], br[u], ar[t][u]);
+      ar[t][u] = Mfma<T>::op(ei[t], nb, ar[t][u]);
+      ai[t][u] = Mfma<T>::op(er[t], bi[u], ai[t][u]);
+      ai[t][u] = Mfma<T>::op(ei[t], br[u], ai[t][u]);
+    }
+  }
+}
+
+template <typename T, int PM, int NT, bool UNI>
+__global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
+    int n, int q, const int *__restrict__ p, const int64_t *__restrict__ off,
+    const double2 *__restrict__ x, int64_t ldx, const double2 *__restrict__ Vp_t,
+    const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
+    const typename Mfma<T>::C *__restrict__ Etab) {
+  using Acc = typename Mfma<T>::Acc;
+  using C = typename Mfma<T>::C;
+  constexpr int NM = 2 * PM + 1, NU = (NM + 15) / 16;
+  const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
+  const int jb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
+  const int c = blockIdx.y, wave = blockIdx.z & 1, r = blockIdx.z >> 1;
+  const int m0 = c * per_chunk, m1 = min(n, m0 + per_chunk);
+  const double2 *xr = x + (int64_t)r * ldx;
+  const C *Ew = Etab + (int64_t)wave * n * q;
+  Acc ar[NT][NU], ai[NT][NU];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+  int jl[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) jl[t] = min(jb + 16 * t + i16, q - 1);
+  C en[NT];
+  double2 xn[NU];
+  auto fetch = [&](int m) {
+    const int mc = min(m + kq, m1 - 1);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
+    // uniform orders: the coefficient address needs no table lookup
+    const int pm = UNI ? PM : p[mc];
+    const int64_t base = (UNI ? (int64_t)mc * 2 * NM : off[mc]) + wave * (2 * pm + 1) + pm;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int nn = 16 * u + i16 - PM;
+      xn[u] = (nn >= -pm && nn <= pm) ? xr[base + nn] : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(m0);
+  for (int m = m0; m < m1; m += 4) {
+    const bool ok = m + kq < m1;
+    T er[NT], ei[NT], br[NU], bi[NU];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      er[t] = en[t].x;
+      ei[t] = en[t].y;
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      br[u] = ok ? (T)xn[u].x : T(0);
+      bi[u] = ok ? (T)xn[u].y : T(0);
+    }
+    fetch(m + 4);
+    mfma_cstep<T, NT, NU>(ar, ai, er, ei, br, bi);
+  }
+  // I_j = sum_k V[j][k] A[j][k]; the 16 lanes of a group hold the 16 columns
+  const double2 *Vt = wave ? Vs_t : Vp_t;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = jb + 16 * t + Mfma<T>::row(kq, v);
+      const int jc = min(j, q - 1);
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int k = 16 * u + i16;
+        if (k < NM) {
+          const double2 w = Vt[(int64_t)jc * NM + k];
+          const double a = (double)ar[t][u][v], b = (double)ai[t][u][v];
+          re += w.x * a - w.y * b;
+          im += w.x * b + w.y * a;
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (i16 == 0 && j < q)
+        agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = make_double2(re, im);
+    }
+  }
+}
+
+template <typename T, int PM, int NT>
+__global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
+    int n, int q, const int *__restrict__ p, const int64_t *__restrict__ off,
+    const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
+    const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
+    int per_chunk, const typename Mfma<T>::C *__restrict__ Etab) {
+  using Acc = typename Mfma<T>::Acc;
+  using C = typename Mfma<T>::C;
+  constexpr int NM = 2 * PM + 1, NU = (NM + 15) / 16;
+  const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
+  const int lb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
+  const int c = blockIdx.y, wave = blockIdx.z & 1, r = blockIdx.z >> 1;
+  const int j0 = c * per_chunk, j1 = min(q, j0 + per_chunk);
+  const double2 *gr = g + (int64_t)(r * 2 + wave) * q;
+  const double2 *Vt = wave ? Vs_t : Vp_t;
+  const C *Ew = Etab + (int64_t)wave * q * n;
+  Acc ar[NT][NU], ai[NT][NU];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+  int lc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) lc[t] = min(lb + 16 * t + i16, n - 1);
+  C en[NT];
+  double2 vn[NU], gn;
+  auto fetch = [&](int j) {
+    const int jc = min(j + kq, j1 - 1);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)jc * n + lc[t]];
+    gn = gr[jc];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) vn[u] = Vt[(int64_t)jc * NM + min(16 * u + i16, NM - 1)];
+  };
+  fetch(j0);
+  for (int j = j0; j < j1; j += 4) {
+    const bool ok = j + kq < j1;
+    T er[NT], ei[NT], br[NU], bi[NU];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      er[t] = en[t].x;
+      ei[t] = en[t].y;
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const bool use = ok && 16 * u + i16 < NM;
+      const double2 G = cmul(gn, vn[u]);
+      br[u] = use ? (T)G.x : T(0);
+      bi[u] = use ? (T)G.y : T(0);
+    }
+    fetch(j + 4);
+    mfma_cstep<T, NT, NU>(ar, ai, er, ei, br, bi);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int l = lb + 16 * t + Mfma<T>::row(kq, v);
+      if (l >= n) continue;
+      const int pl = p[l];
+      double2 *o = dis + ((int64_t)r * chunks + c) * ncoef + off[l] + wave * (2 * pl + 1) + pl;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int nn = 16 * u + i16 - PM;
+        if (nn >= -pl && nn <= pl) o[nn] = make_double2((double)ar[t][u][v], (double)ai[t][u][v]);
+      }
+    }
+  }
+}
+
 #define EMS_AGG_LAUNCH(PMV, UNIV, TABV)                                                    \
   hipLaunchKernelGGL((somm_aggregate_kernel<PMV, UNIV, TABV>), grid, dim3(256), 0, st, h->n,  \
                      h->q, h->pmax, h->d_xy, h->d_p, h->d_off, x, h->ncoef, h->d_xi, h->d_sp,  \
-                     h->d_ss, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, adjoint ? 1 : 0,  \
-                     h->d_Eagg)
+                     h->d_ss, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, adjoint ? 1 : 0)
 #define EMS_AGG_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    if (mode == 0 && uni) EMS_AGG_LAUNCH(PMV, true, 0);                                    \
-    else if (mode == 0) EMS_AGG_LAUNCH(PMV, false, 0);                                     \
-    else if (mode == 1 && uni) EMS_AGG_LAUNCH(PMV, true, 1);                               \
+    if (mode == 1 && uni) EMS_AGG_LAUNCH(PMV, true, 1);                                    \
     else if (mode == 1) EMS_AGG_LAUNCH(PMV, false, 1);                                     \
     else EMS_AGG_LAUNCH(PMV, false, 2);                                                    \
     break;
 
+#define EMS_AGGM_LAUNCH(T, PMV, NT, UNIV, ETAB)                                             \
+  hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, PMV, NT, UNIV>),                         \
+                     dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * nrhs), dim3(256), \
+                     0, st, h->n, h->q, h->d_p, h->d_off, x, h->ncoef, h->d_Vp, h->d_Vs,        \
+                     h->d_agg, h->agg_chunks, per, ETAB)
+#define EMS_AGGM_CASE(PMV)                                                                   \
+  case PMV:                                                                                  \
+    if (mixed && h->d_Eagg32) {                                                              \
+      if (uni) EMS_AGGM_LAUNCH(float, PMV, 4, true, h->d_Eagg32);                            \
+      else EMS_AGGM_LAUNCH(float, PMV, 4, false, h->d_Eagg32);                               \
+    } else {                                                                                 \
+      if (uni) EMS_AGGM_LAUNCH(double, PMV, 2, true, h->d_Eagg);                             \
+      else EMS_AGGM_LAUNCH(double, PMV, 2, false, h->d_Eagg);                                \
+    }                                                                                        \
+    break;
+
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st) {
-  (void)mixed;
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
-  dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int pb = pm_bucket(h->pmax);
-  const int mode = adjoint ? 2 : (h->d_Eagg != nullptr ? 0 : 1);
   const bool uni = h->p_uniform && pb == h->pmax;
+  if (!adjoint && h->d_Eagg != nullptr) {
+    switch (pb) {
+      EMS_AGGM_CASE(4)
+      EMS_AGGM_CASE(8)
+      EMS_AGGM_CASE(10)
+      EMS_AGGM_CASE(12)
+      EMS_AGGM_CASE(15)
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
+  const int mode = adjoint ? 2 : 1;
   switch (pb) {
     EMS_AGG_CASE(4)
     EMS_AGG_CASE(8)
@@ -257,20 +483,47 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
   hipLaunchKernelGGL((somm_disaggregate_kernel<PMV, TABV>), grid, dim3(256), 0, st, h->n, h->q, \
                      h->pmax, h->d_xy, h->d_p, h->d_off, h->d_xi, h->d_sp, h->d_ss, h->d_Vp,    \
                      h->d_Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per,               \
-                     adjoint ? 1 : 0, h->d_Edis)
+                     adjoint ? 1 : 0)
 #define EMS_DIS_CASE(PMV)                                                                  \
   case PMV:                                                                                \
-    if (mode == 0) EMS_DIS_LAUNCH(PMV, 0);                                                 \
-    else if (mode == 1) EMS_DIS_LAUNCH(PMV, 1);                                            \
+    if (mode == 1) EMS_DIS_LAUNCH(PMV, 1);                                                 \
     else EMS_DIS_LAUNCH(PMV, 2);                                                           \
+    break;
+
+#define EMS_DISM_CASE(PMV)                                                                   \
+  case PMV:                                                                                  \
+    if (mixed && h->d_Edis32) {                                                              \
+      constexpr int NT = 4;                                                                  \
+      hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<float, PMV, NT>),                    \
+                         dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * nrhs),     \
+                         dim3(256), 0, st, h->n, h->q, h->d_p, h->d_off, h->d_Vp, h->d_Vs,    \
+                         h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, h->d_Edis32);    \
+    } else {                                                                                 \
+      constexpr int NT = 4;                                                                  \
+      hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<double, PMV, NT>),                   \
+                         dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * nrhs),     \
+                         dim3(256), 0, st, h->n, h->q, h->d_p, h->d_off, h->d_Vp, h->d_Vs,    \
+                         h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, h->d_Edis);      \
+    }                                                                                        \
     break;
 
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st) {
-  (void)mixed;
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
+  if (!adjoint && h->d_Edis != nullptr) {
+    switch (pm_bucket(h->pmax)) {
+      EMS_DISM_CASE(4)
+      EMS_DISM_CASE(8)
+      EMS_DISM_CASE(10)
+      EMS_DISM_CASE(12)
+      EMS_DISM_CASE(15)
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
-  const int mode = adjoint ? 2 : (h->d_Edis != nullptr ? 0 : 1);
+  const int mode = adjoint ? 2 : 1;
   switch (pm_bucket(h->pmax)) {
     EMS_DIS_CASE(4)
     EMS_DIS_CASE(8)
@@ -288,7 +541,8 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
 // Edis[w][j][l] = e^{i xi_j x_l + s_w(j) y_l}.
 __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
                                 const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
-                                const double2 *__restrict__ ss_t, double2 *__restrict__ E) {
+                                const double2 *__restrict__ ss_t, double2 *__restrict__ E,
+                                float2 *__restrict__ E32) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   const int w = blockIdx.z;
@@ -297,12 +551,16 @@ __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
   const double2 s = w ? ss_t[j] : sp_t[j];
   const double xm = xy[2 * m], ym = xy[2 * m + 1];
   // s y - i xi x
-  E[((int64_t)w * n + m) * q + j] = cexp(make_double2(s.x * ym + xi.y * xm, s.y * ym - xi.x * xm));
+  const double2 e = cexp(make_double2(s.x * ym + xi.y * xm, s.y * ym - xi.x * xm));
+  const int64_t at = ((int64_t)w * n + m) * q + j;
+  E[at] = e;
+  if (E32) E32[at] = make_float2((float)e.x, (float)e.y);
 }
 
 __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
                                 const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
-                                const double2 *__restrict__ ss_t, double2 *__restrict__ E) {
+                                const double2 *__restrict__ ss_t, double2 *__restrict__ E,
+                                float2 *__restrict__ E32) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int w = blockIdx.z;
@@ -311,16 +569,19 @@ __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
   const double2 s = w ? ss_t[j] : sp_t[j];
   const double xl = xy[2 * l], yl = xy[2 * l + 1];
   // i xi x + s y
-  E[((int64_t)w * q + j) * n + l] = cexp(make_double2(s.x * yl - xi.y * xl, s.y * yl + xi.x * xl));
+  const double2 e = cexp(make_double2(s.x * yl - xi.y * xl, s.y * yl + xi.x * xl));
+  const int64_t at = ((int64_t)w * q + j) * n + l;
+  E[at] = e;
+  if (E32) E32[at] = make_float2((float)e.x, (float)e.y);
 }
 
 hipError_t launch_etables(ems_handle *h, hipStream_t st) {
   hipLaunchKernelGGL(etab_agg_kernel, dim3((h->q + 255) / 256, h->n, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg);
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg, h->d_Eagg32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(etab_dis_kernel, dim3((h->n + 255) / 256, h->q, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis);
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis, h->d_Edis32);
   return hipGetLastError();
 }
 

@@ -1,0 +1,86 @@
+"""GPU tests of the mixed-precision form and of the adjoint solve.
+
+Mixed apply: the aggregate/disaggregate contractions run on FP32 matrix cores
+over complex64 exponential tables, the direct Graf sum in FP32.  Its error
+against the FP64 form is bounded by the FP32 unit roundoff u = 2^-24 ~ 6e-8
+times the growth of a K-term sum of rounded products (about sqrt(K) for
+independent rounding, K <= a few thousand nodes or particles here) and the
+cancellation in the reflected sums; the test allows 3e-5 relative L2 on the
+non-identity part z = S T x, and requires the difference to exceed 1e-10 so
+a silent FP64 path would be caught.  The mixed solve (FP64 outer residual and
+update) must still meet the FP64 backward-residual bound under the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import oracle_media, product_operator, rel, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2608_26875_amd as E  # noqa: E402
+from oracle import incident, operator, smatrix  # noqa: E402
+
+TOL_MIXED = 3e-5
+Z = E.EMS_PART_FREE | E.EMS_PART_REFL | E.EMS_PART_S
+
+
+@pytest.mark.parametrize("case", ["c0", "ragged"])
+def test_mixed_apply_close_to_fp64(case):
+    if case == "c0":
+        w = W.c0_circles()
+        op = product_operator(w)
+    else:
+        w = W.small_cloud(70, seed=12, p=6, omega=5.0, width=50.0, depth=(1.0, 9.0), ragged=True)
+        op = product_operator(w, S_blocks=W.random_smatrix_blocks(w.p, seed=99))
+    op.build()
+    x = to_gpu(W.random_coeffs(w.n_coeff, 31, nrhs=2))
+    for flags in (Z, E.EMS_PART_REFL, E.EMS_PART_FREE):
+        z64 = to_np(op.apply(x, flags=flags))
+        z32 = to_np(op.apply(x, flags=flags | E.EMS_MIXED))
+        e = rel(z32, z64)
+        print(case, flags, "mixed vs fp64", e, flush=True)
+        assert 1e-10 < e <= TOL_MIXED, (flags, e)
+
+
+def test_mixed_solve_meets_fp64_residual():
+    """Iterative refinement with FP32 inner applies reaches the FP64 bound."""
+    w = W.c0_circles()
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    op = product_operator(w)
+    op.build()
+    wave, ang = w.incidence[0]
+    b = op.incident([(wave, ang)])
+    x, info = op.solve(b, tol=1e-10, restart=200, maxit=600, precision=1, inner_tol=1e-5)
+    print("mixed solve", info, flush=True)
+    assert info["converged"] == 1 and info["outer_iters"] >= 2
+    xg = to_np(x)[0]
+    b_orc = incident.rhs(w, m, S, wave, ang)
+    r = b_orc - operator.apply(w, m, S, xg, tol=1e-13)
+    assert np.linalg.norm(r) / np.linalg.norm(b_orc) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_solve_against_dense_oracle(precision):
+    """GMRES on A^H: ||b - A_oracle^H lambda|| / ||b|| <= 1e-9 with the
+    oracle's densely assembled operator (ragged p, 4 particles)."""
+    w = W.small_cloud(4, seed=21, p=3, omega=4.0, width=8.0, depth=(1.0, 4.0), ragged=True)
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    A = operator.dense_matrix(w, m, S, tol=1e-12)
+    op = product_operator(w)
+    op.build()
+    b = W.random_coeffs(w.n_coeff, 5, nrhs=2)
+    lam, info = op.solve(to_gpu(b), tol=1e-12, restart=50, maxit=200, precision=precision,
+                         adjoint=True)
+    print("adjoint solve", precision, info, flush=True)
+    assert info["converged"] == 1
+    L = to_np(lam)
+    for r in range(2):
+        res = b[r] - A.conj().T @ L[r]
+        assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-9
