@@ -140,7 +140,7 @@ int ems_set_media(ems_handle *h, const ems_media *m);
 
 /* Particles (Section 2, well-separated enclosing disks, Section 3.3): n centres
  * xy[n][2] in the paper frame, enclosing radii R[n], truncation orders
- * p[n] in [1, 15].  Host data, copied.  Validation at ems_build:
+ * p[n] in [1, 16].  Host data, copied.  Validation at ems_build:
  * |x_m - x_l| > R_m + R_l and y_m + R_m < 0, else EMS_ERR_GEOMETRY. */
 int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *R,
                       const int32_t *p);
@@ -240,6 +240,32 @@ int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
  * u device [nrhs][npts][2] complex128. */
 int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
                        const double *pts, void *u, ems_stream_t stream);
+
+/* Conjugate transpose of ems_eval_scattered: g = F^H res, the right-hand
+ * side A^H lambda = F^H res of the adjoint system of a receiver misfit
+ * J = 1/2 sum |u - u_obs|^2 (res = u - u_obs).  res device [nrhs][npts][2]
+ * complex128, pts device [npts][2], g device [nrhs][n_coeff] (overwritten).
+ * Receivers are validated as in ems_eval_scattered. */
+int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_t nrhs, int32_t npts,
+                               const double *pts, void *g, ems_stream_t stream);
+
+/* Gradient of a receiver misfit J = 1/2 sum_r sum_rcv |u_r(x_rcv) - u_obs|^2
+ * with respect to the particle centres and the substrate's Lame parameters
+ * (adjoint method; the derivative identities of the translation, plane-wave
+ * and interface operators of Sections 3-4 applied to the Schur system).
+ * Inputs, all for the same nrhs plane waves `waves` (host array):
+ *   gamma  device [nrhs][n_coeff]: solutions of A gamma = b (b from ems_incident),
+ *   lam    device [nrhs][n_coeff]: solutions of A^H lam = F^H res
+ *          (ems_eval_scattered_adjoint, then ems_solve_adjoint),
+ *   pts    device [npts][2], res device [nrhs][npts][2]: u - u_obs.
+ * Outputs: dxy device [n][2] (dJ/dx_m, dJ/dy_m), dlame host [2]
+ * (dJ/dlambda_b, dJ/dmu_b).  The first call after a build constructs an
+ * internal operator with orders p + 1 (so p <= 15 here).  Synchronous.
+ * Errors: EMS_ERR_ARG, EMS_ERR_STATE, EMS_ERR_GEOMETRY (receivers),
+ * EMS_ERR_UNIMPLEMENTED (p = 16), EMS_ERR_HIP, EMS_ERR_NUMERIC. */
+int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, const void *gamma,
+                  const void *lam, int32_t npts, const double *pts, const void *res, double *dxy,
+                  double *dlame, ems_stream_t stream);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel the library queues.  ems_profile(h, 1) clears and starts

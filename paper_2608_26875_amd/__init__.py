@@ -106,6 +106,9 @@ def _load():
         "ems_solve_adjoint": ([P, P, P, I32, ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveInfo),
                                P], I32),
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
+        "ems_eval_scattered_adjoint": ([P, P, I32, I32, P, P, P], I32),
+        "ems_param_vjp": ([P, ctypes.POINTER(PlaneWave), I32, P, P, I32, P, P, P,
+                           ctypes.POINTER(ctypes.c_double), P], I32),
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
                                   ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
         "ems_reflection": ([ctypes.POINTER(Media), D, D, P], I32),
@@ -124,7 +127,7 @@ _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
-            "ems_solve_adjoint",
+            "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp",
             "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
@@ -306,6 +309,56 @@ class Operator:
                                             int(p.shape[0]), ctypes.c_void_p(p.data_ptr()),
                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
+
+    def param_vjp(self, waves, gamma, lam, pts, res, stream=None):
+        """(dJ/d centres [n, 2] on the device, (dJ/dlambda_b, dJ/dmu_b)) for the
+        misfit residual res = u - u_obs at pts, forward solutions gamma and
+        adjoint solutions lam (A^H lam = F^H res)."""
+        import torch
+        arr = (PlaneWave * len(waves))(*[PlaneWave(int(w), float(a)) for w, a in waves])
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+        res = res.contiguous()
+        dxy = torch.empty((self.n, 2), dtype=torch.float64, device="cuda")
+        dl = (ctypes.c_double * 2)()
+        self._check(_lib.ems_param_vjp(self.h, arr, len(waves), ctypes.c_void_p(gamma.data_ptr()),
+                                       ctypes.c_void_p(lam.data_ptr()), int(p.shape[0]),
+                                       ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(res.data_ptr()),
+                                       ctypes.c_void_p(dxy.data_ptr()), dl, _stream_ptr(stream)))
+        return dxy, (dl[0], dl[1])
+
+    def misfit_gradient(self, waves, pts, u_obs, tol=1e-12, restart=200, maxit=2000,
+                        precision=0):
+        """J = 1/2 sum |u - u_obs|^2 over the plane waves and receivers, and its
+        gradient: forward solve, field, adjoint right-hand side F^H res,
+        adjoint solve, parameter vector-Jacobian product.  u_obs: complex128
+        [nwaves, npts, 2] (device or host).  Returns (J, dJ/dxy [n, 2] host,
+        (dJ/dlambda_b, dJ/dmu_b), info)."""
+        import torch
+        b = self.incident(waves)
+        gam, i1 = self.solve(b, tol=tol, restart=restart, maxit=maxit, precision=precision)
+        u = self.scattered_field(gam, pts)
+        res = u - torch.as_tensor(u_obs, dtype=torch.complex128).to(u.device)
+        J = 0.5 * float(torch.sum(torch.abs(res) ** 2))
+        g = self.scattered_field_adjoint(res, pts)
+        lam, i2 = self.solve(g, tol=tol, restart=restart, maxit=maxit, precision=precision,
+                             adjoint=True)
+        dxy, dl = self.param_vjp(waves, gam, lam, pts, res)
+        return J, dxy.cpu().numpy(), dl, {"forward": i1, "adjoint": i2}
+
+    def scattered_field_adjoint(self, res, pts, stream=None):
+        """g = F^H res for residuals res [nrhs, npts, 2] at host points pts [npts, 2]."""
+        import torch
+        res = res.contiguous()
+        nrhs = int(res.shape[0])
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+        if tuple(res.shape[1:]) != (p.shape[0], 2) or res.dtype != torch.complex128:
+            raise ValueError("res must be complex128 [nrhs, npts, 2]")
+        g = torch.empty((nrhs, self.n_coeff), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_eval_scattered_adjoint(self.h, ctypes.c_void_p(res.data_ptr()), nrhs,
+                                                    int(p.shape[0]), ctypes.c_void_p(p.data_ptr()),
+                                                    ctypes.c_void_p(g.data_ptr()),
+                                                    _stream_ptr(stream)))
+        return g
 
     def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-5,
               stream=None, adjoint=False):

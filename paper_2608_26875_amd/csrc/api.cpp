@@ -62,6 +62,11 @@ void free_device(ems_handle *h) {
   dfree(h->d_sp);
   dfree(h->d_ss);
   dfree(h->d_R);
+  dfree(h->d_dR);
+  if (h->ext) {
+    ems_destroy(h->ext);
+    h->ext = nullptr;
+  }
   dfree(h->d_Vp);
   dfree(h->d_Vs);
   dfree(h->d_Eagg);
@@ -358,7 +363,7 @@ int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *
   h->pmax = 0;
   for (int i = 0; i < n; ++i) {
     if (p[i] < 1 || p[i] > ems::kMaxP)
-      return fail(h, EMS_ERR_UNIMPLEMENTED, "truncation order must be in [1, 15]");
+      return fail(h, EMS_ERR_UNIMPLEMENTED, "truncation order must be in [1, 16]");
     h->off[i + 1] = h->off[i] + 2 * (2 * p[i] + 1);
     h->pmax = std::max(h->pmax, p[i]);
   }
@@ -506,17 +511,18 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   // power tables padded to the kernels' compile-time order (zeros beyond pmax)
   const int pmb = ems::pm_bucket(h->pmax);
   const int q = h->q, ld = 2 * pmb + 1;
-  std::vector<double2> xi(q), w(q), sp(q), ss(q), R(4 * (size_t)q), Vp((size_t)q * ld),
-      Vs((size_t)q * ld);
+  std::vector<double2> xi(q), w(q), sp(q), ss(q), R(4 * (size_t)q), dR(8 * (size_t)q),
+      Vp((size_t)q * ld), Vs((size_t)q * ld);
   const cd I(0.0, 1.0);
   for (int j = 0; j < q; ++j) {
     const cd x = nt.xi[j];
     cd s4[4];
     ems::node_s(x, nt.bp[j], nt.d[j], h->md, s4);
     const cd s1 = s4[0], s2 = s4[1];
-    cd Rj[4];
-    rc = ems::reflection_s(x, s4, h->md, Rj);
+    cd Rj[4], dRj[8];
+    rc = ems::reflection_deriv_s(x, s4, h->md, Rj, dRj);
     if (rc) return fail(h, rc, "singular interface system at a Sommerfeld node");
+    for (int k = 0; k < 8; ++k) dR[8 * (size_t)j + k] = make_double2(dRj[k].real(), dRj[k].imag());
     xi[j] = make_double2(x.real(), x.imag());
     w[j] = make_double2(nt.w[j].real(), nt.w[j].imag());
     sp[j] = make_double2(s1.real(), s1.imag());
@@ -590,6 +596,7 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if ((rc = upload(h, h->d_sp, sp.data(), sp.size()))) return rc;
   if ((rc = upload(h, h->d_ss, ss.data(), ss.size()))) return rc;
   if ((rc = upload(h, h->d_R, R.data(), R.size()))) return rc;
+  if ((rc = upload(h, h->d_dR, dR.data(), dR.size()))) return rc;
   if ((rc = upload(h, h->d_Vp, Vp.data(), Vp.size()))) return rc;
   if ((rc = upload(h, h->d_Vs, Vs.data(), Vs.size()))) return rc;
   if (h->fmm_on) {
@@ -755,7 +762,11 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
   }
   int rc = ensure_tmp(h, sizeof(double2) * 2 * nrhs * vec);
   if (rc) return rc;
-  rc = ensure_red(h, sizeof(double2) * ((size_t)(restart + 2) * 520 + 64 * (restart + 2)));
+  // d_h, d_h2 [restart + 2] each, the norm result (restart + 2 + 8 slots
+  // before the partials), then up to restart + 1 reduced vectors of
+  // kRedBlocks complex partials each
+  rc = ensure_red(h, sizeof(double2) * (3 * (size_t)(restart + 2) + 8 +
+                                        (size_t)(restart + 1) * ems::kRedBlocks));
   if (rc) return rc;
   double2 *W = h->d_tmp;                 // [nrhs][n] operator output
   double2 *d_h = reinterpret_cast<double2 *>(h->d_red);  // device coefficients
@@ -915,7 +926,8 @@ namespace {
 
 // Euclidean norms of nrhs stacked vectors (device) into host memory.
 int norms(ems_handle *h, const double2 *v, int nrhs, std::vector<double> &out, hipStream_t st) {
-  int rc = ensure_red(h, sizeof(double) * 1024);
+  // result (8 doubles, aligned for the partials) + kRedBlocks complex partials
+  int rc = ensure_red(h, sizeof(double) * 8 + sizeof(double2) * ems::kRedBlocks);
   if (rc) return rc;
   double *d_nrm = reinterpret_cast<double *>(h->d_red);
   double *scratch = d_nrm + 8;
@@ -1038,13 +1050,10 @@ extern "C" int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t 
   return solve_impl(h, b, x, nrhs, o, info, stream, true);
 }
 
-extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
-                                  const double *pts, void *u, ems_stream_t stream) {
-  if (!h || !gamma || !pts || !u || nrhs <= 0 || npts <= 0)
-    return fail(h, EMS_ERR_ARG, "bad field arguments");
-  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
-  hipStream_t st = (hipStream_t)stream;
-  // receivers must lie in the host layer and outside every enclosing disk
+namespace {
+
+// Receivers must lie in the host layer (y < 0) and outside every enclosing disk.
+int check_receivers(ems_handle *h, const double *pts, int npts, hipStream_t st) {
   std::vector<double> hp(2 * (size_t)npts);
   HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
@@ -1060,8 +1069,20 @@ extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs
                         std::to_string(m));
     }
   }
-  int rc = ensure_ws(h, nrhs);
+  return EMS_OK;
+}
+
+}  // namespace
+
+extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
+                                  const double *pts, void *u, ems_stream_t stream) {
+  if (!h || !gamma || !pts || !u || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad field arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = check_receivers(h, pts, npts, st);
   if (rc) return rc;
+  if ((rc = ensure_ws(h, nrhs))) return rc;
   const double2 *g = (const double2 *)gamma;
   double2 *uo = (double2 *)u;
   {
@@ -1075,4 +1096,173 @@ extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs
     HIPCHK(h, ems::launch_field_refl(h, nrhs, npts, pts, uo, st));
   }
   return EMS_OK;
+}
+
+extern "C" int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_t nrhs,
+                                          int32_t npts, const double *pts, void *g,
+                                          ems_stream_t stream) {
+  if (!h || !res || !pts || !g || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad field arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = check_receivers(h, pts, npts, st);
+  if (rc) return rc;
+  if ((rc = ensure_ws(h, nrhs))) return rc;
+  const double2 *rs = (const double2 *)res;
+  {
+    ems::ProfScope ps(h, "field_direct_adjoint", st);
+    HIPCHK(h, ems::launch_field_direct_adjoint(h, rs, nrhs, npts, pts, h->d_free, st));
+  }
+  {
+    ems::ProfScope ps(h, "field_refl_adjoint", st);
+    HIPCHK(h, ems::launch_field_refl_adjoint(h, rs, nrhs, npts, pts, st));
+  }
+  HIPCHK(h, ems::launch_somm_reflect(h, nrhs, true, st));
+  HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, true, false, st));
+  HIPCHK(h, ems::launch_combine(h, nullptr, (double2 *)g, nrhs, EMS_PART_FREE | EMS_PART_REFL,
+                                true, st));
+  return EMS_OK;
+}
+
+namespace {
+
+// The operator with orders p + 1 and S = I on the same geometry, media,
+// Sommerfeld rule kind and FMM settings: its free + reflected parts give the
+// order-(p + 1) incoming and adjoint expansions the centre gradient needs,
+// its plane-wave right-hand side the raw local coefficients.  Built once per
+// build of the parent; the exponential tables are left out (the vector-ALU
+// contractions form them on the fly).
+int build_ext(ems_handle *h, hipStream_t st) {
+  if (h->pmax + 1 > ems::kMaxP)
+    return fail(h, EMS_ERR_UNIMPLEMENTED, "gradient needs truncation orders below 16");
+  ems_handle *e = nullptr;
+  int rc = ems_create(&e);
+  if (rc) return fail(h, rc, "cannot create the extended operator");
+  e->md = h->md;
+  e->have_media = true;
+  std::vector<int32_t> pe(h->n);
+  for (int i = 0; i < h->n; ++i) pe[i] = h->p[i] + 1;
+  rc = ems_set_particles(e, h->n, h->xy.data(), h->R.data(), pe.data());
+  if (rc == EMS_OK) {
+    std::vector<int64_t> so(h->n + 1, 0);
+    for (int i = 0; i < h->n; ++i) so[i + 1] = so[i] + (int64_t)(4 * pe[i] + 2) * (4 * pe[i] + 2);
+    std::vector<double> S(2 * (size_t)so[h->n], 0.0);
+    for (int i = 0; i < h->n; ++i) {
+      const int64_t K = 4 * pe[i] + 2;
+      for (int64_t k = 0; k < K; ++k) S[2 * (size_t)(so[i] + k * K + k)] = 1.0;
+    }
+    rc = ems_set_smatrices(e, S.data(), so.data());
+  }
+  if (rc == EMS_OK) {
+    e->somm = h->somm;
+    e->fmm_mode = h->fmm_mode;
+    e->fmm_leaf = h->fmm_leaf;
+    e->fmm_top = h->fmm_top;
+    e->fmm_digits = h->fmm_digits;
+    e->etab_budget_gb = 0.0;
+    rc = ems_build(e, st);
+  }
+  if (rc) {
+    const std::string msg = "extended operator: " + std::string(e->err);
+    ems_destroy(e);
+    return fail(h, rc, msg);
+  }
+  h->ext = e;
+  return EMS_OK;
+}
+
+}  // namespace
+
+extern "C" int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs,
+                             const void *gamma, const void *lam, int32_t npts, const double *pts,
+                             const void *res, double *dxy, double *dlame, ems_stream_t stream) {
+  if (!h || !waves || !gamma || !lam || !pts || !res || !dxy || !dlame || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad gradient arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = check_receivers(h, pts, npts, st);
+  if (rc) return rc;
+  if (!h->ext && (rc = build_ext(h, st))) return rc;
+  ems_handle *E = h->ext;
+  if ((rc = ensure_ws(h, nrhs))) return rc;
+  const size_t nh = (size_t)nrhs * h->ncoef, ne = (size_t)nrhs * E->ncoef;
+  const size_t nq = (size_t)nrhs * 2 * h->q;
+  constexpr int kBlocks = 256;
+  double2 *buf = nullptr;
+  HIPCHK(h, hipMalloc(&buf, sizeof(double2) * (2 * nh + 6 * ne + 2 * nq) + sizeof(double) * 8 * kBlocks));
+  double2 *mu = buf, *a0dR = mu + nh, *gpad = a0dR + nh, *mpad = gpad + ne, *ae = mpad + ne,
+          *ze = ae + ne, *fe = ze + ne, *a0e = fe + ne, *Ig = a0e + ne, *Lam = Ig + nq;
+  double *part = reinterpret_cast<double *>(Lam + nq);
+  const double2 *G = (const double2 *)gamma;
+  auto run = [&]() -> int {
+    // mu = S^H lambda
+    HIPCHK(h, ems::launch_s_apply(h, (const double2 *)lam, mu, nrhs, true, st));
+    HIPCHK(h, ems::launch_repack(h, E, G, gpad, nrhs, st));
+    HIPCHK(h, ems::launch_repack(h, E, mu, mpad, nrhs, st));
+    int r2 = apply_impl(E, gpad, ae, nrhs, EMS_PART_FREE | EMS_PART_REFL, false, st);
+    if (r2) return fail(h, r2, std::string("extended apply: ") + E->err);
+    r2 = apply_impl(E, mpad, ze, nrhs, EMS_PART_FREE | EMS_PART_REFL, true, st);
+    if (r2) return fail(h, r2, std::string("extended adjoint apply: ") + E->err);
+    r2 = ems_eval_scattered_adjoint(E, res, nrhs, npts, pts, fe, st);
+    if (r2) return fail(h, r2, std::string("extended field adjoint: ") + E->err);
+    r2 = ems_incident(E, waves, nrhs, a0e, st);
+    if (r2) return fail(h, r2, std::string("extended incident: ") + E->err);
+    HIPCHK(h, ems::launch_grad_centres(h, E, G, mu, ae, a0e, fe, ze, nrhs, dxy, st));
+    // Lame parameters: node term
+    HIPCHK(h, ems::launch_somm_aggregate(h, G, nrhs, false, false, st));
+    HIPCHK(h, ems::launch_lame_ig(h, nrhs, Ig, st));
+    HIPCHK(h, ems::launch_somm_aggregate(h, mu, nrhs, true, false, st));
+    HIPCHK(h, ems::launch_lame_lam(h, nrhs, Lam, false, st));
+    HIPCHK(h, ems::launch_field_refl_adjoint(h, (const double2 *)res, nrhs, npts, pts, st));
+    HIPCHK(h, ems::launch_lame_lam(h, nrhs, Lam, true, st));
+    HIPCHK(h, ems::launch_lame_reduce(h, nrhs, Ig, Lam, part, kBlocks, st));
+    // right-hand-side term: the reflected plane wave with dR(xi0) in place of R(xi0)
+    const cd I(0.0, 1.0);
+    std::vector<double2> pw[2];
+    for (int th = 0; th < 2; ++th) pw[th].resize(7 * (size_t)nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+      const int wv = waves[r].wave;
+      const double k = wv == 0 ? h->md.kp : h->md.ks;
+      const double xi0 = k * std::sin(waves[r].angle);
+      const cd A = 1.0 / (I * k);
+      const cd Ap = wv == 0 ? A : 0.0, As = wv == 1 ? A : 0.0;
+      cd R0[4], dR0[8];
+      if (ems::reflection_deriv(cd(xi0, 0.0), h->md, R0, dR0))
+        return fail(h, EMS_ERR_NUMERIC, "singular interface system at the incident wavenumber");
+      const cd s1 = ems::branch_s(cd(xi0, 0.0), h->md.kp), s2 = ems::branch_s(cd(xi0, 0.0), h->md.ks);
+      for (int th = 0; th < 2; ++th) {
+        const cd *D = dR0 + 4 * th;
+        const cd v[7] = {cd(xi0, 0.0), s1, s2, 0.0, 0.0, D[0] * Ap + D[1] * As, D[2] * Ap + D[3] * As};
+        for (int k2 = 0; k2 < 7; ++k2)
+          pw[th][7 * (size_t)r + k2] = make_double2(v[k2].real(), v[k2].imag());
+      }
+    }
+    double2 *dpw = Ig;  // Ig is consumed by the node reduction above; reuse as upload space
+    for (int th = 0; th < 2; ++th) {
+      HIPCHK(h, hipMemcpyAsync(dpw, pw[th].data(), pw[th].size() * sizeof(double2),
+                               hipMemcpyHostToDevice, st));
+      HIPCHK(h, ems::launch_incident_pw(h, dpw, nrhs, a0dR, st));
+      HIPCHK(h, ems::launch_re_dot((int64_t)nh, mu, a0dR, part + (2 + th) * kBlocks, kBlocks, st));
+      HIPCHK(h, hipStreamSynchronize(st));  // dpw is rewritten for the next parameter
+    }
+    std::vector<double> hp(4 * kBlocks);
+    HIPCHK(h, hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    double s[2] = {0.0, 0.0};
+    for (int b = 0; b < kBlocks; ++b) {
+      s[0] += hp[2 * b];
+      s[1] += hp[2 * b + 1];
+    }
+    for (int b = 0; b < kBlocks; ++b) {
+      s[0] += hp[2 * kBlocks + b];
+      s[1] += hp[3 * kBlocks + b];
+    }
+    dlame[0] = s[0];
+    dlame[1] = s[1];
+    return EMS_OK;
+  };
+  rc = run();
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  return rc;
 }

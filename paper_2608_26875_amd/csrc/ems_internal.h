@@ -17,8 +17,11 @@ using cd = std::complex<double>;
 
 // Largest truncation order the kernels are built for: one wavefront (64
 // lanes) holds the 2(2p+1) <= 62 coefficients of one particle.
-constexpr int kMaxP = 15;
+constexpr int kMaxP = 16;
 constexpr int kMaxModes = 2 * kMaxP + 1;
+// blocks of the vector reductions (launch_norm2, launch_mdot): each writes
+// kRedBlocks complex partials per reduced vector into its scratch argument
+constexpr int kRedBlocks = 512;
 
 struct Media {
   double lam_h, mu_h, rho_h, lam_b, mu_b, rho_b, omega;
@@ -65,6 +68,8 @@ void node_s(cd xi, double bp, double d, const Media &md, cd out[4]);
 // with the four branch values s given (node_s) or formed from xi.
 int reflection(cd xi, const Media &md, cd R[4]);
 int reflection_s(cd xi, const cd s[4], const Media &md, cd R[4]);
+int reflection_deriv_s(cd xi, const cd s4[4], const Media &md, cd R[4], cd dR[8]);
+int reflection_deriv(cd xi, const Media &md, cd R[4], cd dR[8]);
 
 // Closed-form disk scattering matrix, row-major (4p+2)^2.
 int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S);
@@ -144,6 +149,7 @@ struct ems_handle {
   // node table on device (structure of arrays)
   double2 *d_xi = nullptr, *d_w = nullptr, *d_sp = nullptr, *d_ss = nullptr;
   double2 *d_R = nullptr;        // [q][4]
+  double2 *d_dR = nullptr;       // [q][8]: dR/dlambda_b, dR/dmu_b (substrate), row-major 2x2
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
   float2 *d_Eagg32 = nullptr, *d_Edis32 = nullptr;  // complex64 copies for the mixed form (optional)
@@ -189,12 +195,18 @@ struct ems_handle {
   size_t tmp_bytes = 0;
   double *d_red = nullptr;       // reduction partials
   size_t red_bytes = 0;
+  // operator with orders p + 1 and S = I on the same geometry (gradient)
+  ems_handle *ext = nullptr;
   // mixed-precision refinement: residual and correction [nrhs][ncoef]
   double2 *d_irR = nullptr, *d_irD = nullptr;
   size_t ir_bytes = 0;
 };
 
 namespace ems {
+
+// threads of the one-workgroup-per-particle kernels: one lane per row of a
+// particle block, 2 (2 pmax + 1) rows
+inline int part_threads(const ems_handle *h) { return 2 * (2 * h->pmax + 1) <= 64 ? 64 : 128; }
 
 // Records HIP events around one launch when profiling is on.
 struct ProfScope {
@@ -257,8 +269,25 @@ hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c,
 hipError_t launch_axpy(double2 *y, const double2 *x, int64_t n, double a, hipStream_t st);
 
 // field evaluation
+hipError_t launch_repack(const ems_handle *src, const ems_handle *dst, const double2 *in,
+                         double2 *out, int nrhs, hipStream_t st);
+hipError_t launch_grad_centres(const ems_handle *h, const ems_handle *e, const double2 *gam,
+                               const double2 *mu, const double2 *ae, const double2 *a0e,
+                               const double2 *fe, const double2 *ze, int nrhs, double *dxy,
+                               hipStream_t st);
+hipError_t launch_lame_ig(const ems_handle *h, int nrhs, double2 *Ig, hipStream_t st);
+hipError_t launch_lame_lam(const ems_handle *h, int nrhs, double2 *Lam, bool accumulate,
+                           hipStream_t st);
+hipError_t launch_lame_reduce(const ems_handle *h, int nrhs, const double2 *Ig,
+                              const double2 *Lam, double *part, int blocks, hipStream_t st);
+hipError_t launch_re_dot(int64_t len, const double2 *a, const double2 *b, double *part,
+                         int blocks, hipStream_t st);
 hipError_t launch_field_direct(const ems_handle *h, const double2 *gamma, int nrhs, int npts,
                                const double *pts, double2 *u, hipStream_t st);
+hipError_t launch_field_direct_adjoint(const ems_handle *h, const double2 *res, int nrhs,
+                                       int npts, const double *pts, double2 *g, hipStream_t st);
+hipError_t launch_field_refl_adjoint(const ems_handle *h, const double2 *res, int nrhs, int npts,
+                                     const double *pts, hipStream_t st);
 hipError_t launch_field_refl(const ems_handle *h, int nrhs, int npts, const double *pts,
                              double2 *u, hipStream_t st);
 

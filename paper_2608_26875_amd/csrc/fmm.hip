@@ -100,7 +100,7 @@ __global__ void conj_flip_kernel(const int *__restrict__ p, const int64_t *__res
 
 hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out, int nrhs,
                             hipStream_t st) {
-  hipLaunchKernelGGL(conj_flip_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->d_p, h->d_off, in, out,
+  hipLaunchKernelGGL(conj_flip_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->d_p, h->d_off, in, out,
                      h->ncoef);
   return hipGetLastError();
 }

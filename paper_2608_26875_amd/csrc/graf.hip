@@ -7,8 +7,9 @@
 // The adjoint (conjugate transpose) maps target-side vectors back to the
 // sources with conj(t_{-nu}).
 //
-// One 64-lane workgroup per output particle: lanes 0..31 own the P modes,
-// lanes 32..63 the S modes of that particle.  Partners are taken 16 at a
+// One workgroup of 2 ROWS lanes per output particle (ROWS = 32 for orders up
+// to 15, 64 for order 16): lanes [0, ROWS) own the P modes, [ROWS, 2 ROWS)
+// the S modes of that particle.  Partners are taken 16 at a
 // time; 32 lanes build the 16 x 2 Toeplitz symbols in LDS (Hankel functions
 // by forward recurrence from H_0, H_1, stable because |Y_nu| dominates), then
 // every lane runs its row of the Toeplitz product against the partner
@@ -34,7 +35,7 @@ __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
 
 template <int PM, bool MIXED>
-__global__ __launch_bounds__(64) void graf_direct_kernel(
+__global__ __launch_bounds__(128) void graf_direct_kernel(
     int n, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint,
@@ -43,6 +44,7 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
   constexpr int NT = 4 * PM + 1;
   constexpr int NM = 2 * PM + 1;
   constexpr int SB = 16;
+  constexpr int ROWS = 2 * PM + 1 <= 32 ? 32 : 64;
   __shared__ T t_lds[2][SB][NT];
   __shared__ T c_lds[SB][2][NM];
 
@@ -51,8 +53,8 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
   const int lane = threadIdx.x;
   const double bx = xy[2 * b], by = xy[2 * b + 1];
   const int pb = p[b];
-  const int w = lane >> 5;
-  const int i = (lane & 31) - PM;
+  const int w = lane / ROWS;
+  const int i = lane % ROWS - PM;
   const double2 *xr = x + (int64_t)r * ldx;
   T acc;
   acc.x = 0;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
         }
       }
     }
-    for (int e = lane; e < SB * 2 * NM; e += 64) {
+    for (int e = lane; e < SB * 2 * NM; e += 2 * ROWS) {
       const int s = e / (2 * NM), rem = e - s * (2 * NM);
       const int ww = rem / NM, jj = rem - ww * NM - PM;
       const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
@@ -139,11 +141,11 @@ __global__ __launch_bounds__(64) void graf_direct_kernel(
 #define EMS_GRAF_CASE(PMV)                                                                   \
   case PMV:                                                                                  \
     if (mixed)                                                                               \
-      hipLaunchKernelGGL((graf_direct_kernel<PMV, true>), grid, dim3(64), 0, st, h->n,       \
+      hipLaunchKernelGGL((graf_direct_kernel<PMV, true>), grid, dim3(graf_threads(PMV)), 0, st, h->n, \
                          h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
                          h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
     else                                                                                     \
-      hipLaunchKernelGGL((graf_direct_kernel<PMV, false>), grid, dim3(64), 0, st, h->n,      \
+      hipLaunchKernelGGL((graf_direct_kernel<PMV, false>), grid, dim3(graf_threads(PMV)), 0, st, h->n, \
                          h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
                          h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
     break;
@@ -153,8 +155,11 @@ int pm_bucket(int pmax) {
   if (pmax <= 8) return 8;
   if (pmax <= 10) return 10;
   if (pmax <= 12) return 12;
-  return 15;
+  if (pmax <= 15) return 15;
+  return 16;
 }
+
+static constexpr int graf_threads(int pm) { return 2 * pm + 1 <= 32 ? 64 : 128; }
 
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
                               bool adjoint, bool mixed, hipStream_t st) {
@@ -167,6 +172,7 @@ hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *ou
     EMS_GRAF_CASE(10)
     EMS_GRAF_CASE(12)
     EMS_GRAF_CASE(15)
+    EMS_GRAF_CASE(16)
     default:
       return hipErrorInvalidValue;
   }

@@ -11,13 +11,13 @@
 
 namespace ems {
 
-// One wavefront per particle; lane = row of the particle block.
-__global__ __launch_bounds__(64) void combine_kernel(
+// One workgroup per particle (64 or 128 lanes); lane = row of the particle block.
+__global__ __launch_bounds__(128) void combine_kernel(
     const int *__restrict__ p, const int64_t *__restrict__ off,
     const int64_t *__restrict__ Soff, const double2 *__restrict__ St,
     const double2 *__restrict__ x, double2 *__restrict__ y, const double2 *__restrict__ fre,
     const double2 *__restrict__ dis, int chunks, int64_t ncoef, int flags, int sign) {
-  __shared__ double2 v[64];
+  __shared__ double2 v[2 * kMaxModes];
   const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
   const int pm = p[m];
   const int N = 2 * pm + 1, K = 2 * N;
@@ -51,11 +51,11 @@ __global__ __launch_bounds__(64) void combine_kernel(
 }
 
 // y_m = S_m c_m (adjoint = 0) or S_m^H c_m (adjoint = 1)
-__global__ __launch_bounds__(64) void s_apply_kernel(
+__global__ __launch_bounds__(128) void s_apply_kernel(
     const int *__restrict__ p, const int64_t *__restrict__ off,
     const int64_t *__restrict__ Soff, const double2 *__restrict__ St,
     const double2 *__restrict__ c, double2 *__restrict__ y, int64_t ncoef, int adjoint) {
-  __shared__ double2 v[64];
+  __shared__ double2 v[2 * kMaxModes];
   const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
   const int pm = p[m];
   const int K = 2 * (2 * pm + 1);
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64) void s_apply_kernel(
 
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
                           bool adjoint, hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->d_p, h->d_off,
+  hipLaunchKernelGGL(combine_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->d_p, h->d_off,
                      h->d_Soff, h->d_S, x, y, h->d_free, h->d_dis, h->dis_chunks, h->ncoef,
                      flags, adjoint ? 0 : 1);
   return hipGetLastError();
@@ -84,7 +84,7 @@ hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int
 
 hipError_t launch_s_apply(const ems_handle *h, const double2 *c, double2 *y, int nrhs,
                           bool adjoint, hipStream_t st) {
-  hipLaunchKernelGGL(s_apply_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->d_p, h->d_off,
+  hipLaunchKernelGGL(s_apply_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->d_p, h->d_off,
                      h->d_Soff, h->d_S, c, y, h->ncoef, adjoint ? 1 : 0);
   return hipGetLastError();
 }
@@ -141,7 +141,7 @@ __global__ void incident_kernel(int n, const double *__restrict__ xy, const int 
 
 hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, double2 *c,
                               hipStream_t st) {
-  hipLaunchKernelGGL(incident_kernel, dim3(h->n, nrhs), dim3(64), 0, st, h->n, h->d_xy, h->d_p,
+  hipLaunchKernelGGL(incident_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->n, h->d_xy, h->d_p,
                      h->d_off, pw, h->md.kp, h->md.ks, c, h->ncoef);
   return hipGetLastError();
 }
@@ -149,7 +149,6 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
 // ---------------------------------------------------------------------------
 // GMRES vector kernels.  Reductions write one partial per block and are
 // finished by a single-block kernel in a fixed order (reproducible).
-constexpr int kRedBlocks = 512;
 
 __device__ __forceinline__ double2 warp_reduce(double2 v) {
   for (int o = 32; o > 0; o >>= 1) {

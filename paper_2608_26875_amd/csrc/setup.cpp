@@ -300,6 +300,35 @@ void node_s(cd xi, double bp, double d, const Media &md, cd out[4]) {
   }
 }
 
+// Derivatives of the potential columns with respect to the substrate's
+// Lame parameters: explicit dependence plus the dependence through q.
+static void dpcol(cd xi, cd q, cd dq, double lam, double mu, int which, cd c[4]) {
+  const cd I(0.0, 1.0);
+  // d/dq: (0, 1, 2 mu i xi, 2 (lam + 2 mu) q)
+  c[0] = 0.0;
+  c[1] = dq;
+  c[2] = 2.0 * mu * I * xi * dq;
+  c[3] = 2.0 * (lam + 2.0 * mu) * q * dq;
+  if (which == 0) {  // lambda
+    c[3] += q * q - xi * xi;
+  } else {           // mu
+    c[2] += 2.0 * I * xi * q;
+    c[3] += 2.0 * q * q;
+  }
+}
+static void dscol(cd xi, cd q, cd dq, double mu, int which, cd c[4]) {
+  const cd I(0.0, 1.0);
+  // d/dq: (-1, 0, -2 mu q, 2 mu i xi)
+  c[0] = -dq;
+  c[1] = 0.0;
+  c[2] = -2.0 * mu * q * dq;
+  c[3] = 2.0 * mu * I * xi * dq;
+  if (which == 1) {  // mu
+    c[2] += -(q * q + xi * xi);
+    c[3] += 2.0 * I * xi * q;
+  }
+}
+
 int reflection(cd xi, const Media &md, cd R[4]) {
   cd s[4];
   node_s(xi, 0.0, 0.0, md, s);
@@ -429,6 +458,101 @@ int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S) {
     S[(size_t)(N + k) * K + N + k] = B[3];
   }
   return EMS_OK;
+}
+
+// R(xi) and its derivatives with respect to the substrate's lambda and mu
+// (Section 2.2 system differentiated): with M X = -B, only the substrate
+// columns of M depend on (lambda_b, mu_b), explicitly and through
+// s_pb = sqrt(xi^2 - kpb^2), s_sb = sqrt(xi^2 - ksb^2), kpb^2 = w^2 rho_b /
+// (lambda_b + 2 mu_b), ksb^2 = w^2 rho_b / mu_b; then dX = -M^{-1} (dM) X.
+// dR[0..3]: d/dlambda_b, dR[4..7]: d/dmu_b (row-major 2x2 blocks).
+int reflection_deriv_s(cd xi, const cd s4[4], const Media &md, cd R[4], cd dR[8]) {
+  const cd sp = s4[0], ss = s4[1], spb = s4[2], ssb = s4[3];
+  cd M[4][4], B[4][2], c[4];
+  auto put = [&](int col, const cd *v, double sg) {
+    for (int r = 0; r < 4; ++r) M[r][col] = sg * v[r];
+  };
+  pcol(xi, sp, md.lam_h, md.mu_h, c);
+  put(0, c, 1.0);
+  scol(xi, ss, md.lam_h, md.mu_h, c);
+  put(1, c, 1.0);
+  pcol(xi, -spb, md.lam_b, md.mu_b, c);
+  put(2, c, -1.0);
+  scol(xi, -ssb, md.lam_b, md.mu_b, c);
+  put(3, c, -1.0);
+  pcol(xi, -sp, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) B[r][0] = -c[r];
+  scol(xi, -ss, md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) B[r][1] = -c[r];
+  // LU with partial pivoting (row permutation kept in perm)
+  int perm[4] = {0, 1, 2, 3};
+  cd LU[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int cc = 0; cc < 4; ++cc) LU[r][cc] = M[r][cc];
+  for (int k = 0; k < 4; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < 4; ++r)
+      if (std::abs(LU[r][k]) > std::abs(LU[piv][k])) piv = r;
+    if (std::abs(LU[piv][k]) == 0.0) return EMS_ERR_NUMERIC;
+    if (piv != k) {
+      for (int cc = 0; cc < 4; ++cc) std::swap(LU[k][cc], LU[piv][cc]);
+      std::swap(perm[k], perm[piv]);
+    }
+    for (int r = k + 1; r < 4; ++r) {
+      LU[r][k] /= LU[k][k];
+      for (int cc = k + 1; cc < 4; ++cc) LU[r][cc] -= LU[r][k] * LU[k][cc];
+    }
+  }
+  auto solve = [&](const cd rhs[4], cd x[4]) {
+    cd y[4];
+    for (int r = 0; r < 4; ++r) {
+      cd v = rhs[perm[r]];
+      for (int cc = 0; cc < r; ++cc) v -= LU[r][cc] * y[cc];
+      y[r] = v;
+    }
+    for (int r = 3; r >= 0; --r) {
+      cd v = y[r];
+      for (int cc = r + 1; cc < 4; ++cc) v -= LU[r][cc] * x[cc];
+      x[r] = v / LU[r][r];
+    }
+  };
+  cd X[2][4];
+  for (int col = 0; col < 2; ++col) {
+    const cd rhs[4] = {B[0][col], B[1][col], B[2][col], B[3][col]};
+    solve(rhs, X[col]);
+  }
+  R[0] = X[0][0];
+  R[1] = X[1][0];
+  R[2] = X[0][1];
+  R[3] = X[1][1];
+  const double lp = md.lam_b + 2.0 * md.mu_b;
+  const double kpb2 = md.kpb * md.kpb, ksb2 = md.ksb * md.ksb;
+  for (int which = 0; which < 2; ++which) {
+    // ds/dtheta (s = sqrt(xi^2 - k^2), k^2 depends on theta)
+    const cd dspb = (which == 0 ? 1.0 : 2.0) * kpb2 / (2.0 * spb * lp);
+    const cd dssb = which == 0 ? cd(0.0) : cd(ksb2 / (2.0 * ssb * md.mu_b));
+    cd dM2[4], dM3[4];
+    // columns 2, 3 are -pcol(xi, -spb), -scol(xi, -ssb): q = -s, dq = -ds
+    dpcol(xi, -spb, -dspb, md.lam_b, md.mu_b, which, dM2);
+    dscol(xi, -ssb, -dssb, md.mu_b, which, dM3);
+    for (int col = 0; col < 2; ++col) {
+      cd rhs[4], dx[4];
+      for (int r = 0; r < 4; ++r) rhs[r] = dM2[r] * X[col][2] + dM3[r] * X[col][3];  // -(dM) X
+      solve(rhs, dx);
+      // row-major 2x2: dR[row][col]
+      dR[4 * which + 0 * 2 + col] = dx[0];
+      dR[4 * which + 1 * 2 + col] = dx[1];
+    }
+  }
+  for (int i = 0; i < 8; ++i)
+    if (!std::isfinite(dR[i].real()) || !std::isfinite(dR[i].imag())) return EMS_ERR_NUMERIC;
+  return EMS_OK;
+}
+
+int reflection_deriv(cd xi, const Media &md, cd R[4], cd dR[8]) {
+  cd s[4];
+  node_s(xi, 0.0, 0.0, md, s);
+  return reflection_deriv_s(xi, s, md, R, dR);
 }
 
 }  // namespace ems

@@ -453,6 +453,7 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
       EMS_AGGM_CASE(10)
       EMS_AGGM_CASE(12)
       EMS_AGGM_CASE(15)
+      EMS_AGGM_CASE(16)
       default:
         return hipErrorInvalidValue;
     }
@@ -466,6 +467,7 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
     EMS_AGG_CASE(10)
     EMS_AGG_CASE(12)
     EMS_AGG_CASE(15)
+    EMS_AGG_CASE(16)
     default:
       return hipErrorInvalidValue;
   }
@@ -517,6 +519,7 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
       EMS_DISM_CASE(10)
       EMS_DISM_CASE(12)
       EMS_DISM_CASE(15)
+      EMS_DISM_CASE(16)
       default:
         return hipErrorInvalidValue;
     }
@@ -530,6 +533,7 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
     EMS_DIS_CASE(10)
     EMS_DIS_CASE(12)
     EMS_DIS_CASE(15)
+    EMS_DIS_CASE(16)
     default:
       return hipErrorInvalidValue;
   }

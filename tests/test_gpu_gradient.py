@@ -1,0 +1,66 @@
+"""GPU parity of the adjoint field and of the misfit gradient (centres and
+substrate Lame parameters) against the oracle's forward-mode gradient.
+
+Tolerances: the adjoint field by the dot-product identity <res, F g> =
+<F^H res, g> to 1e-12; the gradient to 1e-8 of its largest entry (both
+solves to 1e-12, the Sommerfeld rules and the oracle's quadrature to
+~1e-13 of the operator, amplified by the condition number of A, ~10 here).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import oracle_media, product_operator, rel, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import gradient as G  # noqa: E402
+from oracle import smatrix  # noqa: E402
+
+
+def _case(n, p, seed):
+    w = W.small_cloud(n, seed=seed, p=p, omega=4.0, width=2.0 * n + 2.0, depth=(1.0, 3.0),
+                      ragged=True)
+    pts = np.stack([np.linspace(-1.0, 2.0 * n + 3.0, 7), np.full(7, -0.4)], 1)
+    waves = [(0, math.radians(25)), (1, math.radians(-40))]
+    rng = np.random.default_rng(seed)
+    u_obs = (rng.normal(size=(2, 7, 2)) + 1j * rng.normal(size=(2, 7, 2))) * 0.1
+    return w, pts, waves, u_obs
+
+
+def test_field_adjoint_dot_product():
+    w, pts, _, _ = _case(6, 4, 31)
+    op = product_operator(w)
+    op.build()
+    g = W.random_coeffs(w.n_coeff, 9, nrhs=2)
+    rng = np.random.default_rng(1)
+    res = rng.normal(size=(2, len(pts), 2)) + 1j * rng.normal(size=(2, len(pts), 2))
+    u = to_np(op.scattered_field(to_gpu(g), pts))
+    fh = to_np(op.scattered_field_adjoint(torch.from_numpy(res).cuda(), pts))
+    for r in range(2):
+        lhs = np.vdot(res[r].ravel(), u[r].ravel())
+        rhs = np.vdot(fh[r], g[r])
+        assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(res[r]) * np.linalg.norm(u[r]), (lhs, rhs)
+
+
+@pytest.mark.parametrize("n,p,seed", [(3, 3, 21), (5, 5, 44)])
+def test_gradient_against_oracle(n, p, seed):
+    w, pts, waves, u_obs = _case(n, p, seed)
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    J0, gxy0, gl0 = G.gradient(w, m, S, waves, pts, u_obs)
+    op = product_operator(w)
+    op.build()
+    J, gxy, gl, info = op.misfit_gradient(waves, pts, u_obs, tol=1e-12)
+    print("J", J, J0, "info", info, flush=True)
+    print("dxy", np.abs(gxy - gxy0).max(), np.abs(gxy0).max(), "lame", gl, gl0, flush=True)
+    assert abs(J - J0) <= 1e-10 * J0
+    scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
+    assert np.abs(gxy - gxy0).max() <= 1e-8 * scale
+    assert np.abs(np.asarray(gl) - gl0).max() <= 1e-8 * scale
