@@ -33,9 +33,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c0", "c1", "c2", "c3", "c4"],
+                    help="c2: the headline single-vector apply; c3: 64-RHS block applies at "
+                         "three frequencies; c4: misfit + gradient at 5000 particles")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--solve", action="store_true", help="also time a GMRES solve to 1e-9")
+    ap.add_argument("--solve-its", type=int, default=0,
+                    help="iteration budget of the GMRES measurement (0: none)")
+    ap.add_argument("--nrhs", type=int, default=64, help="block size of the c3 measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2)
     ap.add_argument("--fmm-leaf", type=int, default=0, help="particles per FMM leaf (0 = library default)")
@@ -157,6 +162,103 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
+def bench_c3(args):
+    """Block applies of 64 right-hand sides (the 64 incident directions) at the
+    three frequencies of the uneven-order cloud; tile shapes autotuned."""
+    import numpy as np
+    import torch
+    import paper_2608_26875_amd as E
+    import workloads as W
+    mixed = args.precision == "mixed"
+    flags = E.EMS_APPLY_ALL | (E.EMS_MIXED if mixed else 0)
+    per = []
+    tot_ms = 0.0
+    for f in range(3):
+        w = W.c3_cloud(f)
+        op = E.Operator(w.xy, w.radius, w.p, E.make_media(w.host, w.substrate, w.omega), bc=w.bc)
+        info = op.build()
+        tune = op.autotune(args.nrhs)
+        x = op.incident(w.incidence[:args.nrhs])
+        y = torch.empty_like(x)
+        for _ in range(args.warmup):
+            op.apply(x, y, flags=flags)
+        torch.cuda.synchronize()
+        op.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            op.apply(x, y, flags=flags)
+        e1.record()
+        torch.cuda.synchronize()
+        op.profile(False)
+        ms = e0.elapsed_time(e1) / args.steps
+        kt = op.profile_read()
+        tot_ms += ms
+        per.append({"omega": w.omega, "p_range": [int(w.p.min()), int(w.p.max())],
+                    "n_coeff": int(w.n_coeff), "q_nodes": info["q"], "ms_per_block_apply": ms,
+                    "tiles": tune,
+                    "kernels": {k: {"avg_ms": v[1] / v[0],
+                                    "tflops": (v[2] / (v[1] * 1e-3) / 1e12) if v[2] else None}
+                                for k, v in kt.items()}})
+        print(json.dumps({"c3_frequency": f, **per[-1]}), file=sys.stderr, flush=True)
+        del op
+        torch.cuda.empty_cache()
+    nrhs = args.nrhs
+    out = {"metric": "block applies/s (64 RHS, 3 frequencies), 20000 particles, uneven p",
+           "value": 3.0 * 1e3 / tot_ms, "unit": "block applies/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": tot_ms / 3.0,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64+c128" if mixed else "c128", "data": "synthetic",
+           "config": {"workload": f"c3: 20000 particles, p_i = ceil(ks a_i) + 8, {nrhs} RHS x "
+                                  f"omega 2/4/8, {'mixed' if mixed else 'FP64'} block apply",
+                      "parallelism": "single GPU"},
+           "rhs_applies_per_s": 3.0 * nrhs * 1e3 / tot_ms, "per_frequency": per}
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(args):
+    """Misfit and gradient (centres + substrate Lame parameters) at 5000
+    particles, 32 P waves, 1024 receivers: forward solves, field, adjoint
+    right-hand side, adjoint solves, vector-Jacobian product."""
+    import numpy as np
+    import torch
+    import paper_2608_26875_amd as E
+    import workloads as W
+    w = W.c4_cloud()
+    pts = W.c4_receivers()
+    waves = w.incidence
+    its = args.solve_its or 300
+    # observed data from the true configuration
+    op = E.Operator(w.xy, w.radius, w.p, E.make_media(w.host, w.substrate, w.omega), bc=w.bc)
+    op.build()
+    b = op.incident(waves)
+    g, i0 = op.solve(b, tol=1e-9, restart=its, maxit=its)
+    u_obs = op.scattered_field(g, pts)
+    torch.cuda.synchronize()
+    del op
+    ws, sub = W.c4_start(w)
+    op = E.Operator(ws.xy, ws.radius, ws.p, E.make_media(ws.host, sub, ws.omega), bc=ws.bc)
+    t0 = time.perf_counter()
+    op.build()
+    t_build = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, gxy, gl, info = op.misfit_gradient(waves, pts, u_obs, tol=1e-9, restart=its, maxit=its,
+                                          precision=1 if args.precision == "mixed" else 0)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    out = {"metric": "misfit + gradient seconds, 5000 particles, 32 P waves, 1024 receivers",
+           "value": secs, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": secs * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c128" if args.precision == "fp64" else "c64+c128", "data": "synthetic",
+           "config": {"workload": "c4: 5000 particles, p=15, omega=8, gradient w.r.t. 10000 centre "
+                                  "coordinates + substrate lambda, mu", "parallelism": "single GPU",
+                      "gmres_budget": its},
+           "J": J, "grad_norm_centres": float(np.linalg.norm(gxy)), "grad_lame": list(gl),
+           "true_data_solve": i0, "solves": info, "build_s": t_build}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -172,6 +274,10 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
     w = workload(args.workload)
     media = E.make_media(w.host, w.substrate, w.omega)
     t0 = time.perf_counter()
@@ -179,6 +285,7 @@ def main():
     if args.fmm_leaf:
         op.set_fmm(mode=0, leaf=args.fmm_leaf)
     info = op.build()
+    tiles = op.autotune(1)
     setup_s = time.perf_counter() - t0
     x = torch.from_numpy(W.random_coeffs(w.n_coeff, 1002)).cuda()
     y = torch.empty_like(x)
@@ -234,14 +341,19 @@ def main():
         "roofline": roof,
         "kernels": per_kernel,
         "setup_s": setup_s,
+        "tiles": tiles,
     }
-    if args.solve:
+    if args.solve or args.solve_its:
+        # GMRES to 1e-9 within an iteration budget (restart = budget): the
+        # time, the iterations and the residual reached are all reported
+        its = args.solve_its or 3000
         b = op.incident([w.incidence[0]])
         torch.cuda.synchronize()
-        xs, sinfo = op.solve(b, tol=1e-9, restart=300, maxit=3000,
+        xs, sinfo = op.solve(b, tol=1e-9, restart=min(its, 300), maxit=its,
                              precision=0 if args.precision == "fp64" else 1)
         out["gmres"] = sinfo
         out["gmres_solve_s"] = sinfo["seconds"]
+        out["gmres_s_per_iteration"] = sinfo["seconds"] / max(sinfo["iters"], 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
     print(json.dumps(out), flush=True)

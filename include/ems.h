@@ -267,6 +267,17 @@ int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, cons
                   const void *lam, int32_t npts, const double *pts, const void *res, double *dxy,
                   double *dlame, ems_stream_t stream);
 
+/* Tile autotuner of the matrix-core Sommerfeld contractions: times each
+ * compiled tile shape (nodes or particles per wave NT, right-hand sides per
+ * wave RB) of the aggregate and disaggregate, FP64 and (when its complex64
+ * tables exist) FP32, on this handle's tables at batch size nrhs, and keeps
+ * the fastest for applies with one (nrhs = 1) or several (nrhs > 1)
+ * right-hand sides.  chosen (host, may be NULL) receives
+ * {agg FP64 NT, RB, agg FP32 NT, RB, dis FP64 NT, RB, dis FP32 NT, RB}
+ * (zeros for forms not tuned; all zeros when the tables were not built).
+ * Synchronous; results of later applies are unchanged up to rounding order. */
+int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_stream_t stream);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel the library queues.  ems_profile(h, 1) clears and starts
  * recording, ems_profile(h, 0) stops.  ems_profile_read synchronizes on the

@@ -107,6 +107,7 @@ def _load():
                                P], I32),
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
         "ems_eval_scattered_adjoint": ([P, P, I32, I32, P, P, P], I32),
+        "ems_autotune": ([P, I32, ctypes.POINTER(ctypes.c_int32), P], I32),
         "ems_param_vjp": ([P, ctypes.POINTER(PlaneWave), I32, P, P, I32, P, P, P,
                            ctypes.POINTER(ctypes.c_double), P], I32),
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
@@ -127,7 +128,7 @@ _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
-            "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp",
+            "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
             "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
@@ -345,6 +346,14 @@ class Operator:
         dxy, dl = self.param_vjp(waves, gam, lam, pts, res)
         return J, dxy.cpu().numpy(), dl, {"forward": i1, "adjoint": i2}
 
+    def autotune(self, nrhs=1, stream=None) -> dict:
+        """Time the matrix-core tile shapes for batches of nrhs; returns the choice."""
+        out = (ctypes.c_int32 * 8)()
+        self._check(_lib.ems_autotune(self.h, int(nrhs), out, _stream_ptr(stream)))
+        v = list(out)
+        return {"aggregate_fp64": tuple(v[0:2]), "aggregate_fp32": tuple(v[2:4]),
+                "disaggregate_fp64": tuple(v[4:6]), "disaggregate_fp32": tuple(v[6:8])}
+
     def scattered_field_adjoint(self, res, pts, stream=None):
         """g = F^H res for residuals res [nrhs, npts, 2] at host points pts [npts, 2]."""
         import torch
@@ -400,3 +409,45 @@ class Operator:
                 self.h = ctypes.c_void_p()
         except Exception:
             pass
+
+
+def _autograd_misfit():
+    import torch
+
+    class MisfitFunction(torch.autograd.Function):
+        """J(xy, lame) = 1/2 sum over plane waves and receivers |u - u_obs|^2.
+
+        Forward builds the operator at the given centres and substrate Lame
+        parameters, solves the forward and adjoint systems on the GPU and keeps
+        the gradient; backward scales it by the incoming gradient.  Centres
+        [n, 2] and lame (lambda_b, mu_b) are float64 tensors."""
+
+        @staticmethod
+        def forward(ctx, xy, lame, radius, p, host, substrate_rho, omega, bc, waves, pts,
+                    u_obs, S_blocks, sommerfeld, fmm, tol):
+            media = make_media(host, (float(lame[0]), float(lame[1]), float(substrate_rho)), omega)
+            op = Operator(xy.detach().cpu().numpy(), radius, p, media, S_blocks=S_blocks, bc=bc,
+                          sommerfeld=sommerfeld, fmm=fmm)
+            op.build()
+            J, gxy, gl, _ = op.misfit_gradient(waves, pts, u_obs, tol=tol)
+            ctx.save_for_backward(torch.as_tensor(gxy, dtype=torch.float64),
+                                  torch.tensor(gl, dtype=torch.float64))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            gxy, gl = ctx.saved_tensors
+            return (gout * gxy.to(gout.device), gout * gl.to(gout.device)) + (None,) * 13
+
+    return MisfitFunction
+
+
+def misfit(xy, lame, *, radius, p, host, substrate_rho, omega, waves, pts, u_obs, bc=None,
+           S_blocks=None, sommerfeld=None, fmm=None, tol=1e-12):
+    """Differentiable receiver misfit (torch.autograd): J as a 0-d tensor whose
+    gradient flows to the centres ``xy`` [n, 2] and to ``lame`` = (lambda_b,
+    mu_b).  Each call builds the operator at the given parameters."""
+    fn = _autograd_misfit()
+    return fn.apply(xy, lame, radius, p, host, substrate_rho, omega, bc, waves, pts, u_obs,
+                    S_blocks, sommerfeld, fmm, tol)
+

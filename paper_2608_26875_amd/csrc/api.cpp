@@ -1266,3 +1266,58 @@ extern "C" int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t
   (void)hipFree(buf);
   return rc;
 }
+
+extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_stream_t stream) {
+  if (!h || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad autotune arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  if (chosen)
+    for (int k = 0; k < 8; ++k) chosen[k] = 0;
+  if (!h->d_Eagg || !h->d_Edis) return EMS_OK;  // no tables: the vector-ALU kernels run
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ensure_ws(h, nrhs);
+  if (rc) return rc;
+  const size_t vec = sizeof(double2) * (size_t)nrhs * h->ncoef;
+  if ((rc = ensure_tmp(h, vec))) return rc;
+  // inputs of the timed launches: zero coefficients and node amplitudes
+  HIPCHK(h, hipMemsetAsync(h->d_tmp, 0, vec, st));
+  HIPCHK(h, hipMemsetAsync(h->d_refl, 0, sizeof(double2) * (size_t)nrhs * 2 * h->q, st));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const int batched = nrhs > 1 ? 1 : 0;
+  for (int kernel = 0; kernel < 2; ++kernel)
+    for (int prec = 0; prec < 2; ++prec) {
+      if (prec == 1 && (!h->d_Eagg32 || !h->d_Edis32)) continue;
+      float best = 1e30f;
+      int bi = -1;
+      for (int idx = 0; idx < 4; ++idx) {
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          HIPCHK(h, hipEventRecord(e0, st));
+          hipError_t e = kernel == 0
+                             ? ems::launch_somm_aggregate_mfma(h, h->d_tmp, nrhs, prec, idx, st)
+                             : ems::launch_somm_disaggregate_mfma(h, nrhs, prec, idx, st);
+          HIPCHK(h, e);
+          HIPCHK(h, hipEventRecord(e1, st));
+          HIPCHK(h, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) tmin = std::min(tmin, ms);  // the first launch warms caches and code
+        }
+        if (tmin < best) {
+          best = tmin;
+          bi = idx;
+        }
+      }
+      h->mfma_cfg[kernel][prec][batched] = bi;
+      if (chosen) {
+        int nt = 0, rb = 0;
+        ems::mfma_candidate(kernel, prec, bi, &nt, &rb);
+        chosen[4 * kernel + 2 * prec] = nt;
+        chosen[4 * kernel + 2 * prec + 1] = rb;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return EMS_OK;
+}

@@ -153,6 +153,9 @@ struct ems_handle {
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
   float2 *d_Eagg32 = nullptr, *d_Edis32 = nullptr;  // complex64 copies for the mixed form (optional)
+  // tile candidate of the matrix-core kernels [aggregate/disaggregate][FP64/FP32]
+  // [one / several right-hand sides]; -1: built-in default (ems_autotune sets it)
+  int mfma_cfg[2][2][2] = {{{-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}}};
   bool p_uniform = false;
   double etab_budget_gb = 96.0;
   // workspaces (sized for ws_nrhs right-hand sides)
@@ -238,6 +241,11 @@ hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out
                             hipStream_t st);
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st);
+hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
+                                      int idx, hipStream_t st);
+hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
+                                         hipStream_t st);
+int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
 hipError_t launch_etables(ems_handle *h, hipStream_t st);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,

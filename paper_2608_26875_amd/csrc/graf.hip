@@ -7,6 +7,9 @@
 // The adjoint (conjugate transpose) maps target-side vectors back to the
 // sources with conj(t_{-nu}).
 //
+// Right-hand sides are taken RB at a time by one workgroup: the symbols of a
+// partner batch are built once and applied to each of them.
+//
 // One workgroup of 2 ROWS lanes per output particle (ROWS = 32 for orders up
 // to 15, 64 for order 16): lanes [0, ROWS) own the P modes, [ROWS, 2 ROWS)
 // the S modes of that particle.  Partners are taken 16 at a
@@ -34,9 +37,9 @@ __device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(
 __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
 
-template <int PM, bool MIXED>
+template <int PM, bool MIXED, int RB>
 __global__ __launch_bounds__(128) void graf_direct_kernel(
-    int n, const double *__restrict__ xy, const int *__restrict__ p,
+    int n, int nrhs, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint,
     const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx) {
@@ -49,16 +52,18 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
   __shared__ T c_lds[SB][2][NM];
 
   const int b = blockIdx.x;
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RB;  // right-hand sides r0 .. r0 + RB - 1 share the symbols
   const int lane = threadIdx.x;
   const double bx = xy[2 * b], by = xy[2 * b + 1];
   const int pb = p[b];
   const int w = lane / ROWS;
   const int i = lane % ROWS - PM;
-  const double2 *xr = x + (int64_t)r * ldx;
-  T acc;
-  acc.x = 0;
-  acc.y = 0;
+  T acc[RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    acc[rr].x = 0;
+    acc[rr].y = 0;
+  }
   // partners: every other particle, or the near list of b
   const int np = nbr_ptr ? nbr_ptr[b + 1] - nbr_ptr[b] : n;
   const int *nl = nbr_ptr ? nbr_idx + nbr_ptr[b] : nullptr;
@@ -109,45 +114,57 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
         }
       }
     }
-    for (int e = lane; e < SB * 2 * NM; e += 2 * ROWS) {
-      const int s = e / (2 * NM), rem = e - s * (2 * NM);
-      const int ww = rem / NM, jj = rem - ww * NM - PM;
-      const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
-      double2 v = make_double2(0.0, 0.0);
-      if (l < n && l != b) {
-        const int pl = p[l];
-        if (jj >= -pl && jj <= pl) v = xr[off[l] + ww * (2 * pl + 1) + jj + pl];
-      }
-      c_lds[s][ww][jj + PM] = CT<MIXED>::from(v);
-    }
-    __syncthreads();
-    if (i <= PM) {
-      for (int s = 0; s < SB; ++s) {
 #pragma unroll
-        for (int jj = 0; jj < NM; ++jj) {
-          const int nu = i - (jj - PM);
-          T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
-          cfma_any(acc, tv, c_lds[s][w][jj]);
+    for (int rr = 0; rr < RB; ++rr) {
+      if (r0 + rr >= nrhs) break;  // uniform over the workgroup
+      const double2 *xr = x + (int64_t)(r0 + rr) * ldx;
+      for (int e = lane; e < SB * 2 * NM; e += 2 * ROWS) {
+        const int s = e / (2 * NM), rem = e - s * (2 * NM);
+        const int ww = rem / NM, jj = rem - ww * NM - PM;
+        const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
+        double2 v = make_double2(0.0, 0.0);
+        if (l < n && l != b) {
+          const int pl = p[l];
+          if (jj >= -pl && jj <= pl) v = xr[off[l] + ww * (2 * pl + 1) + jj + pl];
+        }
+        c_lds[s][ww][jj + PM] = CT<MIXED>::from(v);
+      }
+      __syncthreads();
+      if (i <= PM) {
+        for (int s = 0; s < SB; ++s) {
+#pragma unroll
+          for (int jj = 0; jj < NM; ++jj) {
+            const int nu = i - (jj - PM);
+            T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
+            cfma_any(acc[rr], tv, c_lds[s][w][jj]);
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (i >= -pb && i <= pb)
-    out[(int64_t)r * ldo + off[b] + w * (2 * pb + 1) + i + pb] =
-        make_double2((double)acc.x, (double)acc.y);
+  if (i >= -pb && i <= pb) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+      if (r0 + rr < nrhs)
+        out[(int64_t)(r0 + rr) * ldo + off[b] + w * (2 * pb + 1) + i + pb] =
+            make_double2((double)acc[rr].x, (double)acc[rr].y);
+  }
 }
 
+#define EMS_GRAF_LAUNCH(PMV, MIX, RBV)                                                       \
+  hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV>), dim3(h->n, (nrhs + RBV - 1) / RBV),    \
+                     dim3(graf_threads(PMV)), 0, st, h->n, nrhs, h->d_xy, h->d_p, h->d_off, x,   \
+                     h->ncoef, out, h->ncoef, h->md.kp, h->md.ks, adjoint ? 1 : 0, nptr, nidx)
 #define EMS_GRAF_CASE(PMV)                                                                   \
   case PMV:                                                                                  \
-    if (mixed)                                                                               \
-      hipLaunchKernelGGL((graf_direct_kernel<PMV, true>), grid, dim3(graf_threads(PMV)), 0, st, h->n, \
-                         h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
-                         h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
-    else                                                                                     \
-      hipLaunchKernelGGL((graf_direct_kernel<PMV, false>), grid, dim3(graf_threads(PMV)), 0, st, h->n, \
-                         h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,   \
-                         h->md.ks, adjoint ? 1 : 0, nptr, nidx);                              \
+    if (mixed) {                                                                             \
+      if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, true, 8);                                           \
+      else EMS_GRAF_LAUNCH(PMV, true, 1);                                                    \
+    } else {                                                                                 \
+      if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, false, 8);                                          \
+      else EMS_GRAF_LAUNCH(PMV, false, 1);                                                   \
+    }                                                                                        \
     break;
 
 int pm_bucket(int pmax) {
@@ -163,7 +180,6 @@ static constexpr int graf_threads(int pm) { return 2 * pm + 1 <= 32 ? 64 : 128; 
 
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
                               bool adjoint, bool mixed, hipStream_t st) {
-  dim3 grid(h->n, nrhs);
   const int *nptr = h->fmm_on ? h->d_nbr_ptr : nullptr;
   const int *nidx = h->fmm_on ? h->d_nbr_idx : nullptr;
   switch (pm_bucket(h->pmax)) {

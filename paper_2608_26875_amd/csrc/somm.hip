@@ -26,6 +26,8 @@
 // Partial sums over particle chunks (aggregate) and node chunks
 // (disaggregate) are written separately and reduced in a fixed order, so
 // results are reproducible run to run.
+#include <type_traits>
+
 #include "dev.h"
 #include "ems_internal.h"
 
@@ -241,13 +243,13 @@ template <> struct Mfma<float> {
   __device__ static int row(int kq, int v) { return 4 * kq + v; }
 };
 
-template <typename T, int NT, int NU>
-__device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NU],
-                                           typename Mfma<T>::Acc (&ai)[NT][NU],
-                                           const T (&er)[NT], const T (&ei)[NT], const T (&br)[NU],
-                                           const T (&bi)[NU]) {
+template <typename T, int NT, int NC>
+__device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NC],
+                                           typename Mfma<T>::Acc (&ai)[NT][NC],
+                                           const T (&er)[NT], const T (&ei)[NT], const T (&br)[NC],
+                                           const T (&bi)[NC]) {
 #pragma unroll
-  for (int u = 0; u < NU; ++u) {
+  for (int u = 0; u < NC; ++u) {
     const T nb = -bi[u];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -259,143 +261,159 @@ __device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NU],
   }
 }
 
-template <typename T, int PM, int NT, bool UNI>
+// Column tiles: NU tiles of 16 modes for each of RB right-hand sides (tile
+// c = k NU + u is right-hand side r0 + k, modes 16 u .. 16 u + 15).  nm =
+// 2 PM + 1 of the power tables (PM their padded order), nrhs bounds r0 + k.
+template <typename T, int NU, int NT, int RB, bool UNI>
 __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
-    int n, int q, const int *__restrict__ p, const int64_t *__restrict__ off,
+    int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ x, int64_t ldx, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
     const typename Mfma<T>::C *__restrict__ Etab) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
-  constexpr int NM = 2 * PM + 1, NU = (NM + 15) / 16;
+  constexpr int NC = NU * RB;
+  const int PM = nm >> 1;
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int jb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
-  const int c = blockIdx.y, wave = blockIdx.z & 1, r = blockIdx.z >> 1;
+  const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
   const int m0 = c * per_chunk, m1 = min(n, m0 + per_chunk);
-  const double2 *xr = x + (int64_t)r * ldx;
   const C *Ew = Etab + (int64_t)wave * n * q;
-  Acc ar[NT][NU], ai[NT][NU];
+  Acc ar[NT][NC], ai[NT][NC];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int u = 0; u < NU; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
   int jl[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) jl[t] = min(jb + 16 * t + i16, q - 1);
   C en[NT];
-  double2 xn[NU];
+  double2 xn[NC];
   auto fetch = [&](int m) {
     const int mc = min(m + kq, m1 - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
     // uniform orders: the coefficient address needs no table lookup
     const int pm = UNI ? PM : p[mc];
-    const int64_t base = (UNI ? (int64_t)mc * 2 * NM : off[mc]) + wave * (2 * pm + 1) + pm;
+    const int64_t base = (UNI ? (int64_t)mc * 2 * nm : off[mc]) + wave * (2 * pm + 1) + pm;
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const int nn = 16 * u + i16 - PM;
-      xn[u] = (nn >= -pm && nn <= pm) ? xr[base + nn] : make_double2(0.0, 0.0);
+    for (int k = 0; k < RB; ++k) {
+      const int r = min(r0 + k, nrhs - 1);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int nn = 16 * u + i16 - PM;
+        xn[k * NU + u] = (nn >= -pm && nn <= pm) ? x[(int64_t)r * ldx + base + nn]
+                                                 : make_double2(0.0, 0.0);
+      }
     }
   };
   fetch(m0);
   for (int m = m0; m < m1; m += 4) {
     const bool ok = m + kq < m1;
-    T er[NT], ei[NT], br[NU], bi[NU];
+    T er[NT], ei[NT], br[NC], bi[NC];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       er[t] = en[t].x;
       ei[t] = en[t].y;
     }
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
+    for (int u = 0; u < NC; ++u) {
       br[u] = ok ? (T)xn[u].x : T(0);
       bi[u] = ok ? (T)xn[u].y : T(0);
     }
     fetch(m + 4);
-    mfma_cstep<T, NT, NU>(ar, ai, er, ei, br, bi);
+    mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
   }
   // I_j = sum_k V[j][k] A[j][k]; the 16 lanes of a group hold the 16 columns
   const double2 *Vt = wave ? Vs_t : Vp_t;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
+  for (int k = 0; k < RB; ++k) {
+    const int r = r0 + k;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = jb + 16 * t + Mfma<T>::row(kq, v);
-      const int jc = min(j, q - 1);
-      double re = 0.0, im = 0.0;
+    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int k = 16 * u + i16;
-        if (k < NM) {
-          const double2 w = Vt[(int64_t)jc * NM + k];
-          const double a = (double)ar[t][u][v], b = (double)ai[t][u][v];
-          re += w.x * a - w.y * b;
-          im += w.x * b + w.y * a;
+      for (int v = 0; v < 4; ++v) {
+        const int j = jb + 16 * t + Mfma<T>::row(kq, v);
+        const int jc = min(j, q - 1);
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int kk = 16 * u + i16;
+          if (kk < nm) {
+            const double2 w = Vt[(int64_t)jc * nm + kk];
+            const double a = (double)ar[t][k * NU + u][v], b = (double)ai[t][k * NU + u][v];
+            re += w.x * a - w.y * b;
+            im += w.x * b + w.y * a;
+          }
         }
-      }
 #pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
+        for (int o = 1; o < 16; o <<= 1) {
+          re += __shfl_xor(re, o);
+          im += __shfl_xor(im, o);
+        }
+        if (i16 == 0 && j < q && r < nrhs)
+          agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = make_double2(re, im);
       }
-      if (i16 == 0 && j < q)
-        agg[((int64_t)(r * 2 + wave) * chunks + c) * q + j] = make_double2(re, im);
     }
   }
 }
 
-template <typename T, int PM, int NT>
+template <typename T, int NU, int NT, int RB>
 __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
-    int n, int q, const int *__restrict__ p, const int64_t *__restrict__ off,
+    int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
-  constexpr int NM = 2 * PM + 1, NU = (NM + 15) / 16;
+  constexpr int NC = NU * RB;
+  const int PM = nm >> 1;
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int lb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
-  const int c = blockIdx.y, wave = blockIdx.z & 1, r = blockIdx.z >> 1;
+  const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
   const int j0 = c * per_chunk, j1 = min(q, j0 + per_chunk);
-  const double2 *gr = g + (int64_t)(r * 2 + wave) * q;
   const double2 *Vt = wave ? Vs_t : Vp_t;
   const C *Ew = Etab + (int64_t)wave * q * n;
-  Acc ar[NT][NU], ai[NT][NU];
+  Acc ar[NT][NC], ai[NT][NC];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int u = 0; u < NU; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
   int lc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) lc[t] = min(lb + 16 * t + i16, n - 1);
   C en[NT];
-  double2 vn[NU], gn;
+  double2 vn[NU], gn[RB];
   auto fetch = [&](int j) {
     const int jc = min(j + kq, j1 - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)jc * n + lc[t]];
-    gn = gr[jc];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) vn[u] = Vt[(int64_t)jc * NM + min(16 * u + i16, NM - 1)];
+    for (int k = 0; k < RB; ++k)
+      gn[k] = g[(int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) vn[u] = Vt[(int64_t)jc * nm + min(16 * u + i16, nm - 1)];
   };
   fetch(j0);
   for (int j = j0; j < j1; j += 4) {
     const bool ok = j + kq < j1;
-    T er[NT], ei[NT], br[NU], bi[NU];
+    T er[NT], ei[NT], br[NC], bi[NC];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       er[t] = en[t].x;
       ei[t] = en[t].y;
     }
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      const bool use = ok && 16 * u + i16 < NM;
-      const double2 G = cmul(gn, vn[u]);
-      br[u] = use ? (T)G.x : T(0);
-      bi[u] = use ? (T)G.y : T(0);
-    }
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const bool use = ok && 16 * u + i16 < nm;
+        const double2 G = cmul(gn[k], vn[u]);
+        br[k * NU + u] = use ? (T)G.x : T(0);
+        bi[k * NU + u] = use ? (T)G.y : T(0);
+      }
     fetch(j + 4);
-    mfma_cstep<T, NT, NU>(ar, ai, er, ei, br, bi);
+    mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -404,11 +422,16 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
       const int l = lb + 16 * t + Mfma<T>::row(kq, v);
       if (l >= n) continue;
       const int pl = p[l];
-      double2 *o = dis + ((int64_t)r * chunks + c) * ncoef + off[l] + wave * (2 * pl + 1) + pl;
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int nn = 16 * u + i16 - PM;
-        if (nn >= -pl && nn <= pl) o[nn] = make_double2((double)ar[t][u][v], (double)ai[t][u][v]);
+      for (int k = 0; k < RB; ++k) {
+        if (r0 + k >= nrhs) break;
+        double2 *o = dis + ((int64_t)(r0 + k) * chunks + c) * ncoef + off[l] + wave * (2 * pl + 1) + pl;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int nn = 16 * u + i16 - PM;
+          if (nn >= -pl && nn <= pl)
+            o[nn] = make_double2((double)ar[t][k * NU + u][v], (double)ai[t][k * NU + u][v]);
+        }
       }
     }
   }
@@ -425,21 +448,112 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     else EMS_AGG_LAUNCH(PMV, false, 2);                                                    \
     break;
 
-#define EMS_AGGM_LAUNCH(T, PMV, NT, UNIV, ETAB)                                             \
-  hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, PMV, NT, UNIV>),                         \
-                     dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * nrhs), dim3(256), \
-                     0, st, h->n, h->q, h->d_p, h->d_off, x, h->ncoef, h->d_Vp, h->d_Vs,        \
-                     h->d_agg, h->agg_chunks, per, ETAB)
-#define EMS_AGGM_CASE(PMV)                                                                   \
-  case PMV:                                                                                  \
-    if (mixed && h->d_Eagg32) {                                                              \
-      if (uni) EMS_AGGM_LAUNCH(float, PMV, 4, true, h->d_Eagg32);                            \
-      else EMS_AGGM_LAUNCH(float, PMV, 4, false, h->d_Eagg32);                               \
+// Candidate tile shapes (node or particle tiles NT, right-hand sides per
+// wave RB) of the matrix-core kernels, indexed by MfmaCfg::idx; the
+// autotuner times them on the handle's own tables.
+static constexpr int kCand[2][2][4][2] = {
+    // [kernel: 0 aggregate, 1 disaggregate][precision: 0 FP64, 1 FP32][candidate] = {NT, RB}
+    {{{1, 1}, {2, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 4}, {1, 8}}},
+    {{{2, 1}, {4, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 4}, {1, 8}}}};
+
+int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
+  if (kernel < 0 || kernel > 1 || prec < 0 || prec > 1 || idx < 0 || idx > 3) return -1;
+  *nt = kCand[kernel][prec][idx][0];
+  *rb = kCand[kernel][prec][idx][1];
+  return 0;
+}
+
+template <typename T, int NU, int NT, int RB, bool UNI>
+static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per,
+                   const typename Mfma<T>::C *E, hipStream_t st) {
+  hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI>),
+                     dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB)),
+                     dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
+                     h->d_off, x, h->ncoef, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, E);
+}
+template <typename T, int NU, bool UNI>
+static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
+                     const typename Mfma<T>::C *E, hipStream_t st) {
+  constexpr int P = std::is_same<T, float>::value ? 1 : 0;
+  switch (idx) {
+    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, st); break;
+    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, st); break;
+    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, st); break;
+    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, st); break;
+  }
+}
+template <typename T, int NU, int NT, int RB>
+static void dis_go(const ems_handle *h, int nrhs, int per, const typename Mfma<T>::C *E,
+                   hipStream_t st) {
+  hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB>),
+                     dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB)),
+                     dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
+                     h->d_off, h->d_Vp, h->d_Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per,
+                     E);
+}
+template <typename T, int NU>
+static void dis_cand(const ems_handle *h, int idx, int nrhs, int per,
+                     const typename Mfma<T>::C *E, hipStream_t st) {
+  constexpr int P = std::is_same<T, float>::value ? 1 : 0;
+  switch (idx) {
+    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, st); break;
+    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, st); break;
+    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, st); break;
+    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, st); break;
+  }
+}
+
+// Matrix-core aggregate with the candidate idx (prec 0 FP64 tables, 1 FP32).
+hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
+                                      int idx, hipStream_t st) {
+  const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
+  const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
+  const bool uni = h->p_uniform && pm_bucket(h->pmax) == h->pmax;
+  if (prec == 1 && !h->d_Eagg32) return hipErrorInvalidValue;
+  if (prec == 0 && !h->d_Eagg) return hipErrorInvalidValue;
+#define EMS_AGGM_NU(NUV)                                                                     \
+  if (nu == NUV) {                                                                           \
+    if (prec == 1) {                                                                         \
+      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, st);           \
+      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, st);              \
     } else {                                                                                 \
-      if (uni) EMS_AGGM_LAUNCH(double, PMV, 2, true, h->d_Eagg);                             \
-      else EMS_AGGM_LAUNCH(double, PMV, 2, false, h->d_Eagg);                                \
+      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg, st);            \
+      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg, st);               \
     }                                                                                        \
-    break;
+    return hipGetLastError();                                                                \
+  }
+  EMS_AGGM_NU(1)
+  EMS_AGGM_NU(2)
+  EMS_AGGM_NU(3)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
+                                         hipStream_t st) {
+  const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
+  const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
+  if (prec == 1 && !h->d_Edis32) return hipErrorInvalidValue;
+  if (prec == 0 && !h->d_Edis) return hipErrorInvalidValue;
+#define EMS_DISM_NU(NUV)                                                                     \
+  if (nu == NUV) {                                                                           \
+    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, st);                \
+    else dis_cand<double, NUV>(h, idx, nrhs, per, h->d_Edis, st);                           \
+    return hipGetLastError();                                                                \
+  }
+  EMS_DISM_NU(1)
+  EMS_DISM_NU(2)
+  EMS_DISM_NU(3)
+  return hipErrorInvalidValue;
+}
+
+// The tuned (or default) candidate for a kernel, precision and batch size.
+static int pick(const ems_handle *h, int kernel, int prec, int nrhs) {
+  const int v = h->mfma_cfg[kernel][prec][nrhs > 1 ? 1 : 0];
+  if (v >= 0) return v;
+  // defaults from the tile sweep at 20000 particles, p = 15
+  static constexpr int def[2][2][2] = {{{1, 2}, {1, 2}}, {{1, 2}, {1, 2}}};
+  return def[kernel][prec][nrhs > 1 ? 1 : 0];
+}
 
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st) {
@@ -447,17 +561,8 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   const int pb = pm_bucket(h->pmax);
   const bool uni = h->p_uniform && pb == h->pmax;
   if (!adjoint && h->d_Eagg != nullptr) {
-    switch (pb) {
-      EMS_AGGM_CASE(4)
-      EMS_AGGM_CASE(8)
-      EMS_AGGM_CASE(10)
-      EMS_AGGM_CASE(12)
-      EMS_AGGM_CASE(15)
-      EMS_AGGM_CASE(16)
-      default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const int prec = (mixed && h->d_Eagg32) ? 1 : 0;
+    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st);
   }
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
@@ -492,38 +597,12 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
     else EMS_DIS_LAUNCH(PMV, 2);                                                           \
     break;
 
-#define EMS_DISM_CASE(PMV)                                                                   \
-  case PMV:                                                                                  \
-    if (mixed && h->d_Edis32) {                                                              \
-      constexpr int NT = 4;                                                                  \
-      hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<float, PMV, NT>),                    \
-                         dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * nrhs),     \
-                         dim3(256), 0, st, h->n, h->q, h->d_p, h->d_off, h->d_Vp, h->d_Vs,    \
-                         h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, h->d_Edis32);    \
-    } else {                                                                                 \
-      constexpr int NT = 4;                                                                  \
-      hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<double, PMV, NT>),                   \
-                         dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * nrhs),     \
-                         dim3(256), 0, st, h->n, h->q, h->d_p, h->d_off, h->d_Vp, h->d_Vs,    \
-                         h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, h->d_Edis);      \
-    }                                                                                        \
-    break;
-
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st) {
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   if (!adjoint && h->d_Edis != nullptr) {
-    switch (pm_bucket(h->pmax)) {
-      EMS_DISM_CASE(4)
-      EMS_DISM_CASE(8)
-      EMS_DISM_CASE(10)
-      EMS_DISM_CASE(12)
-      EMS_DISM_CASE(15)
-      EMS_DISM_CASE(16)
-      default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const int prec = (mixed && h->d_Edis32) ? 1 : 0;
+    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st);
   }
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;

@@ -64,3 +64,22 @@ def test_gradient_against_oracle(n, p, seed):
     scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
     assert np.abs(gxy - gxy0).max() <= 1e-8 * scale
     assert np.abs(np.asarray(gl) - gl0).max() <= 1e-8 * scale
+
+
+def test_autograd_misfit_against_oracle():
+    """The torch.autograd path (forward solve, adjoint solve and vector-Jacobian
+    product inside one autograd.Function) gives the oracle's gradient."""
+    import paper_2608_26875_amd as E
+    w, pts, waves, u_obs = _case(3, 3, 21)
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    J0, gxy0, gl0 = G.gradient(w, m, S, waves, pts, u_obs)
+    xy = torch.tensor(w.xy, dtype=torch.float64, requires_grad=True)
+    lame = torch.tensor([w.substrate.lam, w.substrate.mu], dtype=torch.float64, requires_grad=True)
+    J = E.misfit(xy, lame, radius=w.radius, p=w.p, host=w.host, substrate_rho=w.substrate.rho,
+                 omega=w.omega, waves=waves, pts=pts, u_obs=u_obs, bc=w.bc)
+    (2.0 * J).backward()
+    scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
+    assert abs(float(J) - J0) <= 1e-10 * J0
+    assert np.abs(xy.grad.numpy() - 2.0 * gxy0).max() <= 2e-8 * scale
+    assert np.abs(lame.grad.numpy() - 2.0 * gl0).max() <= 2e-8 * scale

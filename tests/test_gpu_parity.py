@@ -213,3 +213,36 @@ def test_scattered_field_rejects_receiver_inside_disk():
     with pytest.raises(E.EmsError) as ei:
         op.scattered_field(g, w.xy[:1] + 0.01)
     assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("flags_name", ["fp64", "mixed"])
+def test_batched_chunks_match_single(flags_name):
+    """11 right-hand sides (chunks of 8 plus a ragged tail in the direct Graf,
+    FMM and matrix-core kernels) against one-at-a-time applies, forward and
+    adjoint; the FP32 form to its own rounding level."""
+    w = W.small_cloud(40, seed=14, p=5, omega=4.0, width=40.0, depth=(1.0, 6.0), ragged=True)
+    op = product_operator(w)
+    op.build()
+    flags = E.EMS_APPLY_ALL | (E.EMS_MIXED if flags_name == "mixed" else 0)
+    tol = 1e-14 if flags_name == "fp64" else 1e-6
+    X = W.random_coeffs(w.n_coeff, 8, nrhs=11)
+    for adjoint in (False, True):
+        Yb = to_np(op.apply(to_gpu(X), flags=flags, adjoint=adjoint))
+        for r in (0, 7, 8, 10):
+            y1 = to_np(op.apply(to_gpu(X[r:r + 1]), flags=flags, adjoint=adjoint))[0]
+            assert rel(Yb[r], y1) < tol, (adjoint, r, rel(Yb[r], y1))
+
+
+def test_autotune_keeps_results():
+    w = W.small_cloud(30, seed=4, p=6, omega=4.0, width=30.0, depth=(1.0, 6.0))
+    op = product_operator(w)
+    op.build()
+    X = to_gpu(W.random_coeffs(w.n_coeff, 3, nrhs=6))
+    before = {m: to_np(op.apply(X, flags=E.EMS_APPLY_ALL | m)) for m in (0, E.EMS_MIXED)}
+    for nr in (1, 6):
+        choice = op.autotune(nr)
+        print("autotune", nr, choice, flush=True)
+        assert choice["aggregate_fp64"][0] > 0
+    for m in (0, E.EMS_MIXED):
+        after = to_np(op.apply(X, flags=E.EMS_APPLY_ALL | m))
+        assert rel(after, before[m]) < (1e-14 if m == 0 else 1e-6)

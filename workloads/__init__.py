@@ -213,6 +213,64 @@ def c2_cloud(shapes: bool = False) -> Workload:
                  name="c2")
 
 
+def c3_cloud(freq: int) -> Workload:
+    """The 20000-particle geometry with uneven orders p_i = ceil(ks a_i) + 8 at
+    omega = 2, 4, 8 (kp a_mean = 0.5, 1, 2) for freq = 0, 1, 2, and 64
+    incident directions linspace(-80, 80) degrees, even index P, odd SV."""
+    omega = (2.0, 4.0, 8.0)[freq]
+    w = cloud(20000, 600.0, (1.0, 150.0), seed=2, p=None, omega=omega, name=f"c3f{freq}")
+    ang = np.radians(np.linspace(-80.0, 80.0, 64))
+    w.incidence = [(k % 2, float(a)) for k, a in enumerate(ang)]
+    return w
+
+
+def c4_cloud() -> Workload:
+    """5000 particles at the density of the 2000-particle cloud, [0,320] x [1,80]
+    with z - R >= 0.6 (receivers at z = 0.5 stay outside every disk), p = 15,
+    omega = 8; 32 P waves at linspace(-80, 80) degrees."""
+    w = cloud(5000, 320.0, (1.0, 80.0), seed=4, p=15, omega=8.0, min_z_clear=0.6, name="c4")
+    w.incidence = [(0, float(a)) for a in np.radians(np.linspace(-80.0, 80.0, 32))]
+    return w
+
+
+def c4_receivers(n: int = 1024, width: float = 320.0, z: float = 0.5) -> np.ndarray:
+    """Receiver line in the paper frame: x equispaced over the box width, y = -z."""
+    return np.stack([np.linspace(0.0, width, n), np.full(n, -z)], axis=1)
+
+
+def c4_start(w: Workload, seed: int = 5, sigma: float = 0.05, lam_factor: float = 1.05,
+             mu_factor: float = 0.95, z_clear: float = 0.55):
+    """Perturbed start of the inverse problem: centres + N(0, sigma^2) per
+    coordinate, substrate lambda and mu scaled.  A perturbation that would make
+    two enclosing disks touch, or bring a disk within z_clear of the
+    interface, is drawn again (up to 50 times, then the centre stays).
+    Returns (workload, substrate)."""
+    rng = _rng(seed)
+    xy = w.xy.copy()
+    R = w.radius
+    cell = 4.0 * float(R.max()) + 1.0
+    grid: dict = {}
+    for i in range(w.n):
+        grid.setdefault((int(xy[i, 0] // cell), int(xy[i, 1] // cell)), []).append(i)
+    for i in range(w.n):
+        for _ in range(50):
+            c = w.xy[i] + rng.normal(0.0, sigma, size=2)
+            if -c[1] - R[i] < z_clear:
+                continue
+            gx, gy = int(c[0] // cell), int(c[1] // cell)
+            ok = True
+            for ax in (gx - 1, gx, gx + 1):
+                for ay in (gy - 1, gy, gy + 1):
+                    for j in grid.get((ax, ay), ()):
+                        if j != i and np.hypot(*(c - xy[j])) <= 1.001 * (R[i] + R[j]):
+                            ok = False
+            if ok:
+                xy[i] = c
+                break
+    sub = Medium(w.substrate.lam * lam_factor, w.substrate.mu * mu_factor, w.substrate.rho)
+    return dataclasses.replace(w, xy=xy, substrate=sub, name=w.name + "-start"), sub
+
+
 def small_cloud(n: int, seed: int, p: int = 6, omega: float = 4.0, width: float = 30.0,
                 depth: tuple = (1.0, 8.0), ragged: bool = False) -> Workload:
     """A small cloud for parity tests that the oracle finishes in seconds."""
