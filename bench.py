@@ -91,10 +91,11 @@ KERNEL_SRC = {"graf_direct": ("graf.hip",), "somm_aggregate": ("somm.hip",),
               "somm_disaggregate": ("somm.hip",), "combine_s_apply": ("linalg.hip",)}
 
 
-def traffic_from_profiles(kernel, workload_name):
+def traffic_from_profiles(kernel, workload_name, mixed=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when there is none or the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_pmc.json")
+    suffix = "_mixed" if mixed else ""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}{suffix}_pmc.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -324,7 +325,7 @@ def main():
     if check is not None and abs(check - fl_launch) > 1e-9 * check:
         raise SystemExit(f"flop count mismatch for {dom}: library {fl_launch} vs {check}")
     bound, peak = kernel_unit(dom, mixed)
-    traffic = traffic_from_profiles(dom, w.name)
+    traffic = traffic_from_profiles(dom, w.name, mixed)
     roof = {"bound": bound, "achieved": fl_launch / dom_avg_s / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": fl_launch / dom_avg_s / peak, "traffic": traffic,
             "kernel": dom, "flops_per_launch": fl_launch}

@@ -207,6 +207,18 @@ int ems_get_info(const ems_handle *h, ems_build_info *out);
 int ems_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
               ems_stream_t stream);
 
+/* Captured apply: the first call for a given (x, y, nrhs, flags, adjoint)
+ * runs the apply (ems_apply or ems_apply_adjoint) and records the same
+ * launch sequence into a HIP graph; later calls with the same buffers replay
+ * it (one launch, no host work per kernel), reading whatever x holds then.
+ * The graph contains kernels only (no memory set or copy nodes).  A
+ * reallocated workspace (a larger nrhs elsewhere) or a rebuild makes the
+ * next call capture again.  On the null stream the replay runs on an internal
+ * non-blocking stream joined by events.  Not for concurrent use of one
+ * handle. */
+int ems_apply_graph(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+                    int32_t adjoint, ems_stream_t stream);
+
 /* Conjugate-transpose apply (same flags; y = x - T^H S^H x for ALL). */
 int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
                       ems_stream_t stream);

@@ -108,6 +108,7 @@ def _load():
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
         "ems_eval_scattered_adjoint": ([P, P, I32, I32, P, P, P], I32),
         "ems_autotune": ([P, I32, ctypes.POINTER(ctypes.c_int32), P], I32),
+        "ems_apply_graph": ([P, P, P, I32, I32, I32, P], I32),
         "ems_param_vjp": ([P, ctypes.POINTER(PlaneWave), I32, P, P, I32, P, P, P,
                            ctypes.POINTER(ctypes.c_double), P], I32),
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
@@ -129,6 +130,7 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
+            "ems_apply_graph",
             "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
@@ -345,6 +347,16 @@ class Operator:
                              adjoint=True)
         dxy, dl = self.param_vjp(waves, gam, lam, pts, res)
         return J, dxy.cpu().numpy(), dl, {"forward": i1, "adjoint": i2}
+
+    def apply_graph(self, x, y, flags=EMS_APPLY_ALL, adjoint=False, stream=None):
+        """Apply through a captured HIP graph (captured on the first call with
+        these buffers, replayed afterwards).  x, y: complex128 [nrhs, n_coeff]."""
+        nrhs = self._vec_check(x)
+        self._vec_check(y)
+        self._check(_lib.ems_apply_graph(self.h, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(y.data_ptr()), nrhs, int(flags),
+                                         1 if adjoint else 0, _stream_ptr(stream)))
+        return y
 
     def autotune(self, nrhs=1, stream=None) -> dict:
         """Time the matrix-core tile shapes for batches of nrhs; returns the choice."""

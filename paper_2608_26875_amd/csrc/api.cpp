@@ -49,7 +49,13 @@ void clear_prof(ems_handle *h) {
   h->prof_recs.clear();
 }
 
+void drop_graphs(ems_handle *h) {
+  for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second.first);
+  h->graphs.clear();
+}
+
 void free_device(ems_handle *h) {
+  drop_graphs(h);
   clear_prof(h);
   dfree(h->d_xy);
   dfree(h->d_p);
@@ -125,6 +131,7 @@ bool finite_all(const double *v, size_t n) {
 // Workspace for nrhs right-hand sides.
 int ensure_ws(ems_handle *h, int nrhs) {
   if (h->ws_nrhs >= nrhs) return EMS_OK;
+  ++h->ws_epoch;
   dfree(h->d_agg);
   dfree(h->d_refl);
   dfree(h->d_dis);
@@ -154,6 +161,7 @@ int ensure_ws(ems_handle *h, int nrhs) {
 
 int ensure_tmp(ems_handle *h, size_t bytes) {
   if (h->tmp_bytes >= bytes) return EMS_OK;
+  ++h->ws_epoch;
   dfree(h->d_tmp);
   HIPCHK(h, hipMalloc(&h->d_tmp, bytes));
   h->tmp_bytes = bytes;
@@ -234,6 +242,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
       // reciprocity: T^H v = P conj(T conj(P v))
       const size_t bytes = sizeof(double2) * (size_t)nrhs * h->ncoef;
       if (h->adj_bytes < bytes) {
+        ++h->ws_epoch;
         dfree(h->d_adj1);
         dfree(h->d_adj2);
         HIPCHK(h, hipMalloc(&h->d_adj1, bytes));
@@ -290,6 +299,9 @@ int ems_create(ems_handle **out) {
 void ems_destroy(ems_handle *h) {
   if (!h) return;
   free_device(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (auto &e : h->cap_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -1291,6 +1303,9 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
       float best = 1e30f;
       int bi = -1;
       for (int idx = 0; idx < 4; ++idx) {
+        int nt = 0, rb = 0;
+        ems::mfma_candidate(kernel, prec, idx, &nt, &rb);
+        if (rb > 1 && nrhs == 1) continue;  // batched shapes only pay with several RHS
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
           HIPCHK(h, hipEventRecord(e0, st));
@@ -1319,5 +1334,59 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return EMS_OK;
+}
+
+extern "C" int ems_apply_graph(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+                               int32_t adjoint, ems_stream_t stream) {
+  if (!h || !x || !y || nrhs <= 0 || x == y) return fail(h, EMS_ERR_ARG, "bad apply arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  const auto key = std::make_tuple(x, y, (int)nrhs, (int)flags, adjoint ? 1 : 0);
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end() || it->second.second != h->ws_epoch) {
+    if (it != h->graphs.end()) {
+      (void)hipGraphExecDestroy(it->second.first);
+      h->graphs.erase(it);
+    }
+    // eager apply: the result of this call, and every workspace sized before capture
+    int rc = apply_impl(h, (const double2 *)x, (double2 *)y, nrhs, flags, adjoint != 0, st);
+    if (rc) return rc;
+    if (!h->cap_stream) {
+      HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      for (auto &e : h->cap_ev) HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    hipStream_t cs = st ? st : h->cap_stream;
+    const uint64_t epoch = h->ws_epoch;
+    const bool prof = h->prof;
+    h->prof = false;
+    HIPCHK(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    rc = apply_impl(h, (const double2 *)x, (double2 *)y, nrhs, flags, adjoint != 0, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    h->prof = prof;
+    if (rc || ee != hipSuccess || h->ws_epoch != epoch) {
+      if (g) (void)hipGraphDestroy(g);
+      if (rc) return rc;
+      return fail(h, EMS_ERR_HIP, "apply capture failed");
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(h, EMS_ERR_HIP, "graph instantiate failed");
+    h->graphs[key] = std::make_pair(ex, epoch);
+    return EMS_OK;
+  }
+  hipGraphExec_t ex = it->second.first;
+  if (st) {
+    HIPCHK(h, hipGraphLaunch(ex, st));
+  } else {
+    // join the null stream through events around the replay stream
+    HIPCHK(h, hipEventRecord(h->cap_ev[0], st));
+    HIPCHK(h, hipStreamWaitEvent(h->cap_stream, h->cap_ev[0], 0));
+    HIPCHK(h, hipGraphLaunch(ex, h->cap_stream));
+    HIPCHK(h, hipEventRecord(h->cap_ev[1], h->cap_stream));
+    HIPCHK(h, hipStreamWaitEvent(st, h->cap_ev[1], 0));
+  }
   return EMS_OK;
 }

@@ -7,6 +7,8 @@
 #include <complex>
 #include <cstdint>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ems.h"
@@ -198,6 +200,14 @@ struct ems_handle {
   size_t tmp_bytes = 0;
   double *d_red = nullptr;       // reduction partials
   size_t red_bytes = 0;
+  // captured applies (ems_apply_graph): key (x, y, nrhs, flags, adjoint) ->
+  // (executable graph, workspace epoch at capture); any reallocation of an
+  // apply workspace bumps ws_epoch and forces a new capture
+  std::map<std::tuple<const void *, void *, int, int, int>, std::pair<hipGraphExec_t, uint64_t>>
+      graphs;
+  uint64_t ws_epoch = 0;
+  hipStream_t cap_stream = nullptr;  // capture/replay stream for callers on the null stream
+  hipEvent_t cap_ev[2] = {nullptr, nullptr};
   // operator with orders p + 1 and S = I on the same geometry (gradient)
   ems_handle *ext = nullptr;
   // mixed-precision refinement: residual and correction [nrhs][ncoef]
