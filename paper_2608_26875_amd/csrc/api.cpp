@@ -90,6 +90,7 @@ void free_device(ems_handle *h) {
   dfree(h->d_tmp);
   dfree(h->d_red);
   dfree(h->d_pool);
+  dfree(h->d_fmm_part);
   dfree(h->d_mult);
   dfree(h->d_loc);
   dfree(h->d_nbr_ptr);
@@ -104,6 +105,13 @@ void free_device(ems_handle *h) {
     dfree(D.out_P);
     dfree(D.item_out);
     dfree(D.item_row0);
+    dfree(D.item_t0);
+    dfree(D.item_t1);
+    dfree(D.item_slot);
+    dfree(D.red_out);
+    dfree(D.red_row0);
+    dfree(D.red_slot0);
+    dfree(D.red_g);
     dfree(D.in_base);
     dfree(D.sym_base);
     dfree(D.out_base);
@@ -149,11 +157,15 @@ int ensure_ws(ems_handle *h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_free, sizeof(double2) * (size_t)nrhs * nc));
   dfree(h->d_mult);
   dfree(h->d_loc);
+  dfree(h->d_fmm_part);
   dfree(h->d_adj1);
   dfree(h->d_adj2);
   if (h->fmm_on) {
     HIPCHK(h, hipMalloc(&h->d_mult, sizeof(double2) * (size_t)nrhs * h->fmm.exp_len));
     HIPCHK(h, hipMalloc(&h->d_loc, sizeof(double2) * (size_t)nrhs * h->fmm.exp_len));
+    if (h->fmm.max_slots > 0)
+      HIPCHK(h, hipMalloc(&h->d_fmm_part,
+                          sizeof(double2) * (size_t)nrhs * h->fmm.max_slots * ems::kFmmRows));
   }
   h->ws_nrhs = nrhs;
   return EMS_OK;
@@ -619,11 +631,20 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
     if ((rc = upload(h, h->d_nbr_ptr, F.nbr_ptr.data(), F.nbr_ptr.size()))) return rc;
     if ((rc = upload(h, h->d_nbr_idx, F.nbr_idx.data(), std::max<size_t>(1, F.nbr_idx.size())))) return rc;
     h->fmm_dev.assign(F.launches.size(), ems::FmmDev());
-    static const char *names[] = {"fmm_p2m", "fmm_m2m", "fmm_m2l_l2l", "fmm_l2p"};
+    static const char *names[] = {"fmm_p2m", "fmm_m2m", "fmm_l2p"};
+    // M2L (+L2L) launches named by tree level, top level first
+    static const char *m2l_names[] = {"fmm_m2l_l2l_0", "fmm_m2l_l2l_1", "fmm_m2l_l2l_2",
+                                      "fmm_m2l_l2l_3", "fmm_m2l_l2l_4", "fmm_m2l_l2l_5",
+                                      "fmm_m2l_l2l_6", "fmm_m2l_l2l_7", "fmm_m2l_l2l_8",
+                                      "fmm_m2l_l2l_9", "fmm_m2l_l2l_10", "fmm_m2l_l2l_11",
+                                      "fmm_m2l_l2l_12"};
+    int m2l_level = 0;
     for (size_t i = 0; i < F.launches.size(); ++i) {
       ems::FmmLaunch &L = F.launches[i];
-      L.name = L.in_kind == 0 ? names[0]
-                              : (L.out_kind == 1 ? names[1] : (L.out_kind == 2 ? names[2] : names[3]));
+      if (L.in_kind == 0) L.name = names[0];
+      else if (L.out_kind == 1) L.name = names[1];
+      else if (L.out_kind == 2) L.name = m2l_names[std::min(m2l_level++, 12)];
+      else L.name = names[2];
       ems::FmmDev &D = h->fmm_dev[i];
       if ((rc = upload(h, D.ptr, L.ptr.data(), L.ptr.size()))) return rc;
       if ((rc = upload(h, D.in_P, L.in_P.data(), L.in_P.size()))) return rc;
@@ -632,6 +653,13 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
       if ((rc = upload(h, D.out_P, L.out_P.data(), L.out_P.size()))) return rc;
       if ((rc = upload(h, D.item_out, L.item_out.data(), L.item_out.size()))) return rc;
       if ((rc = upload(h, D.item_row0, L.item_row0.data(), L.item_row0.size()))) return rc;
+      if ((rc = upload(h, D.item_t0, L.item_t0.data(), L.item_t0.size()))) return rc;
+      if ((rc = upload(h, D.item_t1, L.item_t1.data(), L.item_t1.size()))) return rc;
+      if ((rc = upload(h, D.item_slot, L.item_slot.data(), L.item_slot.size()))) return rc;
+      if ((rc = upload(h, D.red_out, L.red_out.data(), L.red_out.size()))) return rc;
+      if ((rc = upload(h, D.red_row0, L.red_row0.data(), L.red_row0.size()))) return rc;
+      if ((rc = upload(h, D.red_slot0, L.red_slot0.data(), L.red_slot0.size()))) return rc;
+      if ((rc = upload(h, D.red_g, L.red_g.data(), L.red_g.size()))) return rc;
       if ((rc = upload(h, D.in_base, L.in_base.data(), L.in_base.size()))) return rc;
       if ((rc = upload(h, D.sym_base, L.sym_base.data(), L.sym_base.size()))) return rc;
       if ((rc = upload(h, D.out_base, L.out_base.data(), L.out_base.size()))) return rc;

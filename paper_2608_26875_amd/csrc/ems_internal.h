@@ -89,17 +89,27 @@ struct FmmLevel {
 // 1 multipoles, 2 locals; out_kind: 1 multipoles, 2 locals, 3 free-part
 // output.  Tasks with sgn = 2 read from the locals (L2L inside an M2L launch);
 // sgn = -1 flips the odd symbol entries (L2P).
+// Items of a launch are (output, 192-row chunk, task group): when a launch
+// has few outputs their task lists are split into groups on separate
+// wavefronts, each writing a partial chunk (slot) that a second kernel sums
+// in a fixed order (red_* lists, one entry per (output, chunk)).
+constexpr int kFmmRows = 192;
 struct FmmLaunch {
   const char *name = "fmm";
   int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0;
   double flops = 0.0;  // 8 (2 P_out + 1)(2 P_in + 1) summed over the tasks, per right-hand side
   std::vector<int> ptr, in_P, sym_L, sgn, out_P, item_out, item_row0;
+  std::vector<int> item_t0, item_t1, item_slot;  // task range, partial slot (-1: direct)
+  int nslot = 0;                                  // partial slots of kFmmRows complex
+  std::vector<int> red_out, red_row0, red_slot0, red_g;
   std::vector<int64_t> in_base, sym_base, out_base;
 };
 
 struct FmmDev {
   int *ptr = nullptr, *in_P = nullptr, *sym_L = nullptr, *sgn = nullptr, *out_P = nullptr;
   int *item_out = nullptr, *item_row0 = nullptr;
+  int *item_t0 = nullptr, *item_t1 = nullptr, *item_slot = nullptr;
+  int *red_out = nullptr, *red_row0 = nullptr, *red_slot0 = nullptr, *red_g = nullptr;
   int64_t *in_base = nullptr, *sym_base = nullptr, *out_base = nullptr;
 };
 
@@ -108,6 +118,7 @@ struct FmmPlan {
   double S0 = 0.0;
   std::vector<FmmLevel> levels;  // index 0 = top level Lt
   int64_t exp_len = 0;           // complex elements of all expansions (per RHS)
+  int max_slots = 0;             // largest partial-slot count over the launches
   std::vector<int> nbr_ptr, nbr_idx;
   std::vector<int64_t> part_sym;
   std::vector<FmmLaunch> launches;
@@ -180,6 +191,7 @@ struct ems_handle {
   ems::FmmPlan fmm;
   std::vector<ems::FmmDev> fmm_dev;
   double2 *d_pool = nullptr, *d_mult = nullptr, *d_loc = nullptr;
+  double2 *d_fmm_part = nullptr;  // [nrhs][max_slots][kFmmRows] task-group partials
   int *d_nbr_ptr = nullptr, *d_nbr_idx = nullptr;
   double2 *d_adj1 = nullptr, *d_adj2 = nullptr;  // adjoint free-part scratch
   size_t adj_bytes = 0;

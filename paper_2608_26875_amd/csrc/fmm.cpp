@@ -373,14 +373,37 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
   }
   for (auto &L : F.launches) {
     L.nout = (int)L.out_base.size();
-    // (output, 256-row chunk) items
+    // (output, 192-row chunk) items: the task kernel's wavefront owns 64 x 3 rows
+    int nchunk = 0, max_tasks = 1;
+    for (int o = 0; o < L.nout; ++o) {
+      nchunk += (2 * L.out_P[o] + 1 + kFmmRows - 1) / kFmmRows;
+      max_tasks = std::max(max_tasks, L.ptr[o + 1] - L.ptr[o]);
+    }
+    // split task lists when there are too few items to fill the chip
+    constexpr int kTargetItems = 4096;
+    const int G = std::max(1, std::min({16, max_tasks, (kTargetItems + nchunk - 1) / std::max(1, nchunk)}));
+    L.nslot = 0;
     for (int o = 0; o < L.nout; ++o) {
       const int rows = 2 * L.out_P[o] + 1;
-      for (int c = 0; c * 256 < rows; ++c) {
-        L.item_out.push_back(o);
-        L.item_row0.push_back(c * 256);
+      const int t0 = L.ptr[o], nt = L.ptr[o + 1] - L.ptr[o];
+      const int g = std::max(1, std::min(G, nt));
+      for (int c = 0; c * kFmmRows < rows; ++c) {
+        if (g > 1) {
+          L.red_out.push_back(o);
+          L.red_row0.push_back(c * kFmmRows);
+          L.red_slot0.push_back(L.nslot);
+          L.red_g.push_back(g);
+        }
+        for (int k = 0; k < g; ++k) {
+          L.item_out.push_back(o);
+          L.item_row0.push_back(c * kFmmRows);
+          L.item_t0.push_back(t0 + (int)((int64_t)nt * k / g));
+          L.item_t1.push_back(t0 + (int)((int64_t)nt * (k + 1) / g));
+          L.item_slot.push_back(g > 1 ? L.nslot++ : -1);
+        }
       }
     }
+    F.max_slots = std::max(F.max_slots, L.nslot);
     for (int t = 0; t < (int)L.in_P.size(); ++t) L.max_in_P = std::max(L.max_in_P, L.in_P[t]);
     L.flops = 0.0;
     for (int o = 0; o < L.nout; ++o)
@@ -411,9 +434,19 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
         }
       }
     }
-    for (size_t it = 0; it < L.item_out.size(); ++it)
-      if (L.item_row0[it] >= 2 * L.out_P[L.item_out[it]] + 1) {
-        err = "fmm plan: row chunk out of range";
+    for (size_t it = 0; it < L.item_out.size(); ++it) {
+      const int o = L.item_out[it];
+      if (L.item_row0[it] >= 2 * L.out_P[o] + 1 || L.item_t0[it] < L.ptr[o] ||
+          L.item_t1[it] > L.ptr[o + 1] || L.item_t0[it] > L.item_t1[it] ||
+          L.item_slot[it] >= L.nslot) {
+        err = "fmm plan: item out of range";
+        return EMS_ERR_NUMERIC;
+      }
+    }
+    for (size_t k = 0; k < L.red_out.size(); ++k)
+      if (L.red_slot0[k] < 0 || L.red_slot0[k] + L.red_g[k] > L.nslot ||
+          L.red_row0[k] >= 2 * L.out_P[L.red_out[k]] + 1) {
+        err = "fmm plan: partial sum out of range";
         return EMS_ERR_NUMERIC;
       }
   }
