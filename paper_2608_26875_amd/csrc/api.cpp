@@ -79,6 +79,12 @@ void free_device(ems_handle *h) {
   dfree(h->d_Edis);
   dfree(h->d_Eagg32);
   dfree(h->d_Edis32);
+  dfree(h->d_EaggA);
+  dfree(h->d_EdisA);
+  dfree(h->d_VpA_agg);
+  dfree(h->d_VsA_agg);
+  dfree(h->d_VpA_dis);
+  dfree(h->d_VsA_dis);
   dfree(h->d_irR);
   dfree(h->d_irD);
   h->ir_bytes = 0;
@@ -91,6 +97,7 @@ void free_device(ems_handle *h) {
   dfree(h->d_red);
   dfree(h->d_pool);
   dfree(h->d_fmm_part);
+  dfree(h->d_nsym);
   dfree(h->d_mult);
   dfree(h->d_loc);
   dfree(h->d_nbr_ptr);
@@ -623,6 +630,23 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if ((rc = upload(h, h->d_dR, dR.data(), dR.size()))) return rc;
   if ((rc = upload(h, h->d_Vp, Vp.data(), Vp.size()))) return rc;
   if ((rc = upload(h, h->d_Vs, Vs.data(), Vs.size()))) return rc;
+  {
+    // power tables of the adjoint matrix-core contractions: conj(V) (-1)^n
+    // (aggregate of the conjugated disaggregate factors) and conj(V)
+    std::vector<double2> a1(Vp.size()), a2(Vs.size()), d1(Vp.size()), d2(Vs.size());
+    for (size_t k = 0; k < Vp.size(); ++k) {
+      const int nn = (int)(k % ld) - pmb;
+      const double sg = (nn & 1) ? -1.0 : 1.0;
+      d1[k] = make_double2(Vp[k].x, -Vp[k].y);
+      d2[k] = make_double2(Vs[k].x, -Vs[k].y);
+      a1[k] = make_double2(sg * d1[k].x, sg * d1[k].y);
+      a2[k] = make_double2(sg * d2[k].x, sg * d2[k].y);
+    }
+    if ((rc = upload(h, h->d_VpA_agg, a1.data(), a1.size()))) return rc;
+    if ((rc = upload(h, h->d_VsA_agg, a2.data(), a2.size()))) return rc;
+    if ((rc = upload(h, h->d_VpA_dis, d1.data(), d1.size()))) return rc;
+    if ((rc = upload(h, h->d_VsA_dis, d2.data(), d2.size()))) return rc;
+  }
   if (h->fmm_on) {
     ems::FmmPlan &F = h->fmm;
     std::vector<double2> pool(F.pool.size());
@@ -630,6 +654,30 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
     if ((rc = upload(h, h->d_pool, pool.data(), pool.size()))) return rc;
     if ((rc = upload(h, h->d_nbr_ptr, F.nbr_ptr.data(), F.nbr_ptr.size()))) return rc;
     if ((rc = upload(h, h->d_nbr_idx, F.nbr_idx.data(), std::max<size_t>(1, F.nbr_idx.size())))) return rc;
+    // near-pair symbols, tabulated once when they fit (forward near field)
+    {
+      const size_t nt = 4 * (size_t)ems::pm_bucket(h->pmax) + 1;
+      const size_t bytes = (size_t)h->n_pairs * 2 * nt * sizeof(double2);
+      size_t fre = 0, tot = 0;
+      (void)hipMemGetInfo(&fre, &tot);
+      if (h->n_pairs > 0 && bytes <= (size_t)16 << 30 && (double)bytes < 0.25 * (double)fre) {
+        std::vector<int> tgt((size_t)h->n_pairs);
+        for (int b = 0; b < h->n; ++b)
+          for (int k = F.nbr_ptr[b]; k < F.nbr_ptr[b + 1]; ++k) tgt[k] = b;
+        int *d_tgt = nullptr;
+        if (hipMalloc(&h->d_nsym, bytes) == hipSuccess) {
+          if ((rc = upload(h, d_tgt, tgt.data(), tgt.size()))) return rc;
+          const hipError_t e = ems::launch_near_symbols(h, d_tgt, 0);
+          const hipError_t e2 = hipDeviceSynchronize();
+          dfree(d_tgt);
+          HIPCHK(h, e);
+          HIPCHK(h, e2);
+        } else {
+          (void)hipGetLastError();
+          h->d_nsym = nullptr;
+        }
+      }
+    }
     h->fmm_dev.assign(F.launches.size(), ems::FmmDev());
     static const char *names[] = {"fmm_p2m", "fmm_m2m", "fmm_l2p"};
     // M2L (+L2L) launches named by tree level, top level first
@@ -690,6 +738,14 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
           (void)hipGetLastError();
           dfree(h->d_Eagg32);
           dfree(h->d_Edis32);
+        }
+        // conjugated tables of the adjoint when those fit too
+        if (2.5 * gb <= h->etab_budget_gb && 2.5 * gb * 1e9 < 0.6 * (double)fre &&
+            (hipMalloc(&h->d_EaggA, sizeof(double2) * half) != hipSuccess ||
+             hipMalloc(&h->d_EdisA, sizeof(double2) * half) != hipSuccess)) {
+          (void)hipGetLastError();
+          dfree(h->d_EaggA);
+          dfree(h->d_EdisA);
         }
         HIPCHK(h, ems::launch_etables(h, 0));
       }

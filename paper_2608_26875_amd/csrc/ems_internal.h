@@ -166,6 +166,10 @@ struct ems_handle {
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
   float2 *d_Eagg32 = nullptr, *d_Edis32 = nullptr;  // complex64 copies for the mixed form (optional)
+  // adjoint tables (optional): conj(E_dis) in the aggregate layout, conj(E_agg)
+  // in the disaggregate layout, and their power tables conj(V) (-1)^n, conj(V)
+  double2 *d_EaggA = nullptr, *d_EdisA = nullptr;
+  double2 *d_VpA_agg = nullptr, *d_VsA_agg = nullptr, *d_VpA_dis = nullptr, *d_VsA_dis = nullptr;
   // tile candidate of the matrix-core kernels [aggregate/disaggregate][FP64/FP32]
   // [one / several right-hand sides]; -1: built-in default (ems_autotune sets it)
   int mfma_cfg[2][2][2] = {{{-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}}};
@@ -192,6 +196,7 @@ struct ems_handle {
   std::vector<ems::FmmDev> fmm_dev;
   double2 *d_pool = nullptr, *d_mult = nullptr, *d_loc = nullptr;
   double2 *d_fmm_part = nullptr;  // [nrhs][max_slots][kFmmRows] task-group partials
+  double2 *d_nsym = nullptr;      // near-pair symbols [pair][2][4 PMb + 1] (optional)
   int *d_nbr_ptr = nullptr, *d_nbr_idx = nullptr;
   double2 *d_adj1 = nullptr, *d_adj2 = nullptr;  // adjoint free-part scratch
   size_t adj_bytes = 0;
@@ -257,6 +262,7 @@ struct ProfScope {
 hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *out, int nrhs,
                               bool adjoint, bool mixed, hipStream_t st);
 int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err);
+hipError_t launch_near_symbols(ems_handle *h, const int *pair_tgt, hipStream_t st);
 hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs,
                       hipStream_t st);
 hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out, int nrhs,
@@ -264,9 +270,9 @@ hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
                                  bool mixed, hipStream_t st);
 hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
-                                      int idx, hipStream_t st);
+                                      int idx, hipStream_t st, bool adj = false);
 hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
-                                         hipStream_t st);
+                                         hipStream_t st, bool adj = false);
 int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
 hipError_t launch_etables(ems_handle *h, hipStream_t st);

@@ -37,16 +37,52 @@ __device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(
 __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
 
-template <int PM, bool MIXED, int RB>
+// Toeplitz symbol of one pair and wave number: t[2 PM + nu] = H_nu(k d)
+// e^{-i nu (th - pi)} for |nu| <= 2 PM, (d, th) the polar form of (dx, dy),
+// Hankel functions by forward recurrence from H_0, H_1 (stable because
+// |Y_nu| dominates).
+template <int PM, typename T, typename Cvt>
+__device__ __forceinline__ void graf_symbol(double dx, double dy, double k, T *t, Cvt cvt) {
+  const double d = sqrt(dx * dx + dy * dy);
+  const double th = atan2(dy, dx);
+  const double z = k * d;
+  double sn, cs;
+  sincos(th, &sn, &cs);
+  const double2 e1 = make_double2(-cs, sn);  // e^{-i (th - pi)}
+  double2 hm = make_double2(j0(z), y0(z));
+  double2 h = make_double2(j1(z), y1(z));
+  t[2 * PM] = cvt(hm);
+  double2 ph = e1;
+  t[2 * PM + 1] = cvt(cmul(h, ph));
+  // t_{-nu} = (-1)^nu H_nu conj(e^{-i nu (th - pi)})
+  t[2 * PM - 1] = cvt(cscale(cmul(h, cconj(ph)), -1.0));
+  const double iz = 2.0 / z;
+#pragma unroll
+  for (int nu = 2; nu <= 2 * PM; ++nu) {
+    const double2 hn = csub(cscale(h, (nu - 1) * iz), hm);
+    hm = h;
+    h = hn;
+    ph = cmul(ph, e1);
+    t[2 * PM + nu] = cvt(cmul(h, ph));
+    const double sg = (nu & 1) ? -1.0 : 1.0;
+    t[2 * PM - nu] = cvt(cscale(cmul(h, cconj(ph)), sg));
+  }
+}
+
+template <int PM, bool MIXED, int RB, bool STORED>
 __global__ __launch_bounds__(128) void graf_direct_kernel(
     int n, int nrhs, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint,
-    const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx) {
+    const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx,
+    const double2 *__restrict__ nsym) {
   using T = typename CT<MIXED>::T;
   constexpr int NT = 4 * PM + 1;
   constexpr int NM = 2 * PM + 1;
-  constexpr int SB = 16;
+  // partners per batch: generated symbols amortise the Hankel work over 16;
+  // tabulated ones are only copied, and a small batch keeps LDS low enough
+  // for several wavefronts per CU to hide the loads
+  constexpr int SB = STORED ? 4 : 16;
   constexpr int ROWS = 2 * PM + 1 <= 32 ? 32 : 64;
   __shared__ T t_lds[2][SB][NT];
   __shared__ T c_lds[SB][2][NM];
@@ -69,7 +105,16 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
   const int *nl = nbr_ptr ? nbr_idx + nbr_ptr[b] : nullptr;
 
   for (int base = 0; base < np; base += SB) {
-    if (lane < 2 * SB) {
+    if (STORED) {
+      // symbols of the near pairs, tabulated at set-up in near-list order
+      const int ns = min(SB, np - base);
+      const double2 *src = nsym + ((int64_t)(nbr_ptr[b] + base) * 2) * NT;
+      for (int e = lane; e < SB * 2 * NT; e += 2 * ROWS) {
+        const int s = e / (2 * NT), rem = e - s * 2 * NT;
+        const int ww = rem / NT, kk = rem - ww * NT;
+        t_lds[ww][s][kk] = CT<MIXED>::from(s < ns ? src[e] : make_double2(0.0, 0.0));
+      }
+    } else if (lane < 2 * SB) {
       const int s = lane >> 1, ww = lane & 1;
       const int l = base + s < np ? (nl ? nl[base + s] : base + s) : n;
       T *t = t_lds[ww][s];
@@ -80,33 +125,7 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
           dx = -dx;
           dy = -dy;
         }
-        const double d = sqrt(dx * dx + dy * dy);
-        const double th = atan2(dy, dx);
-        const double z = (ww ? ks : kp) * d;
-        double sn, cs;
-        sincos(th, &sn, &cs);
-        const double2 e1 = make_double2(-cs, sn);  // e^{-i (th - pi)}
-        double2 hm = make_double2(j0(z), y0(z));
-        double2 h = make_double2(j1(z), y1(z));
-        t[2 * PM] = CT<MIXED>::from(hm);
-        double2 ph = e1;
-        {
-          const double2 v = cmul(h, ph);
-          t[2 * PM + 1] = CT<MIXED>::from(v);
-          // t_{-nu} = (-1)^nu H_nu conj(e^{-i nu (th - pi)})
-          t[2 * PM - 1] = CT<MIXED>::from(cscale(cmul(h, cconj(ph)), -1.0));
-        }
-        const double iz = 2.0 / z;
-#pragma unroll
-        for (int nu = 2; nu <= 2 * PM; ++nu) {
-          const double2 hn = csub(cscale(h, (nu - 1) * iz), hm);
-          hm = h;
-          h = hn;
-          ph = cmul(ph, e1);
-          t[2 * PM + nu] = CT<MIXED>::from(cmul(h, ph));
-          const double sg = (nu & 1) ? -1.0 : 1.0;
-          t[2 * PM - nu] = CT<MIXED>::from(cscale(cmul(h, cconj(ph)), sg));
-        }
+        graf_symbol<PM>(dx, dy, ww ? ks : kp, t, [](double2 v) { return CT<MIXED>::from(v); });
       } else {
         for (int k = 0; k < NT; ++k) {
           t[k].x = 0;
@@ -152,18 +171,37 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
   }
 }
 
-#define EMS_GRAF_LAUNCH(PMV, MIX, RBV)                                                       \
-  hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV>), dim3(h->n, (nrhs + RBV - 1) / RBV),    \
-                     dim3(graf_threads(PMV)), 0, st, h->n, nrhs, h->d_xy, h->d_p, h->d_off, x,   \
-                     h->ncoef, out, h->ncoef, h->md.kp, h->md.ks, adjoint ? 1 : 0, nptr, nidx)
+// Symbols of every near pair (forward orientation), for both wave numbers:
+// nsym[(pair * 2 + w) * (4 PM + 1) + 2 PM + nu], pair = position in the near list.
+template <int PM>
+__global__ __launch_bounds__(256) void near_symbols_kernel(int npairs, const double *__restrict__ xy,
+                                                           const int *__restrict__ pair_tgt,
+                                                           const int *__restrict__ nbr_idx,
+                                                           double kp, double ks,
+                                                           double2 *__restrict__ nsym) {
+  constexpr int NT = 4 * PM + 1;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 2 * (int64_t)npairs) return;
+  const int pr = (int)(g >> 1), w = (int)(g & 1);
+  const int b = pair_tgt[pr], l = nbr_idx[pr];
+  graf_symbol<PM>(xy[2 * b] - xy[2 * l], xy[2 * b + 1] - xy[2 * l + 1], w ? ks : kp,
+                  nsym + g * NT, [](double2 v) { return v; });
+}
+
+#define EMS_GRAF_LAUNCH(PMV, MIX, RBV, STV)                                                  \
+  hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV, STV>),                                  \
+                     dim3(h->n, (nrhs + RBV - 1) / RBV), dim3(graf_threads(PMV)), 0, st, h->n,   \
+                     nrhs, h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,      \
+                     h->md.ks, adjoint ? 1 : 0, nptr, nidx, h->d_nsym)
+#define EMS_GRAF_RB(PMV, MIX, STV)                                                           \
+  if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, MIX, 8, STV);                                           \
+  else EMS_GRAF_LAUNCH(PMV, MIX, 1, STV);
 #define EMS_GRAF_CASE(PMV)                                                                   \
   case PMV:                                                                                  \
-    if (mixed) {                                                                             \
-      if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, true, 8);                                           \
-      else EMS_GRAF_LAUNCH(PMV, true, 1);                                                    \
+    if (stored) {                                                                            \
+      if (mixed) { EMS_GRAF_RB(PMV, true, true) } else { EMS_GRAF_RB(PMV, false, true) }      \
     } else {                                                                                 \
-      if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, false, 8);                                          \
-      else EMS_GRAF_LAUNCH(PMV, false, 1);                                                   \
+      if (mixed) { EMS_GRAF_RB(PMV, true, false) } else { EMS_GRAF_RB(PMV, false, false) }    \
     }                                                                                        \
     break;
 
@@ -182,6 +220,9 @@ hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *ou
                               bool adjoint, bool mixed, hipStream_t st) {
   const int *nptr = h->fmm_on ? h->d_nbr_ptr : nullptr;
   const int *nidx = h->fmm_on ? h->d_nbr_idx : nullptr;
+  // tabulated near-pair symbols serve the forward map (the adjoint with the
+  // FMM runs the forward map through reciprocity)
+  const bool stored = h->fmm_on && h->d_nsym != nullptr && !adjoint;
   switch (pm_bucket(h->pmax)) {
     EMS_GRAF_CASE(4)
     EMS_GRAF_CASE(8)
@@ -189,6 +230,33 @@ hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *ou
     EMS_GRAF_CASE(12)
     EMS_GRAF_CASE(15)
     EMS_GRAF_CASE(16)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ems
+
+namespace ems {
+
+#define EMS_NSYM_CASE(PMV)                                                                   \
+  case PMV:                                                                                  \
+    hipLaunchKernelGGL((near_symbols_kernel<PMV>), dim3((unsigned)((2 * np + 255) / 256)),     \
+                       dim3(256), 0, st, (int)np, h->d_xy, pair_tgt, h->d_nbr_idx, h->md.kp,   \
+                       h->md.ks, h->d_nsym);                                                 \
+    break;
+
+hipError_t launch_near_symbols(ems_handle *h, const int *pair_tgt, hipStream_t st) {
+  const int64_t np = h->n_pairs;
+  if (np <= 0 || !h->d_nsym) return hipSuccess;
+  switch (pm_bucket(h->pmax)) {
+    EMS_NSYM_CASE(4)
+    EMS_NSYM_CASE(8)
+    EMS_NSYM_CASE(10)
+    EMS_NSYM_CASE(12)
+    EMS_NSYM_CASE(15)
+    EMS_NSYM_CASE(16)
     default:
       return hipErrorInvalidValue;
   }

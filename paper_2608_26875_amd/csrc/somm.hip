@@ -465,60 +465,66 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
 
 template <typename T, int NU, int NT, int RB, bool UNI>
 static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per,
-                   const typename Mfma<T>::C *E, hipStream_t st) {
+                   const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
+                   hipStream_t st) {
   hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI>),
                      dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, x, h->ncoef, h->d_Vp, h->d_Vs, h->d_agg, h->agg_chunks, per, E);
+                     h->d_off, x, h->ncoef, Vp, Vs, h->d_agg, h->agg_chunks, per, E);
 }
 template <typename T, int NU, bool UNI>
 static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
-                     const typename Mfma<T>::C *E, hipStream_t st) {
+                     const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
+                     hipStream_t st) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, st); break;
-    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, st); break;
-    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, st); break;
-    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, st); break;
+    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
+    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
+    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
+    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
   }
 }
 template <typename T, int NU, int NT, int RB>
 static void dis_go(const ems_handle *h, int nrhs, int per, const typename Mfma<T>::C *E,
-                   hipStream_t st) {
+                   const double2 *Vp, const double2 *Vs, hipStream_t st) {
   hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB>),
                      dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, h->d_Vp, h->d_Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per,
-                     E);
+                     h->d_off, Vp, Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, E);
 }
 template <typename T, int NU>
 static void dis_cand(const ems_handle *h, int idx, int nrhs, int per,
-                     const typename Mfma<T>::C *E, hipStream_t st) {
+                     const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
+                     hipStream_t st) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, st); break;
-    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, st); break;
-    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, st); break;
-    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, st); break;
+    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, Vp, Vs, st); break;
+    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, Vp, Vs, st); break;
+    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, Vp, Vs, st); break;
+    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, Vp, Vs, st); break;
   }
 }
 
-// Matrix-core aggregate with the candidate idx (prec 0 FP64 tables, 1 FP32).
+// Matrix-core aggregate with the candidate idx (prec 0 FP64 tables, 1 FP32;
+// adj: the adjoint's conjugated tables, FP64).
 hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
-                                      int idx, hipStream_t st) {
+                                      int idx, hipStream_t st, bool adj) {
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
   const bool uni = h->p_uniform && pm_bucket(h->pmax) == h->pmax;
+  if (adj) prec = 0;
+  const double2 *E64 = adj ? h->d_EaggA : h->d_Eagg;
+  const double2 *Vp = adj ? h->d_VpA_agg : h->d_Vp, *Vs = adj ? h->d_VsA_agg : h->d_Vs;
   if (prec == 1 && !h->d_Eagg32) return hipErrorInvalidValue;
-  if (prec == 0 && !h->d_Eagg) return hipErrorInvalidValue;
+  if (prec == 0 && !E64) return hipErrorInvalidValue;
 #define EMS_AGGM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
     if (prec == 1) {                                                                         \
-      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, st);           \
-      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, st);              \
+      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st);      \
+      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st);         \
     } else {                                                                                 \
-      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg, st);            \
-      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg, st);               \
+      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, E64, Vp, Vs, st);             \
+      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, E64, Vp, Vs, st);                \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }
@@ -529,15 +535,18 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
 }
 
 hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
-                                         hipStream_t st) {
+                                         hipStream_t st, bool adj) {
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
+  if (adj) prec = 0;
+  const double2 *E64 = adj ? h->d_EdisA : h->d_Edis;
+  const double2 *Vp = adj ? h->d_VpA_dis : h->d_Vp, *Vs = adj ? h->d_VsA_dis : h->d_Vs;
   if (prec == 1 && !h->d_Edis32) return hipErrorInvalidValue;
-  if (prec == 0 && !h->d_Edis) return hipErrorInvalidValue;
+  if (prec == 0 && !E64) return hipErrorInvalidValue;
 #define EMS_DISM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
-    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, st);                \
-    else dis_cand<double, NUV>(h, idx, nrhs, per, h->d_Edis, st);                           \
+    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, Vp, Vs, st);          \
+    else dis_cand<double, NUV>(h, idx, nrhs, per, E64, Vp, Vs, st);                           \
     return hipGetLastError();                                                                \
   }
   EMS_DISM_NU(1)
@@ -562,8 +571,10 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   const bool uni = h->p_uniform && pb == h->pmax;
   if (!adjoint && h->d_Eagg != nullptr) {
     const int prec = (mixed && h->d_Eagg32) ? 1 : 0;
-    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st);
+    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st, false);
   }
+  if (adjoint && h->d_EaggA != nullptr)
+    return launch_somm_aggregate_mfma(h, x, nrhs, 0, pick(h, 0, 0, nrhs), st, true);
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pb) {
@@ -602,8 +613,10 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   if (!adjoint && h->d_Edis != nullptr) {
     const int prec = (mixed && h->d_Edis32) ? 1 : 0;
-    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st);
+    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, false);
   }
+  if (adjoint && h->d_EdisA != nullptr)
+    return launch_somm_disaggregate_mfma(h, nrhs, 0, pick(h, 1, 0, nrhs), st, true);
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pm_bucket(h->pmax)) {
@@ -625,7 +638,7 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
 __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
                                 const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
                                 const double2 *__restrict__ ss_t, double2 *__restrict__ E,
-                                float2 *__restrict__ E32) {
+                                float2 *__restrict__ E32, double2 *__restrict__ EA) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   const int w = blockIdx.z;
@@ -638,12 +651,14 @@ __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
   const int64_t at = ((int64_t)w * n + m) * q + j;
   E[at] = e;
   if (E32) E32[at] = make_float2((float)e.x, (float)e.y);
+  // adjoint aggregate table: conj(e^{i xi x_m + s y_m}) in this layout
+  if (EA) EA[at] = cconj(cexp(make_double2(s.x * ym - xi.y * xm, s.y * ym + xi.x * xm)));
 }
 
 __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
                                 const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
                                 const double2 *__restrict__ ss_t, double2 *__restrict__ E,
-                                float2 *__restrict__ E32) {
+                                float2 *__restrict__ E32, double2 *__restrict__ EA) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int w = blockIdx.z;
@@ -656,15 +671,19 @@ __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
   const int64_t at = ((int64_t)w * q + j) * n + l;
   E[at] = e;
   if (E32) E32[at] = make_float2((float)e.x, (float)e.y);
+  // adjoint disaggregate table: conj(e^{s y_l - i xi x_l}) in this layout
+  if (EA) EA[at] = cconj(cexp(make_double2(s.x * yl + xi.y * xl, s.y * yl - xi.x * xl)));
 }
 
 hipError_t launch_etables(ems_handle *h, hipStream_t st) {
   hipLaunchKernelGGL(etab_agg_kernel, dim3((h->q + 255) / 256, h->n, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg, h->d_Eagg32);
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg, h->d_Eagg32,
+                     h->d_EaggA);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(etab_dis_kernel, dim3((h->n + 255) / 256, h->q, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis, h->d_Edis32);
+                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis, h->d_Edis32,
+                     h->d_EdisA);
   return hipGetLastError();
 }
 
