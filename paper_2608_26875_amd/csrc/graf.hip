@@ -151,7 +151,9 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
       __syncthreads();
       if (i <= PM) {
         for (int s = 0; s < SB; ++s) {
-#pragma unroll
+          // partial unroll: full unrolling hoists every LDS read into
+          // registers and leaves one wavefront per SIMD
+#pragma unroll 8
           for (int jj = 0; jj < NM; ++jj) {
             const int nu = i - (jj - PM);
             T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
