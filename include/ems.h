@@ -73,7 +73,12 @@ typedef struct {
  * particle and the largest p (decay of exp(-|xi| D)(2|xi|/k)^(2p)).
  * panel_scale multiplies the default panel length of kind 1 (1 = default);
  * panel_order is the Gauss-Legendre order of the kind 1 panels (0 = 64);
- * tail_factor scales the trapezoidal density of the kind 1 tails (0 = 1). */
+ * tail_factor scales the trapezoidal density of the kind 1 tails (0 = 1).
+ * depth_cut: with the tabulated (matrix-core) contractions, a pair of a real
+ * node xi and a particle at depth d is left out of the aggregate and the
+ * disaggregate when exp(-Re s(xi) d) (2|xi|/k + 1)^p, times the same factor
+ * of the shallowest particle, is below depth_cut times the peak of the
+ * t_max bound for the shallowest pair (0 = 1e-26; < 0: every pair kept). */
 typedef struct {
   int32_t kind;
   int32_t q;
@@ -83,6 +88,7 @@ typedef struct {
   const double *nodes; /* host, kind 2 only */
   int32_t panel_order;
   double tail_factor;
+  double depth_cut;
 } ems_sommerfeld;
 
 /* Plane wave sent from the particle side towards the interface, direction
@@ -120,6 +126,8 @@ typedef struct {
   int32_t fmm_levels;   /* 0 = direct sum                                     */
   int64_t fmm_m2l;      /* multipole-to-local translations per apply          */
   double kp, ks, kpb, ksb;
+  double somm_kept;     /* fraction of the Sommerfeld contraction work kept by
+                           the depth truncation (1 without the tables)        */
 } ems_build_info;
 
 /* Parts of the operator selected by ems_apply's flags. */
@@ -169,6 +177,20 @@ int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s);
 int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
                          const double *xy, const int32_t *p, int32_t *q, double *nodes_out,
                          double *t_max);
+
+/* Host-only: the depth truncation ems_build applies to the tabulated
+ * Sommerfeld contractions of this cloud (rule: ems_sommerfeld.depth_cut;
+ * Section 4.1 places t_max by the same decay bound).  q must be the node
+ * count ems_sommerfeld_nodes reports.  Outputs, caller-owned host arrays:
+ * perm_out[n] = particle indices by increasing depth; kcut_out[2 q] = for
+ * wave w (0 P, 1 S) and node j, entry w q + j: how many particles of that
+ * order the node keeps (a prefix); range_out[4 n] = entries 2 (w n + i) and
+ * 2 (w n + i) + 1: the node range [lo, hi) holding every node that keeps the
+ * i-th particle of that order (lo = hi = 0 when none does); *kept_out
+ * (optional) = the kept fraction of (node, particle, wave) triples. */
+int ems_sommerfeld_depth_cuts(const ems_media *m, const ems_sommerfeld *s, int32_t n,
+                              const double *xy, const int32_t *p, int32_t q, int32_t *perm_out,
+                              int32_t *kcut_out, int32_t *range_out, double *kept_out);
 
 /* Host-only: the 2x2 reflection R(xi) of upgoing P / S potentials at the
  * welded interface (Section 2.2, the 4x4 continuity system per Fourier mode,

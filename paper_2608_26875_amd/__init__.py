@@ -15,6 +15,14 @@ import os
 
 import numpy as np
 
+# torch ships a HIP runtime of its own next to the one the library links.
+# torch's is loaded first, as in every GPU run of the library: with the
+# library's runtime loaded ahead of it, the library's runtime saw no device.
+try:
+    import torch  # noqa: F401
+except ImportError:  # host-only use (node tables, reflection, S-matrices)
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libems.so")
 
@@ -46,7 +54,7 @@ class Sommerfeld(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("q", ctypes.c_int32), ("t_max", ctypes.c_double),
                 ("delta", ctypes.c_double), ("panel_scale", ctypes.c_double),
                 ("nodes", ctypes.POINTER(ctypes.c_double)), ("panel_order", ctypes.c_int32),
-                ("tail_factor", ctypes.c_double)]
+                ("tail_factor", ctypes.c_double), ("depth_cut", ctypes.c_double)]
 
 
 class PlaneWave(ctypes.Structure):
@@ -79,7 +87,7 @@ class BuildInfo(ctypes.Structure):
                 ("q", ctypes.c_int32), ("t_max", ctypes.c_double), ("n_pairs", ctypes.c_int64),
                 ("fmm_levels", ctypes.c_int32), ("fmm_m2l", ctypes.c_int64),
                 ("kp", ctypes.c_double), ("ks", ctypes.c_double), ("kpb", ctypes.c_double),
-                ("ksb", ctypes.c_double)]
+                ("ksb", ctypes.c_double), ("somm_kept", ctypes.c_double)]
 
 
 def _load():
@@ -113,6 +121,8 @@ def _load():
                            ctypes.POINTER(ctypes.c_double), P], I32),
         "ems_sommerfeld_nodes": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P, P,
                                   ctypes.POINTER(I32), P, ctypes.POINTER(D)], I32),
+        "ems_sommerfeld_depth_cuts": ([ctypes.POINTER(Media), ctypes.POINTER(Sommerfeld), I32, P,
+                                       P, I32, P, P, P, ctypes.POINTER(D)], I32),
         "ems_reflection": ([ctypes.POINTER(Media), D, D, P], I32),
         "ems_profile": ([P, I32], I32),
         "ems_set_fmm": ([P, ctypes.POINTER(Fmm)], I32),
@@ -131,7 +141,8 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
             "ems_apply_graph",
-            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_reflection", "ems_profile",
+            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_sommerfeld_depth_cuts",
+            "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
 
@@ -160,12 +171,12 @@ def smatrix_disk(media: Media, a: float, p: int, bc: int) -> np.ndarray:
 
 
 def sommerfeld_nodes(media: Media, xy, p, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0,
-                     panel_order=0, tail_factor=0.0):
+                     panel_order=0, tail_factor=0.0, depth_cut=0.0):
     """Host-only node table [q, 6] = (Re xi, Im xi, Re w, Im w, bp, d) and the tail extent."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     p = np.ascontiguousarray(p, dtype=np.int32)
     s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), None,
-                   int(panel_order), float(tail_factor))
+                   int(panel_order), float(tail_factor), float(depth_cut))
     cnt = ctypes.c_int32(0)
     tm = ctypes.c_double(0)
     rc = _lib.ems_sommerfeld_nodes(ctypes.byref(media), ctypes.byref(s), len(p), xy.ctypes.data,
@@ -178,6 +189,31 @@ def sommerfeld_nodes(media: Media, xy, p, kind=1, q=0, t_max=0.0, delta=0.5, pan
     if rc != EMS_OK:
         raise EmsError(rc, "ems_sommerfeld_nodes failed")
     return out, tm.value
+
+
+def sommerfeld_depth_cuts(media: Media, xy, p, depth_cut=0.0, **node_opts):
+    """Host-only depth truncation of the tabulated Sommerfeld contractions:
+    (perm [n], kcut [2, q], ranges [2, n, 2], kept fraction)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.int32)
+    nodes, _ = sommerfeld_nodes(media, xy, p, depth_cut=depth_cut, **node_opts)
+    q = nodes.shape[0]
+    s = Sommerfeld(int(node_opts.get("kind", 1)), int(node_opts.get("q", 0)),
+                   float(node_opts.get("t_max", 0.0)), float(node_opts.get("delta", 0.5)),
+                   float(node_opts.get("panel_scale", 1.0)), None,
+                   int(node_opts.get("panel_order", 0)), float(node_opts.get("tail_factor", 0.0)),
+                   float(depth_cut))
+    n = len(p)
+    perm = np.zeros(n, dtype=np.int32)
+    kcut = np.zeros(2 * q, dtype=np.int32)
+    rng = np.zeros(4 * n, dtype=np.int32)
+    kept = ctypes.c_double(0.0)
+    rc = _lib.ems_sommerfeld_depth_cuts(ctypes.byref(media), ctypes.byref(s), n, xy.ctypes.data,
+                                        p.ctypes.data, q, perm.ctypes.data, kcut.ctypes.data,
+                                        rng.ctypes.data, ctypes.byref(kept))
+    if rc != EMS_OK:
+        raise EmsError(rc, "ems_sommerfeld_depth_cuts failed")
+    return perm, kcut.reshape(2, q), rng.reshape(2, n, 2), kept.value
 
 
 def reflection(media: Media, xi: complex) -> np.ndarray:
@@ -249,14 +285,14 @@ class Operator:
         self.built = False
 
     def set_sommerfeld(self, kind=1, q=0, t_max=0.0, delta=0.5, panel_scale=1.0, nodes=None,
-                       panel_order=0, tail_factor=0.0):
+                       panel_order=0, tail_factor=0.0, depth_cut=0.0):
         ptr = None
         if nodes is not None:
             self._nodes_keep = np.ascontiguousarray(nodes, dtype=np.float64)
             ptr = self._nodes_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             q = self._nodes_keep.shape[0]
         s = Sommerfeld(int(kind), int(q), float(t_max), float(delta), float(panel_scale), ptr,
-                       int(panel_order), float(tail_factor))
+                       int(panel_order), float(tail_factor), float(depth_cut))
         self._check(_lib.ems_set_sommerfeld(self.h, ctypes.byref(s)))
         self.built = False
 

@@ -81,6 +81,10 @@ void free_device(ems_handle *h) {
   dfree(h->d_Edis32);
   dfree(h->d_EaggA);
   dfree(h->d_EdisA);
+  dfree(h->d_sperm);
+  dfree(h->d_kcut);
+  dfree(h->d_jr);
+  h->depth_kept = 1.0;
   dfree(h->d_VpA_agg);
   dfree(h->d_VsA_agg);
   dfree(h->d_VpA_dis);
@@ -278,8 +282,11 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
     }
   }
   if (parts & EMS_PART_REFL) {
-    // one complex multiply-add per (node, coefficient) in each contraction
-    const double fc = 8.0 * (double)h->q * (double)h->ncoef * nrhs;
+    // one complex multiply-add per (node, coefficient) in each contraction,
+    // over the (node, particle) pairs the depth truncation keeps when the
+    // tabulated kernels run
+    const bool tab = adjoint ? h->d_EaggA != nullptr : h->d_Eagg != nullptr;
+    const double fc = 8.0 * (double)h->q * (double)h->ncoef * nrhs * (tab ? h->depth_kept : 1.0);
     {
       ems::ProfScope ps(h, "somm_aggregate", st, fc);
       HIPCHK(h, ems::launch_somm_aggregate(h, src, nrhs, adjoint, mixed, st));
@@ -447,6 +454,7 @@ static int spec_from(const ems_sommerfeld *s, ems::SommerfeldSpec &o, std::strin
   o.panel_scale = s->panel_scale > 0 ? s->panel_scale : 1.0;
   o.panel_order = s->panel_order > 0 ? s->panel_order : 64;
   o.tail_factor = s->tail_factor > 0 ? s->tail_factor : 1.0;
+  o.depth_cut = s->depth_cut > 0 ? s->depth_cut : (s->depth_cut < 0 ? 0.0 : 1e-26);
   if (o.panel_order < 8 || o.panel_order > 256) {
     err = "panel_order must be in [8, 256]";
     return EMS_ERR_ARG;
@@ -489,6 +497,33 @@ int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
       nodes_out[6 * j + 5] = nt.d[j];
     }
   }
+  return EMS_OK;
+}
+
+int ems_sommerfeld_depth_cuts(const ems_media *m, const ems_sommerfeld *s, int32_t n,
+                              const double *xy, const int32_t *p, int32_t q, int32_t *perm_out,
+                              int32_t *kcut_out, int32_t *range_out, double *kept_out) {
+  if (!m || !s || n <= 0 || !xy || !p || !perm_out || !kcut_out || !range_out)
+    return EMS_ERR_ARG;
+  ems::SommerfeldSpec spec;
+  std::string err;
+  int rc = spec_from(s, spec, err);
+  if (rc) return rc;
+  std::vector<double> vxy(xy, xy + 2 * (size_t)n);
+  std::vector<int> vp(p, p + n);
+  int pmax = 0;
+  for (int i = 0; i < n; ++i) pmax = std::max(pmax, vp[i]);
+  ems::NodeTable nt;
+  const ems::Media md = ems::make_media(*m);
+  rc = ems::build_nodes(spec, md, vxy, vp, nt, err);
+  if (rc) return rc;
+  if (q != (int32_t)nt.xi.size()) return EMS_ERR_ARG;
+  ems::DepthCuts dc;
+  ems::depth_cuts(nt, md, vxy, pmax, spec.depth_cut, dc);
+  std::copy(dc.perm.begin(), dc.perm.end(), perm_out);
+  std::copy(dc.kcut.begin(), dc.kcut.end(), kcut_out);
+  std::copy(dc.jr.begin(), dc.jr.end(), range_out);
+  if (kept_out) *kept_out = dc.kept;
   return EMS_OK;
 }
 
@@ -747,6 +782,19 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
           dfree(h->d_EaggA);
           dfree(h->d_EdisA);
         }
+        // table rows (aggregate) and columns (disaggregate) in depth order,
+        // with the ranges of the depth truncation
+        ems::DepthCuts dc;
+        ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, dc);
+        // coefficient-weighted kept fraction: the work of either contraction
+        std::vector<double> pre(h->n + 1, 0.0);
+        for (int i = 0; i < h->n; ++i) pre[i + 1] = pre[i] + 2.0 * h->p[dc.perm[i]] + 1.0;
+        double kept = 0.0;
+        for (size_t k = 0; k < dc.kcut.size(); ++k) kept += pre[dc.kcut[k]];
+        h->depth_kept = kept / ((double)h->q * (double)h->ncoef);
+        if ((rc = upload(h, h->d_sperm, dc.perm.data(), dc.perm.size()))) return rc;
+        if ((rc = upload(h, h->d_kcut, dc.kcut.data(), dc.kcut.size()))) return rc;
+        if ((rc = upload(h, h->d_jr, dc.jr.data(), dc.jr.size()))) return rc;
         HIPCHK(h, ems::launch_etables(h, 0));
       }
     }
@@ -771,6 +819,7 @@ int ems_get_info(const ems_handle *h, ems_build_info *out) {
   out->ks = h->md.ks;
   out->kpb = h->md.kpb;
   out->ksb = h->md.ksb;
+  out->somm_kept = h->d_Eagg ? h->depth_kept : 1.0;
   return EMS_OK;
 }
 

@@ -51,6 +51,7 @@ struct SommerfeldSpec {
   double panel_scale = 1.0;
   int panel_order = 64;
   double tail_factor = 1.0;
+  double depth_cut = 1e-26;  // depth truncation threshold (<= 0: none)
   std::vector<double> user;  // kind 2: [q][4]
 };
 
@@ -61,6 +62,17 @@ cd branch_s(cd xi, double k);
 // Build the node table for the given cloud.
 int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<double> &xy,
                 const std::vector<int> &p, NodeTable &out, std::string &err);
+
+// Depth truncation of the tabulated Sommerfeld contractions (setup.cpp):
+// perm = particles by increasing depth; kcut[w q + j] = how many of them
+// (in that order) node j of wave w keeps; jr[2 (w n + i)], jr[2 (w n + i) + 1]
+// = the node range [lo, hi) that covers every node keeping the i-th of them.
+struct DepthCuts {
+  std::vector<int> perm, kcut, jr;
+  double kept = 1.0;  // kept fraction of the (node, particle, wave) triples
+};
+void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<double> &xy, int pmax,
+                double eps, DepthCuts &out);
 
 // s(xi; k) for every wavenumber of the media at node (xi, bp, d):
 // out = {s_p, s_s, s_pb, s_sb}.
@@ -170,6 +182,10 @@ struct ems_handle {
   // in the disaggregate layout, and their power tables conj(V) (-1)^n, conj(V)
   double2 *d_EaggA = nullptr, *d_EdisA = nullptr;
   double2 *d_VpA_agg = nullptr, *d_VsA_agg = nullptr, *d_VpA_dis = nullptr, *d_VsA_dis = nullptr;
+  // depth order of the table rows / columns and the per-node and per-particle
+  // ranges of the truncated contractions (with the tables)
+  int *d_sperm = nullptr, *d_kcut = nullptr, *d_jr = nullptr;
+  double depth_kept = 1.0;
   // tile candidate of the matrix-core kernels [aggregate/disaggregate][FP64/FP32]
   // [one / several right-hand sides]; -1: built-in default (ems_autotune sets it)
   int mfma_cfg[2][2][2] = {{{-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}}};

@@ -63,11 +63,17 @@ static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w
   }
 }
 
-// Decay bound of the Sommerfeld integrand tail: exp(-t D) (2t/k + 1)^(2p).
-static double auto_tmax(double dmin, int pmax, double kmin, double kmax) {
+// Decay bound of the Sommerfeld integrand tail: exp(-t D) (2t/k + 1)^(2p)
+// for the depth sum D of a pair; its logarithm peaks at some t.
+static double bound_peak(double dmin, int pmax, double kmin) {
   double peak = -1e300;
   for (double t = 0.0; t < 4000.0; t += 0.01)
     peak = std::max(peak, -t * dmin + 2.0 * pmax * std::log(2.0 * t / kmin + 1.0));
+  return peak;
+}
+
+static double auto_tmax(double dmin, int pmax, double kmin, double kmax) {
+  const double peak = bound_peak(dmin, pmax, kmin);
   for (double t = kmax + 2.0; t < 4000.0; t += 0.01) {
     const double v = -t * dmin + 2.0 * pmax * std::log(2.0 * t / kmin + 1.0);
     if (v < peak + std::log(1e-18)) return t;
@@ -265,6 +271,69 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
   for (size_t i : idx) push(s, out.xi[i], out.w[i], out.bp[i], out.d[i]);
   out = s;
   return EMS_OK;
+}
+
+// Depth truncation.  The term that particle m sends through node xi_j (wave
+// w) to particle l carries exp(-Re s_w(xi_j) d_m) on the source side and
+// exp(-Re s_w'(xi_j) d_l) on the receiving side (d = depth below the
+// interface), times powers of zeta of order up to p on each side, each at
+// most (2|xi|/k_min + 1)^p in modulus on the real axis.  This is the tail
+// bound by which t_max is placed (one factor per end of the pair, with s in
+// place of |xi|).  A (node, particle) pair is left out of both contractions
+// when its bound, with the shallowest particle at the other end, is below
+// eps times the peak of that bound for the shallowest pair.  The bound falls
+// with depth, so each node keeps a prefix of the particles in depth order,
+// and each particle a set of nodes whose hull is recorded.  Complex nodes
+// (the tanh contour, user nodes off the axis) keep every particle.
+void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<double> &xy, int pmax,
+                double eps, DepthCuts &out) {
+  const int n = (int)(xy.size() / 2), q = (int)nodes.xi.size();
+  std::vector<double> depth(n);
+  for (int i = 0; i < n; ++i) depth[i] = -xy[2 * i + 1];
+  out.perm.resize(n);
+  for (int i = 0; i < n; ++i) out.perm[i] = i;
+  std::stable_sort(out.perm.begin(), out.perm.end(),
+                   [&](int a, int b) { return depth[a] < depth[b]; });
+  std::vector<double> ds(n);
+  for (int i = 0; i < n; ++i) ds[i] = depth[out.perm[i]];
+  out.kcut.assign(2 * (size_t)q, n);
+  out.jr.assign(4 * (size_t)n, 0);
+  const double dmin = n > 0 ? ds[0] : 0.0;
+  const double kmin = std::min(md.kp, md.ks);
+  const bool on = eps > 0.0 && n > 0 && dmin > 0.0;
+  const double thr = on ? bound_peak(2.0 * dmin, pmax, kmin) + std::log(eps) : 0.0;
+  double kept = 0.0;
+  for (int j = 0; j < q; ++j) {
+    const cd x = nodes.xi[j];
+    const double t = std::fabs(x.real());
+    const bool real_node = x.imag() == 0.0;
+    const double ap = t > md.kp ? std::sqrt((t - md.kp) * (t + md.kp)) : 0.0;
+    const double as = t > md.ks ? std::sqrt((t - md.ks) * (t + md.ks)) : 0.0;
+    const double amp = pmax * std::log(2.0 * t / kmin + 1.0);
+    const double other = amp - std::min(ap, as) * dmin;
+    for (int w = 0; w < 2; ++w) {
+      const double a = w ? as : ap;
+      int c = n;
+      if (on && real_node && a > 0.0) {
+        const double dcut = (amp + other - thr) / a;
+        c = (int)(std::upper_bound(ds.begin(), ds.end(), dcut) - ds.begin());
+      }
+      out.kcut[(size_t)w * q + j] = c;
+      kept += c;
+    }
+  }
+  out.kept = (q > 0 && n > 0) ? kept / (2.0 * q * (double)n) : 1.0;
+  // node hull of every particle: particle i is kept by node j iff i < kcut
+  for (int w = 0; w < 2; ++w) {
+    const int *kc = out.kcut.data() + (size_t)w * q;
+    int *jr = out.jr.data();
+    int hi = 0;
+    for (int j = 0; j < q; ++j)
+      for (; hi < kc[j]; ++hi) jr[2 * ((size_t)w * n + hi)] = j;
+    hi = 0;
+    for (int j = q - 1; j >= 0; --j)
+      for (; hi < kc[j]; ++hi) jr[2 * ((size_t)w * n + hi) + 1] = j + 1;
+  }
 }
 
 // ---------------------------------------------------------------------------

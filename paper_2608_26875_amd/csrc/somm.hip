@@ -269,7 +269,8 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ x, int64_t ldx, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
-    const typename Mfma<T>::C *__restrict__ Etab) {
+    const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
+    const int *__restrict__ kcut) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
   constexpr int NC = NU * RB;
@@ -277,7 +278,6 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int jb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
   const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
-  const int m0 = c * per_chunk, m1 = min(n, m0 + per_chunk);
   const C *Ew = Etab + (int64_t)wave * n * q;
   Acc ar[NT][NC], ai[NT][NC];
 #pragma unroll
@@ -287,15 +287,24 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   int jl[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) jl[t] = min(jb + 16 * t + i16, q - 1);
+  // table rows run through the particles by depth; the wave's nodes keep the
+  // first kc of them (the largest count over its nodes)
+  int kc = 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) kc = max(kc, kcut[wave * q + jl[t]]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) kc = max(kc, __shfl_xor(kc, o));
+  const int m0 = c * per_chunk, m1 = min(min(n, m0 + per_chunk), kc);
   C en[NT];
   double2 xn[NC];
   auto fetch = [&](int m) {
     const int mc = min(m + kq, m1 - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
-    // uniform orders: the coefficient address needs no table lookup
-    const int pm = UNI ? PM : p[mc];
-    const int64_t base = (UNI ? (int64_t)mc * 2 * nm : off[mc]) + wave * (2 * pm + 1) + pm;
+    const int mo = sperm[mc];
+    // uniform orders: the coefficient address needs no offset lookup
+    const int pm = UNI ? PM : p[mo];
+    const int64_t base = (UNI ? (int64_t)mo * 2 * nm : off[mo]) + wave * (2 * pm + 1) + pm;
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
       const int r = min(r0 + k, nrhs - 1);
@@ -307,7 +316,7 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       }
     }
   };
-  fetch(m0);
+  if (m0 < m1) fetch(m0);
   for (int m = m0; m < m1; m += 4) {
     const bool ok = m + kq < m1;
     T er[NT], ei[NT], br[NC], bi[NC];
@@ -363,7 +372,8 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
-    int per_chunk, const typename Mfma<T>::C *__restrict__ Etab) {
+    int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
+    const int2 *__restrict__ jr) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
   constexpr int NC = NU * RB;
@@ -371,7 +381,6 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int lb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
   const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
-  const int j0 = c * per_chunk, j1 = min(q, j0 + per_chunk);
   const double2 *Vt = wave ? Vs_t : Vp_t;
   const C *Ew = Etab + (int64_t)wave * q * n;
   Acc ar[NT][NC], ai[NT][NC];
@@ -382,6 +391,23 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   int lc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) lc[t] = min(lb + 16 * t + i16, n - 1);
+  // table columns run through the particles by depth; the wave's particles
+  // need the hull of their node ranges (empty ranges add nothing)
+  int lo = q, hi = 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int2 r = jr[wave * n + lc[t]];
+    if (r.y > r.x) {
+      lo = min(lo, r.x);
+      hi = max(hi, r.y);
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+  }
+  const int j0 = max(c * per_chunk, lo), j1 = min(min(q, c * per_chunk + per_chunk), hi);
   C en[NT];
   double2 vn[NU], gn[RB];
   auto fetch = [&](int j) {
@@ -394,7 +420,7 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
 #pragma unroll
     for (int u = 0; u < NU; ++u) vn[u] = Vt[(int64_t)jc * nm + min(16 * u + i16, nm - 1)];
   };
-  fetch(j0);
+  if (j0 < j1) fetch(j0);
   for (int j = j0; j < j1; j += 4) {
     const bool ok = j + kq < j1;
     T er[NT], ei[NT], br[NC], bi[NC];
@@ -421,11 +447,12 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     for (int v = 0; v < 4; ++v) {
       const int l = lb + 16 * t + Mfma<T>::row(kq, v);
       if (l >= n) continue;
-      const int pl = p[l];
+      const int lo_ = sperm[l];
+      const int pl = p[lo_];
 #pragma unroll
       for (int k = 0; k < RB; ++k) {
         if (r0 + k >= nrhs) break;
-        double2 *o = dis + ((int64_t)(r0 + k) * chunks + c) * ncoef + off[l] + wave * (2 * pl + 1) + pl;
+        double2 *o = dis + ((int64_t)(r0 + k) * chunks + c) * ncoef + off[lo_] + wave * (2 * pl + 1) + pl;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int nn = 16 * u + i16 - PM;
@@ -470,7 +497,8 @@ static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per,
   hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI>),
                      dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, x, h->ncoef, Vp, Vs, h->d_agg, h->agg_chunks, per, E);
+                     h->d_off, x, h->ncoef, Vp, Vs, h->d_agg, h->agg_chunks, per, E, h->d_sperm,
+                     h->d_kcut);
 }
 template <typename T, int NU, bool UNI>
 static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
@@ -490,7 +518,8 @@ static void dis_go(const ems_handle *h, int nrhs, int per, const typename Mfma<T
   hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB>),
                      dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, Vp, Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, E);
+                     h->d_off, Vp, Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, E,
+                     h->d_sperm, (const int2 *)h->d_jr);
 }
 template <typename T, int NU>
 static void dis_cand(const ems_handle *h, int idx, int nrhs, int per,
@@ -634,18 +663,21 @@ hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint,
 
 // Tables of the geometry-dependent exponentials (set-up, once per geometry
 // and frequency):  Eagg[w][m][j] = e^{s_w(j) y_m - i xi_j x_m},
-// Edis[w][j][l] = e^{i xi_j x_l + s_w(j) y_l}.
+// Edis[w][j][l] = e^{i xi_j x_l + s_w(j) y_l}, with m and l the positions of
+// the particles in depth order (sperm maps them to particle indices).
 __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
-                                const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
-                                const double2 *__restrict__ ss_t, double2 *__restrict__ E,
-                                float2 *__restrict__ E32, double2 *__restrict__ EA) {
+                                const int *__restrict__ sperm, const double2 *__restrict__ xi_t,
+                                const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
+                                double2 *__restrict__ E, float2 *__restrict__ E32,
+                                double2 *__restrict__ EA) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   const int w = blockIdx.z;
   if (j >= q) return;
   const double2 xi = xi_t[j];
   const double2 s = w ? ss_t[j] : sp_t[j];
-  const double xm = xy[2 * m], ym = xy[2 * m + 1];
+  const int mo = sperm[m];
+  const double xm = xy[2 * mo], ym = xy[2 * mo + 1];
   // s y - i xi x
   const double2 e = cexp(make_double2(s.x * ym + xi.y * xm, s.y * ym - xi.x * xm));
   const int64_t at = ((int64_t)w * n + m) * q + j;
@@ -656,16 +688,18 @@ __global__ void etab_agg_kernel(int n, int q, const double *__restrict__ xy,
 }
 
 __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
-                                const double2 *__restrict__ xi_t, const double2 *__restrict__ sp_t,
-                                const double2 *__restrict__ ss_t, double2 *__restrict__ E,
-                                float2 *__restrict__ E32, double2 *__restrict__ EA) {
+                                const int *__restrict__ sperm, const double2 *__restrict__ xi_t,
+                                const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
+                                double2 *__restrict__ E, float2 *__restrict__ E32,
+                                double2 *__restrict__ EA) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int w = blockIdx.z;
   if (l >= n) return;
   const double2 xi = xi_t[j];
   const double2 s = w ? ss_t[j] : sp_t[j];
-  const double xl = xy[2 * l], yl = xy[2 * l + 1];
+  const int lo = sperm[l];
+  const double xl = xy[2 * lo], yl = xy[2 * lo + 1];
   // i xi x + s y
   const double2 e = cexp(make_double2(s.x * yl - xi.y * xl, s.y * yl + xi.x * xl));
   const int64_t at = ((int64_t)w * q + j) * n + l;
@@ -677,13 +711,13 @@ __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
 
 hipError_t launch_etables(ems_handle *h, hipStream_t st) {
   hipLaunchKernelGGL(etab_agg_kernel, dim3((h->q + 255) / 256, h->n, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg, h->d_Eagg32,
-                     h->d_EaggA);
+                     h->q, h->d_xy, h->d_sperm, h->d_xi, h->d_sp, h->d_ss, h->d_Eagg,
+                     h->d_Eagg32, h->d_EaggA);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(etab_dis_kernel, dim3((h->n + 255) / 256, h->q, 2), dim3(256), 0, st, h->n,
-                     h->q, h->d_xy, h->d_xi, h->d_sp, h->d_ss, h->d_Edis, h->d_Edis32,
-                     h->d_EdisA);
+                     h->q, h->d_xy, h->d_sperm, h->d_xi, h->d_sp, h->d_ss, h->d_Edis,
+                     h->d_Edis32, h->d_EdisA);
   return hipGetLastError();
 }
 
