@@ -64,8 +64,9 @@ def section8d_flops(kernel, w, info):
     (complex multiply-add = 8): a cross-check of the library's own count."""
     import numpy as np
     if kernel in ("somm_aggregate", "somm_disaggregate"):
-        # one complex MAC per (node, coefficient)
-        return 8.0 * info["q"] * float(w.n_coeff)
+        # one complex MAC per (node, coefficient), over the fraction of
+        # (node, particle) pairs the depth truncation keeps
+        return 8.0 * info["q"] * float(w.n_coeff) * info["somm_kept"]
     if kernel == "combine_s_apply":
         return 8.0 * float(np.sum((4 * w.p.astype(np.int64) + 2) ** 2))
     return None
@@ -338,7 +339,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n} particles, p={int(w.p.max())}, omega={w.omega}, "
                                f"{'FP64' if args.precision == 'fp64' else 'mixed'} apply",
-                   "n_coeff": int(w.n_coeff), "q_nodes": info["q"], "pairs_direct": info["n_pairs"],
+                   "n_coeff": int(w.n_coeff), "q_nodes": info["q"], "somm_kept": info["somm_kept"],
+                   "pairs_direct": info["n_pairs"],
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": per_kernel,
