@@ -84,6 +84,9 @@ void free_device(ems_handle *h) {
   dfree(h->d_sperm);
   dfree(h->d_kcut);
   dfree(h->d_jr);
+  dfree(h->d_kcut_f);
+  dfree(h->d_jr_f);
+  h->cut_f_depth = -1.0;
   h->depth_kept = 1.0;
   dfree(h->d_VpA_agg);
   dfree(h->d_VsA_agg);
@@ -519,7 +522,7 @@ int ems_sommerfeld_depth_cuts(const ems_media *m, const ems_sommerfeld *s, int32
   if (rc) return rc;
   if (q != (int32_t)nt.xi.size()) return EMS_ERR_ARG;
   ems::DepthCuts dc;
-  ems::depth_cuts(nt, md, vxy, pmax, spec.depth_cut, dc);
+  ems::depth_cuts(nt, md, vxy, pmax, spec.depth_cut, HUGE_VAL, dc);
   std::copy(dc.perm.begin(), dc.perm.end(), perm_out);
   std::copy(dc.kcut.begin(), dc.kcut.end(), kcut_out);
   std::copy(dc.jr.begin(), dc.jr.end(), range_out);
@@ -785,7 +788,9 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
         // table rows (aggregate) and columns (disaggregate) in depth order,
         // with the ranges of the depth truncation
         ems::DepthCuts dc;
-        ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, dc);
+        h->depth_min = 1e300;
+        for (int i = 0; i < h->n; ++i) h->depth_min = std::min(h->depth_min, -h->xy[2 * i + 1]);
+        ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, h->depth_min, dc);
         // coefficient-weighted kept fraction: the work of either contraction
         std::vector<double> pre(h->n + 1, 0.0);
         for (int i = 0; i < h->n; ++i) pre[i + 1] = pre[i] + 2.0 * h->p[dc.perm[i]] + 1.0;
@@ -1198,12 +1203,15 @@ extern "C" int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t 
 namespace {
 
 // Receivers must lie in the host layer (y < 0) and outside every enclosing disk.
-int check_receivers(ems_handle *h, const double *pts, int npts, hipStream_t st) {
+int check_receivers(ems_handle *h, const double *pts, int npts, hipStream_t st,
+                    double *depth = nullptr) {
   std::vector<double> hp(2 * (size_t)npts);
   HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
+  if (depth) *depth = HUGE_VAL;
   for (int i = 0; i < npts; ++i) {
     const double x = hp[2 * i], y = hp[2 * i + 1];
+    if (depth) *depth = std::min(*depth, -y);
     if (!std::isfinite(x) || !std::isfinite(y)) return fail(h, EMS_ERR_NUMERIC, "non-finite receiver");
     if (!(y < 0)) return fail(h, EMS_ERR_GEOMETRY, "receiver not in the host layer (y < 0)");
     for (int m = 0; m < h->n; ++m) {
@@ -1217,6 +1225,28 @@ int check_receivers(ems_handle *h, const double *pts, int npts, hipStream_t st) 
   return EMS_OK;
 }
 
+// Depth-truncation ranges with receivers at depth dr at the other end of
+// the pairs.  Receivers shallower than every particle see more of each
+// node's particles than the operator's pairs do; the ranges for them are
+// formed on the host from the handle's node table and cached per depth.
+// *kc, *jr stay nullptr (the build's ranges) when dr is not shallower.
+int field_cuts(ems_handle *h, double dr, const int **kc, const int **jr) {
+  *kc = nullptr;
+  *jr = nullptr;
+  if (!h->d_kcut || !(dr < h->depth_min)) return EMS_OK;
+  if (h->cut_f_depth != dr) {
+    ems::DepthCuts dc;
+    ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, dr, dc);
+    int rc;
+    if ((rc = upload(h, h->d_kcut_f, dc.kcut.data(), dc.kcut.size()))) return rc;
+    if ((rc = upload(h, h->d_jr_f, dc.jr.data(), dc.jr.size()))) return rc;
+    h->cut_f_depth = dr;
+  }
+  *kc = h->d_kcut_f;
+  *jr = h->d_jr_f;
+  return EMS_OK;
+}
+
 }  // namespace
 
 extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
@@ -1225,16 +1255,19 @@ extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs
     return fail(h, EMS_ERR_ARG, "bad field arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   hipStream_t st = (hipStream_t)stream;
-  int rc = check_receivers(h, pts, npts, st);
+  double dr = 0.0;
+  int rc = check_receivers(h, pts, npts, st, &dr);
   if (rc) return rc;
   if ((rc = ensure_ws(h, nrhs))) return rc;
+  const int *kc = nullptr, *jr = nullptr;
+  if ((rc = field_cuts(h, dr, &kc, &jr))) return rc;
   const double2 *g = (const double2 *)gamma;
   double2 *uo = (double2 *)u;
   {
     ems::ProfScope ps(h, "field_direct", st);
     HIPCHK(h, ems::launch_field_direct(h, g, nrhs, npts, pts, uo, st));
   }
-  HIPCHK(h, ems::launch_somm_aggregate(h, g, nrhs, false, false, st));
+  HIPCHK(h, ems::launch_somm_aggregate(h, g, nrhs, false, false, st, kc));
   HIPCHK(h, ems::launch_somm_reflect(h, nrhs, false, st));
   {
     ems::ProfScope ps(h, "field_refl", st);
@@ -1250,9 +1283,12 @@ extern "C" int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_
     return fail(h, EMS_ERR_ARG, "bad field arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   hipStream_t st = (hipStream_t)stream;
-  int rc = check_receivers(h, pts, npts, st);
+  double dr = 0.0;
+  int rc = check_receivers(h, pts, npts, st, &dr);
   if (rc) return rc;
   if ((rc = ensure_ws(h, nrhs))) return rc;
+  const int *kc = nullptr, *jr = nullptr;
+  if ((rc = field_cuts(h, dr, &kc, &jr))) return rc;
   const double2 *rs = (const double2 *)res;
   {
     ems::ProfScope ps(h, "field_direct_adjoint", st);
@@ -1263,7 +1299,7 @@ extern "C" int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_
     HIPCHK(h, ems::launch_field_refl_adjoint(h, rs, nrhs, npts, pts, st));
   }
   HIPCHK(h, ems::launch_somm_reflect(h, nrhs, true, st));
-  HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, true, false, st));
+  HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, true, false, st, jr));
   HIPCHK(h, ems::launch_combine(h, nullptr, (double2 *)g, nrhs, EMS_PART_FREE | EMS_PART_REFL,
                                 true, st));
   return EMS_OK;
@@ -1325,8 +1361,11 @@ extern "C" int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t
     return fail(h, EMS_ERR_ARG, "bad gradient arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   hipStream_t st = (hipStream_t)stream;
-  int rc = check_receivers(h, pts, npts, st);
+  double dr = 0.0;
+  int rc = check_receivers(h, pts, npts, st, &dr);
   if (rc) return rc;
+  const int *kc = nullptr, *jr = nullptr;
+  if ((rc = field_cuts(h, dr, &kc, &jr))) return rc;
   if (!h->ext && (rc = build_ext(h, st))) return rc;
   ems_handle *E = h->ext;
   if ((rc = ensure_ws(h, nrhs))) return rc;
@@ -1354,7 +1393,8 @@ extern "C" int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t
     if (r2) return fail(h, r2, std::string("extended incident: ") + E->err);
     HIPCHK(h, ems::launch_grad_centres(h, E, G, mu, ae, a0e, fe, ze, nrhs, dxy, st));
     // Lame parameters: node term
-    HIPCHK(h, ems::launch_somm_aggregate(h, G, nrhs, false, false, st));
+    // Ig meets the receivers' reflected terms as well: their depth ranges
+    HIPCHK(h, ems::launch_somm_aggregate(h, G, nrhs, false, false, st, kc));
     HIPCHK(h, ems::launch_lame_ig(h, nrhs, Ig, st));
     HIPCHK(h, ems::launch_somm_aggregate(h, mu, nrhs, true, false, st));
     HIPCHK(h, ems::launch_lame_lam(h, nrhs, Lam, false, st));

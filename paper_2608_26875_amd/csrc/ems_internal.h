@@ -71,8 +71,10 @@ struct DepthCuts {
   std::vector<int> perm, kcut, jr;
   double kept = 1.0;  // kept fraction of the (node, particle, wave) triples
 };
+// dother: depth of the shallowest point at the other end of a pair (the
+// shallowest particle for the operator; receivers may be shallower).
 void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<double> &xy, int pmax,
-                double eps, DepthCuts &out);
+                double eps, double dother, DepthCuts &out);
 
 // s(xi; k) for every wavenumber of the media at node (xi, bp, d):
 // out = {s_p, s_s, s_pb, s_sb}.
@@ -185,7 +187,10 @@ struct ems_handle {
   // depth order of the table rows / columns and the per-node and per-particle
   // ranges of the truncated contractions (with the tables)
   int *d_sperm = nullptr, *d_kcut = nullptr, *d_jr = nullptr;
-  double depth_kept = 1.0;
+  double depth_kept = 1.0, depth_min = 0.0;
+  // the same for receivers shallower than every particle (field evaluation)
+  int *d_kcut_f = nullptr, *d_jr_f = nullptr;
+  double cut_f_depth = -1.0;
   // tile candidate of the matrix-core kernels [aggregate/disaggregate][FP64/FP32]
   // [one / several right-hand sides]; -1: built-in default (ems_autotune sets it)
   int mfma_cfg[2][2][2] = {{{-1, -1}, {-1, -1}}, {{-1, -1}, {-1, -1}}};
@@ -283,17 +288,22 @@ hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int n
                       hipStream_t st);
 hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out, int nrhs,
                             hipStream_t st);
+// cut: the depth truncation's per-node prefixes (aggregate) or per-particle
+// node ranges (disaggregate) to use; nullptr = the build's (other end of
+// every pair at the shallowest particle's depth).
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
-                                 bool mixed, hipStream_t st);
+                                 bool mixed, hipStream_t st, const int *cut = nullptr);
 hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
-                                      int idx, hipStream_t st, bool adj = false);
+                                      int idx, hipStream_t st, bool adj = false,
+                                      const int *cut = nullptr);
 hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
-                                         hipStream_t st, bool adj = false);
+                                         hipStream_t st, bool adj = false,
+                                         const int *cut = nullptr);
 int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
 hipError_t launch_etables(ems_handle *h, hipStream_t st);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
-                                    hipStream_t st);
+                                    hipStream_t st, const int *cut = nullptr);
 // y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags.
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs,
                           int flags, bool adjoint, hipStream_t st);

@@ -283,10 +283,11 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
 // when its bound, with the shallowest particle at the other end, is below
 // eps times the peak of that bound for the shallowest pair.  The bound falls
 // with depth, so each node keeps a prefix of the particles in depth order,
+// and the other end may be taken shallower (receivers above the particles);
 // and each particle a set of nodes whose hull is recorded.  Complex nodes
 // (the tanh contour, user nodes off the axis) keep every particle.
 void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<double> &xy, int pmax,
-                double eps, DepthCuts &out) {
+                double eps, double dother, DepthCuts &out) {
   const int n = (int)(xy.size() / 2), q = (int)nodes.xi.size();
   std::vector<double> depth(n);
   for (int i = 0; i < n; ++i) depth[i] = -xy[2 * i + 1];
@@ -310,7 +311,7 @@ void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<doubl
     const double ap = t > md.kp ? std::sqrt((t - md.kp) * (t + md.kp)) : 0.0;
     const double as = t > md.ks ? std::sqrt((t - md.ks) * (t + md.ks)) : 0.0;
     const double amp = pmax * std::log(2.0 * t / kmin + 1.0);
-    const double other = amp - std::min(ap, as) * dmin;
+    const double other = amp - std::min(ap, as) * std::min(dmin, std::max(dother, 0.0));
     for (int w = 0; w < 2; ++w) {
       const double a = w ? as : ap;
       int c = n;

@@ -493,51 +493,52 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
 template <typename T, int NU, int NT, int RB, bool UNI>
 static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per,
                    const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
-                   hipStream_t st) {
+                   hipStream_t st, const int *cut) {
   hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI>),
                      dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
                      h->d_off, x, h->ncoef, Vp, Vs, h->d_agg, h->agg_chunks, per, E, h->d_sperm,
-                     h->d_kcut);
+                     cut);
 }
 template <typename T, int NU, bool UNI>
 static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
                      const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
-                     hipStream_t st) {
+                     hipStream_t st, const int *cut) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
-    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
-    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
-    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st); break;
+    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
+    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
   }
 }
 template <typename T, int NU, int NT, int RB>
 static void dis_go(const ems_handle *h, int nrhs, int per, const typename Mfma<T>::C *E,
-                   const double2 *Vp, const double2 *Vs, hipStream_t st) {
+                   const double2 *Vp, const double2 *Vs, hipStream_t st, const int *cut) {
   hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB>),
                      dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB)),
                      dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
                      h->d_off, Vp, Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, E,
-                     h->d_sperm, (const int2 *)h->d_jr);
+                     h->d_sperm, (const int2 *)cut);
 }
 template <typename T, int NU>
 static void dis_cand(const ems_handle *h, int idx, int nrhs, int per,
                      const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
-                     hipStream_t st) {
+                     hipStream_t st, const int *cut) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, Vp, Vs, st); break;
-    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, Vp, Vs, st); break;
-    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, Vp, Vs, st); break;
-    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, Vp, Vs, st); break;
+    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
+    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
   }
 }
 
 // Matrix-core aggregate with the candidate idx (prec 0 FP64 tables, 1 FP32;
 // adj: the adjoint's conjugated tables, FP64).
 hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
-                                      int idx, hipStream_t st, bool adj) {
+                                      int idx, hipStream_t st, bool adj, const int *cut) {
+  if (!cut) cut = h->d_kcut;
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
   const bool uni = h->p_uniform && pm_bucket(h->pmax) == h->pmax;
@@ -549,11 +550,11 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
 #define EMS_AGGM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
     if (prec == 1) {                                                                         \
-      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st);      \
-      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st);         \
+      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st, cut);      \
+      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st, cut);         \
     } else {                                                                                 \
-      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, E64, Vp, Vs, st);             \
-      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, E64, Vp, Vs, st);                \
+      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, E64, Vp, Vs, st, cut);             \
+      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, E64, Vp, Vs, st, cut);                \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }
@@ -564,7 +565,8 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
 }
 
 hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec, int idx,
-                                         hipStream_t st, bool adj) {
+                                         hipStream_t st, bool adj, const int *cut) {
+  if (!cut) cut = h->d_jr;
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
   if (adj) prec = 0;
@@ -574,8 +576,8 @@ hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec
   if (prec == 0 && !E64) return hipErrorInvalidValue;
 #define EMS_DISM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
-    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, Vp, Vs, st);          \
-    else dis_cand<double, NUV>(h, idx, nrhs, per, E64, Vp, Vs, st);                           \
+    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, Vp, Vs, st, cut);          \
+    else dis_cand<double, NUV>(h, idx, nrhs, per, E64, Vp, Vs, st, cut);                           \
     return hipGetLastError();                                                                \
   }
   EMS_DISM_NU(1)
@@ -594,16 +596,16 @@ static int pick(const ems_handle *h, int kernel, int prec, int nrhs) {
 }
 
 hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs, bool adjoint,
-                                 bool mixed, hipStream_t st) {
+                                 bool mixed, hipStream_t st, const int *cut) {
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   const int pb = pm_bucket(h->pmax);
   const bool uni = h->p_uniform && pb == h->pmax;
   if (!adjoint && h->d_Eagg != nullptr) {
     const int prec = (mixed && h->d_Eagg32) ? 1 : 0;
-    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st, false);
+    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st, false, cut);
   }
   if (adjoint && h->d_EaggA != nullptr)
-    return launch_somm_aggregate_mfma(h, x, nrhs, 0, pick(h, 0, 0, nrhs), st, true);
+    return launch_somm_aggregate_mfma(h, x, nrhs, 0, pick(h, 0, 0, nrhs), st, true, cut);
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pb) {
@@ -638,14 +640,14 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
     break;
 
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
-                                    hipStream_t st) {
+                                    hipStream_t st, const int *cut) {
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   if (!adjoint && h->d_Edis != nullptr) {
     const int prec = (mixed && h->d_Edis32) ? 1 : 0;
-    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, false);
+    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, false, cut);
   }
   if (adjoint && h->d_EdisA != nullptr)
-    return launch_somm_disaggregate_mfma(h, nrhs, 0, pick(h, 1, 0, nrhs), st, true);
+    return launch_somm_disaggregate_mfma(h, nrhs, 0, pick(h, 1, 0, nrhs), st, true, cut);
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pm_bucket(h->pmax)) {

@@ -72,3 +72,33 @@ def test_truncated_apply_after_autotune(ops):
         e = rel(to_np(cut.apply(x, flags=E.EMS_PART_REFL)), to_np(full.apply(x, flags=E.EMS_PART_REFL)))
         print("after autotune", nrhs, e, flush=True)
         assert e <= TOL
+
+
+def test_field_with_shallow_receivers(ops):
+    """Receivers above the shallowest particle: the field and its adjoint use
+    depth ranges formed for the receivers' depth and agree with the
+    untruncated kernels (the misfit gradient shares the same ranges)."""
+    w, cut, full = ops
+    rng = np.random.default_rng(77)
+    pts = np.stack([np.linspace(5.0, 195.0, 300), -rng.uniform(0.2, 0.6, 300)], axis=1)
+    # keep receivers outside every enclosing disk
+    d2 = ((pts[:, None, :] - w.xy[None, :, :]) ** 2).sum(-1)
+    pts = pts[np.all(d2 > (1.01 * w.radius[None, :]) ** 2, axis=1)]
+    assert len(pts) > 200 and (-pts[:, 1]).min() < (-w.xy[:, 1]).min()
+    g = to_gpu(W.random_coeffs(w.n_coeff, 61, nrhs=2))
+    uc = to_np(cut.scattered_field(g, pts))
+    uf = to_np(full.scattered_field(g, pts))
+    e = rel(uc, uf)
+    print("field", e, flush=True)
+    assert e <= TOL
+    res = torch.from_numpy(rng.standard_normal((2, len(pts), 2)) + 1j * rng.standard_normal((2, len(pts), 2))).cuda()
+    ac = to_np(cut.scattered_field_adjoint(res, pts))
+    af = to_np(full.scattered_field_adjoint(res, pts))
+    ea = rel(ac, af)
+    print("field adjoint", ea, flush=True)
+    assert ea <= TOL
+    # deep receivers below the shallowest particle use the build's ranges
+    deep = np.stack([np.linspace(5.0, 195.0, 50), np.full(50, -60.0)], axis=1)
+    ed = rel(to_np(cut.scattered_field(g, deep)), to_np(full.scattered_field(g, deep)))
+    print("deep field", ed, flush=True)
+    assert ed <= TOL
