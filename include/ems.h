@@ -91,9 +91,14 @@ typedef struct {
   double depth_cut;
 } ems_sommerfeld;
 
-/* Plane wave sent from the particle side towards the interface, direction
- * (sin a, cos a) in the paper frame.  wave 0: P, unit displacement
- * d e^{i kp d.x}; wave 1: SV, d_perp e^{i ks d.x} (Section 6.3). */
+/* Plane wave of unit displacement, |a| < pi/2.
+ *  wave 0: P from the particle side towards the interface, direction
+ *          d = (sin a, cos a) in the paper frame, d e^{i kp d.x};
+ *  wave 1: SV from the particle side, d_perp e^{i ks d.x}, d_perp = (-d2, d1);
+ *  wave 2: P sent from the substrate, d = (sin a, -cos a), d e^{i kpb d.x}
+ *          (Section 6.3's plane-wave setup: the particles see the wave
+ *          transmitted through the interface);
+ *  wave 3: SV sent from the substrate, d_perp e^{i ksb d.x}. */
 typedef struct {
   int32_t wave;
   double angle;
@@ -246,8 +251,10 @@ int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32
                       ems_stream_t stream);
 
 /* Right-hand side S_m (a0^m, b0^m) of the S-preconditioned system (Section
- * 3.2) for nrhs plane waves (incident + interface-reflected background,
- * Section 6.3), into device memory rhs [nrhs][n_coeff]. */
+ * 3.2) for nrhs plane waves, into device memory rhs [nrhs][n_coeff]: the
+ * local expansions of the background field in the host (Section 6.3,
+ * (bplan)): incident + interface-reflected waves for waves 0 and 1, the
+ * transmitted waves for waves 2 and 3. */
 int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void *rhs,
                  ems_stream_t stream);
 
@@ -268,18 +275,29 @@ int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_sol
 int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
                       const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream);
 
-/* Scattered displacement at npts host points (Section 4, coupled
- * representation: outgoing particle fields plus the reflected Sommerfeld
- * field).  gamma device [nrhs][n_coeff]; pts device [npts][2] doubles;
- * u device [nrhs][npts][2] complex128. */
+/* Scattered displacement at npts points (Section 4, coupled
+ * representation).  Host points (y < 0, outside every enclosing disk):
+ * outgoing particle fields plus the reflected Sommerfeld field; substrate
+ * points (y > 0): the particles' field transmitted through the interface
+ * (the same aggregate with T(xi) in place of R(xi)).  Points on y = 0 are
+ * rejected (EMS_ERR_GEOMETRY).  gamma device [nrhs][n_coeff]; pts device
+ * [npts][2] doubles; u device [nrhs][npts][2] complex128. */
 int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
                        const double *pts, void *u, ems_stream_t stream);
+
+/* Background displacement of nrhs plane waves (no particles; Section 6.3,
+ * (bplan)) at npts points of either layer: in the layer the wave is sent
+ * from, incident + reflected; in the other layer, transmitted.  pts device
+ * [npts][2] (y != 0), u device [nrhs][npts][2] complex128.  The total field
+ * is this plus ems_eval_scattered of the solved coefficients. */
+int ems_eval_background(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs,
+                        int32_t npts, const double *pts, void *u, ems_stream_t stream);
 
 /* Conjugate transpose of ems_eval_scattered: g = F^H res, the right-hand
  * side A^H lambda = F^H res of the adjoint system of a receiver misfit
  * J = 1/2 sum |u - u_obs|^2 (res = u - u_obs).  res device [nrhs][npts][2]
  * complex128, pts device [npts][2], g device [nrhs][n_coeff] (overwritten).
- * Receivers are validated as in ems_eval_scattered. */
+ * Receivers must lie in the host (y < 0) outside every enclosing disk. */
 int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_t nrhs, int32_t npts,
                                const double *pts, void *g, ems_stream_t stream);
 
@@ -296,7 +314,8 @@ int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_t nrhs, int
  * (dJ/dlambda_b, dJ/dmu_b).  The first call after a build constructs an
  * internal operator with orders p + 1 (so p <= 15 here).  Synchronous.
  * Errors: EMS_ERR_ARG, EMS_ERR_STATE, EMS_ERR_GEOMETRY (receivers),
- * EMS_ERR_UNIMPLEMENTED (p = 16), EMS_ERR_HIP, EMS_ERR_NUMERIC. */
+ * EMS_ERR_UNIMPLEMENTED (p = 16, or waves 2 and 3 from the substrate),
+ * EMS_ERR_HIP, EMS_ERR_NUMERIC. */
 int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, const void *gamma,
                   const void *lam, int32_t npts, const double *pts, const void *res, double *dxy,
                   double *dlame, ems_stream_t stream);

@@ -1,4 +1,5 @@
-"""Scattered displacement at host points (Section 4, coupled representation).
+"""Scattered displacement (Section 4, coupled representation): host points
+(y < 0) and, transmitted through the interface, substrate points (y > 0).
 
 u^sc(x) = sum_m sum_n alpha^m_n grad(H_n(kp r_m) e^{i n theta_m})
                   + beta^m_n grad^perp(H_n(ks r_m) e^{i n theta_m})
@@ -103,5 +104,61 @@ def reflected_part(w, m: Media, gamma: np.ndarray, pts: np.ndarray, tol: float =
     return np.stack([v[:npt], v[npt:]], axis=1)
 
 
+def transmitted_part(w, m: Media, gamma: np.ndarray, pts: np.ndarray, tol: float = 1e-13,
+                     T: float | None = None, limit: int = 200000) -> np.ndarray:
+    """Displacement at substrate points (y > 0) [n, 2] -> [n, 2]: the particles'
+    upgoing potentials (the aggregate of ``reflected_part``) crossing the
+    interface with the transmission T(xi) of ``interface.reflect_transmit``,
+    phi_T = int e^{i xi x - s_pb y} TP(xi) dxi and psi_T likewise with TS, so
+    grad -> (i xi, -s_pb) and grad^perp -> (s_sb, i xi)."""
+    kp, ks = m.kp, m.ks
+    groups = sommerfeld._Groups(w, range(w.n))
+    coef = []
+    for pv, sel, xs, ys, o in groups.items:
+        Np = 2 * pv + 1
+        c = gamma[o[:, None] + np.arange(2 * Np)[None, :]]
+        coef.append((c[:, :Np], c[:, Np:]))
+    px, py = pts[:, 0], pts[:, 1]
+    npt = len(pts)
+
+    def f(xi, bp=None, d=None):
+        sv = interface.s_values(xi, m, bp, d)
+        sp, ss, spb, ssb = sv
+        zp = (xi - sp) / kp
+        zs = (xi - ss) / ks
+        Ip = 0j
+        Is = 0j
+        for (pv, sel, xs, ys, o), (ca, cb) in zip(groups.items, coef):
+            n = np.arange(-pv, pv + 1)
+            Ip += np.sum(np.exp(sp * ys - 1j * xi * xs) * (ca @ ((-1j * zp) ** n)))
+            Is += np.sum(np.exp(ss * ys - 1j * xi * xs) * (cb @ ((-1j * zs) ** n)))
+        Ip /= 1j * math.pi * sp
+        Is /= 1j * math.pi * ss
+        _, Tm = interface.reflect_transmit(xi, m, sv)
+        TP = Tm[0, 0] * Ip + Tm[0, 1] * Is
+        TS = Tm[1, 0] * Ip + Tm[1, 1] * Is
+        ep = np.exp(1j * xi * px - spb * py) * TP
+        es = np.exp(1j * xi * px - ssb * py) * TS
+        ux = 1j * xi * ep + ssb * es
+        uy = -spb * ep + 1j * xi * es
+        v = np.concatenate([ux, uy])
+        return np.concatenate([v.real, v.imag])
+
+    if T is None:
+        T = sommerfeld.tail_extent(w, m)
+    pieces = sommerfeld._pieces(m, T)
+    v, _, _ = sommerfeld._integrate(f, 2 * npt, pieces, tol, limit)
+    return np.stack([v[:npt], v[npt:]], axis=1)
+
+
 def scattered(w, m: Media, gamma: np.ndarray, pts: np.ndarray, tol: float = 1e-13) -> np.ndarray:
-    return direct_part(w, m, gamma, pts) + reflected_part(w, m, gamma, pts, tol=tol)
+    """Host points (y < 0): direct + reflected; substrate points (y > 0): transmitted."""
+    pts = np.asarray(pts, dtype=float)
+    u = np.zeros((len(pts), 2), dtype=complex)
+    host = pts[:, 1] < 0
+    if host.any():
+        ph = pts[host]
+        u[host] = direct_part(w, m, gamma, ph) + reflected_part(w, m, gamma, ph, tol=tol)
+    if (~host).any():
+        u[~host] = transmitted_part(w, m, gamma, pts[~host], tol=tol)
+    return u

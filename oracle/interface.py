@@ -91,6 +91,22 @@ def reflect_transmit(xi, m: Media, svals=None):
     return X[:2, :], X[2:, :]
 
 
+def from_substrate(xi, m: Media, svals=None):
+    """(Td, Rb), each 2x2, for waves sent from the substrate (Section 6.3's
+    plane-wave setup): a unit downgoing potential e^{i xi x + s_b y} (column
+    0 P, column 1 S) meets the same four continuity conditions with the
+    unknowns host downgoing (Td, e^{i xi x + s y}) and substrate upgoing (Rb,
+    e^{i xi x - s_b y}):
+      [P_h(+s_p), S_h(+s_s), -P_b(-s_pb), -S_b(-s_sb)] X = [P_b(+s_pb), S_b(+s_sb)].
+    """
+    sp, ss, spb, ssb = svals if svals is not None else s_values(xi, m)
+    M, _ = system(xi, m, (sp, ss, spb, ssb))
+    Pd, _ = _cols(xi, +spb, m.lam_b, m.mu_b)
+    _, Sd = _cols(xi, +ssb, m.lam_b, m.mu_b)
+    X = np.linalg.solve(M, np.stack([Pd, Sd], axis=1))
+    return X[:2, :], X[2:, :]
+
+
 def reflection(xi, m: Media, svals=None) -> np.ndarray:
     return reflect_transmit(xi, m, svals)[0]
 

@@ -32,6 +32,9 @@ EMS_PART_S = 4
 EMS_PART_IDENTITY = 8
 EMS_APPLY_ALL = 15
 EMS_MIXED = 256
+# plane-wave kinds: P / SV sent from the particle side (host), P / SV sent
+# from the substrate (transmitted into the host)
+WAVE_P, WAVE_SV, WAVE_P_SUBSTRATE, WAVE_SV_SUBSTRATE = 0, 1, 2, 3
 EMS_OK = 0
 EMS_NOT_CONVERGED = 1
 
@@ -114,6 +117,7 @@ def _load():
         "ems_solve_adjoint": ([P, P, P, I32, ctypes.POINTER(SolverOpts), ctypes.POINTER(SolveInfo),
                                P], I32),
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
+        "ems_eval_background": ([P, ctypes.POINTER(PlaneWave), I32, I32, P, P, P], I32),
         "ems_eval_scattered_adjoint": ([P, P, I32, I32, P, P, P], I32),
         "ems_autotune": ([P, I32, ctypes.POINTER(ctypes.c_int32), P], I32),
         "ems_apply_graph": ([P, P, P, I32, I32, I32, P], I32),
@@ -141,7 +145,8 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
             "ems_apply_graph",
-            "ems_eval_scattered", "ems_sommerfeld_nodes", "ems_sommerfeld_depth_cuts",
+            "ems_eval_scattered", "ems_eval_background", "ems_sommerfeld_nodes",
+            "ems_sommerfeld_depth_cuts",
             "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
 
@@ -330,7 +335,8 @@ class Operator:
         return y
 
     def incident(self, waves, stream=None):
-        """waves: list of (wave, angle) with wave 0 = P, 1 = SV."""
+        """waves: list of (wave, angle); wave 0 = P, 1 = SV from the particle
+        side, 2 = P, 3 = SV sent from the substrate."""
         import torch
         arr = (PlaneWave * len(waves))(*[PlaneWave(int(w), float(a)) for w, a in waves])
         out = torch.empty((len(waves), self.n_coeff), dtype=torch.complex128, device="cuda")
@@ -338,8 +344,21 @@ class Operator:
                                       _stream_ptr(stream)))
         return out
 
+    def background_field(self, waves, pts, stream=None):
+        """Background displacement [nwaves, npts, 2] of plane waves at points of
+        either layer (y != 0)."""
+        import torch
+        arr = (PlaneWave * len(waves))(*[PlaneWave(int(w), float(a)) for w, a in waves])
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+        out = torch.empty((len(waves), p.shape[0], 2), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_eval_background(self.h, arr, len(waves), int(p.shape[0]),
+                                             ctypes.c_void_p(p.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def scattered_field(self, gamma, pts, stream=None):
-        """Scattered displacement [nrhs, npts, 2] complex128 at host points pts [npts, 2]."""
+        """Scattered displacement [nrhs, npts, 2] complex128 at points pts [npts, 2]:
+        host points (y < 0) and substrate points (y > 0, transmitted field)."""
         import torch
         nrhs = self._vec_check(gamma)
         p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()

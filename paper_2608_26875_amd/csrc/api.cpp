@@ -16,6 +16,8 @@ hipError_t launch_s_apply(const ems_handle *h, const double2 *c, double2 *y, int
                           bool adjoint, hipStream_t st);
 hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, double2 *c,
                               hipStream_t st);
+hipError_t launch_background(int nrhs, int npts, const double *pts, const double2 *comp,
+                             double2 *u, hipStream_t st);
 }  // namespace ems
 
 using ems::cd;
@@ -25,6 +27,67 @@ namespace {
 int fail(ems_handle *h, int code, const std::string &msg) {
   if (h) h->err = msg;
   return code;
+}
+
+// The plane waves that make up the background field of one incident plane
+// wave (Section 6.3, (bplan)): potentials A e^{i xi0 x + q y} in the host
+// (layer 0) or the substrate (layer 1), P (kind 0) or S (kind 1); `up` marks
+// a wave travelling towards y > 0 (q = -s), else q = +s.
+struct PwComp {
+  int layer, kind;
+  bool up;
+  cd A, q;
+};
+struct PwParts {
+  double xi0 = 0.0;
+  cd s4[4];
+  std::vector<PwComp> comp;
+};
+
+int plane_wave_parts(const ems::Media &md, const ems_plane_wave &w, PwParts &out,
+                     std::string &err) {
+  const int wv = w.wave;
+  if (wv < 0 || wv > 3) {
+    err = "wave must be 0 (P) or 1 (SV) from the host, 2 (P) or 3 (SV) from the substrate";
+    return EMS_ERR_ARG;
+  }
+  if (!(std::cos(w.angle) > 0)) {
+    err = "plane wave must travel towards the interface (|angle| < pi/2)";
+    return EMS_ERR_ARG;
+  }
+  const double k = wv == 0 ? md.kp : wv == 1 ? md.ks : wv == 2 ? md.kpb : md.ksb;
+  const cd I(0.0, 1.0);
+  const double xi0 = k * std::sin(w.angle);
+  const cd A = 1.0 / (I * k);  // unit displacement
+  out.xi0 = xi0;
+  ems::node_s(cd(xi0, 0.0), 0.0, 0.0, md, out.s4);
+  const cd *s = out.s4;
+  out.comp.clear();
+  cd X[4], Y[4];
+  if (wv < 2) {
+    if (ems::reflect_transmit_s(cd(xi0, 0.0), s, md, X, Y)) {
+      err = "singular interface system at the incident wavenumber";
+      return EMS_ERR_NUMERIC;
+    }
+    const int c = wv;  // incident column
+    out.comp.push_back({0, c, true, A, -s[c]});
+    out.comp.push_back({0, 0, false, X[0 + c] * A, s[0]});
+    out.comp.push_back({0, 1, false, X[2 + c] * A, s[1]});
+    out.comp.push_back({1, 0, true, Y[0 + c] * A, -s[2]});
+    out.comp.push_back({1, 1, true, Y[2 + c] * A, -s[3]});
+  } else {
+    if (ems::from_substrate_s(cd(xi0, 0.0), s, md, X, Y)) {
+      err = "singular interface system at the incident wavenumber";
+      return EMS_ERR_NUMERIC;
+    }
+    const int c = wv - 2;
+    out.comp.push_back({1, c, false, A, s[2 + c]});
+    out.comp.push_back({1, 0, true, Y[0 + c] * A, -s[2]});
+    out.comp.push_back({1, 1, true, Y[2 + c] * A, -s[3]});
+    out.comp.push_back({0, 0, false, X[0 + c] * A, s[0]});
+    out.comp.push_back({0, 1, false, X[2 + c] * A, s[1]});
+  }
+  return EMS_OK;
 }
 
 #define HIPCHK(h, call)                                                                   \
@@ -69,6 +132,9 @@ void free_device(ems_handle *h) {
   dfree(h->d_ss);
   dfree(h->d_R);
   dfree(h->d_dR);
+  dfree(h->d_Tu);
+  dfree(h->d_spb);
+  dfree(h->d_ssb);
   if (h->ext) {
     ems_destroy(h->ext);
     h->ext = nullptr;
@@ -580,17 +646,22 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   // power tables padded to the kernels' compile-time order (zeros beyond pmax)
   const int pmb = ems::pm_bucket(h->pmax);
   const int q = h->q, ld = 2 * pmb + 1;
-  std::vector<double2> xi(q), w(q), sp(q), ss(q), R(4 * (size_t)q), dR(8 * (size_t)q),
-      Vp((size_t)q * ld), Vs((size_t)q * ld);
+  std::vector<double2> xi(q), w(q), sp(q), ss(q), spb(q), ssb(q), R(4 * (size_t)q),
+      Tu(4 * (size_t)q), dR(8 * (size_t)q), Vp((size_t)q * ld), Vs((size_t)q * ld);
   const cd I(0.0, 1.0);
   for (int j = 0; j < q; ++j) {
     const cd x = nt.xi[j];
     cd s4[4];
     ems::node_s(x, nt.bp[j], nt.d[j], h->md, s4);
     const cd s1 = s4[0], s2 = s4[1];
-    cd Rj[4], dRj[8];
+    cd Rj[4], dRj[8], Rt[4], Tj[4];
     rc = ems::reflection_deriv_s(x, s4, h->md, Rj, dRj);
     if (rc) return fail(h, rc, "singular interface system at a Sommerfeld node");
+    rc = ems::reflect_transmit_s(x, s4, h->md, Rt, Tj);
+    if (rc) return fail(h, rc, "singular interface system at a Sommerfeld node");
+    for (int k = 0; k < 4; ++k) Tu[4 * (size_t)j + k] = make_double2(Tj[k].real(), Tj[k].imag());
+    spb[j] = make_double2(s4[2].real(), s4[2].imag());
+    ssb[j] = make_double2(s4[3].real(), s4[3].imag());
     for (int k = 0; k < 8; ++k) dR[8 * (size_t)j + k] = make_double2(dRj[k].real(), dRj[k].imag());
     xi[j] = make_double2(x.real(), x.imag());
     w[j] = make_double2(nt.w[j].real(), nt.w[j].imag());
@@ -666,6 +737,9 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if ((rc = upload(h, h->d_ss, ss.data(), ss.size()))) return rc;
   if ((rc = upload(h, h->d_R, R.data(), R.size()))) return rc;
   if ((rc = upload(h, h->d_dR, dR.data(), dR.size()))) return rc;
+  if ((rc = upload(h, h->d_Tu, Tu.data(), Tu.size()))) return rc;
+  if ((rc = upload(h, h->d_spb, spb.data(), spb.size()))) return rc;
+  if ((rc = upload(h, h->d_ssb, ssb.data(), ssb.size()))) return rc;
   if ((rc = upload(h, h->d_Vp, Vp.data(), Vp.size()))) return rc;
   if ((rc = upload(h, h->d_Vs, Vs.data(), Vs.size()))) return rc;
   {
@@ -850,23 +924,19 @@ int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void 
   if (!h || !waves || !rhs || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad incident arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   hipStream_t st = (hipStream_t)stream;
+  // host-side plane waves: {xi0, s_p, s_s, upgoing P, S, downgoing P, S}
   std::vector<double2> pw(7 * (size_t)nrhs);
-  const cd I(0.0, 1.0);
   for (int r = 0; r < nrhs; ++r) {
-    const int wv = waves[r].wave;
-    if (wv != 0 && wv != 1) return fail(h, EMS_ERR_ARG, "wave must be 0 (P) or 1 (SV)");
-    const double k = wv == 0 ? h->md.kp : h->md.ks;
-    const double xi0 = k * std::sin(waves[r].angle);
-    if (!(std::cos(waves[r].angle) > 0))
-      return fail(h, EMS_ERR_ARG, "plane wave must travel towards the interface (|angle| < pi/2)");
-    const cd A = 1.0 / (I * k);
-    const cd Ain_p = wv == 0 ? A : 0.0, Ain_s = wv == 1 ? A : 0.0;
-    cd R[4];
-    int rc = ems::reflection(cd(xi0, 0.0), h->md, R);
-    if (rc) return fail(h, rc, "singular interface system at the incident wavenumber");
-    const cd Ar_p = R[0] * Ain_p + R[1] * Ain_s, Ar_s = R[2] * Ain_p + R[3] * Ain_s;
-    const cd s1 = ems::branch_s(cd(xi0, 0.0), h->md.kp), s2 = ems::branch_s(cd(xi0, 0.0), h->md.ks);
-    const cd v[7] = {cd(xi0, 0.0), s1, s2, Ain_p, Ain_s, Ar_p, Ar_s};
+    PwParts pp;
+    const int rc = plane_wave_parts(h->md, waves[r], pp, h->err);
+    if (rc) return rc;
+    cd up[2] = {0.0, 0.0}, dn[2] = {0.0, 0.0};
+    for (const PwComp &c : pp.comp) {
+      if (c.layer != 0) continue;
+      if (c.up) up[c.kind] += c.A;
+      else dn[c.kind] += c.A;
+    }
+    const cd v[7] = {cd(pp.xi0, 0.0), pp.s4[0], pp.s4[1], up[0], up[1], dn[0], dn[1]};
     for (int k2 = 0; k2 < 7; ++k2) pw[7 * (size_t)r + k2] = make_double2(v[k2].real(), v[k2].imag());
   }
   const size_t nvec = (size_t)nrhs * h->ncoef;
@@ -877,6 +947,50 @@ int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void 
   HIPCHK(h, hipMemcpyAsync(dpw, pw.data(), pw.size() * sizeof(double2), hipMemcpyHostToDevice, st));
   HIPCHK(h, ems::launch_incident_pw(h, dpw, nrhs, c, st));
   HIPCHK(h, ems::launch_s_apply(h, c, (double2 *)rhs, nrhs, false, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  return EMS_OK;
+}
+
+int ems_eval_background(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, int32_t npts,
+                        const double *pts, void *u, ems_stream_t stream) {
+  if (!h || !waves || !pts || !u || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad background arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  {
+    std::vector<double> hp(2 * (size_t)npts);
+    HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost,
+                             st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    for (int i = 0; i < npts; ++i) {
+      if (!std::isfinite(hp[2 * i]) || !std::isfinite(hp[2 * i + 1]))
+        return fail(h, EMS_ERR_NUMERIC, "non-finite point");
+      if (hp[2 * i + 1] == 0.0) return fail(h, EMS_ERR_GEOMETRY, "point on the interface (y = 0)");
+    }
+  }
+  std::vector<double2> comp(18 * (size_t)nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    PwParts pp;
+    const int rc = plane_wave_parts(h->md, waves[r], pp, h->err);
+    if (rc) return rc;
+    for (int c = 0; c < 6; ++c) {
+      double2 *C = comp.data() + ((size_t)r * 6 + c) * 3;
+      if (c < (int)pp.comp.size()) {
+        const PwComp &k = pp.comp[c];
+        C[0] = make_double2(k.A.real(), k.A.imag());
+        C[1] = make_double2(k.q.real(), k.q.imag());
+        C[2] = make_double2(pp.xi0, 2.0 * k.layer + k.kind);
+      } else {
+        C[0] = C[1] = make_double2(0.0, 0.0);
+        C[2] = make_double2(0.0, -1.0);
+      }
+    }
+  }
+  int rc = ensure_tmp(h, sizeof(double2) * comp.size());
+  if (rc) return rc;
+  HIPCHK(h, hipMemcpyAsync(h->d_tmp, comp.data(), comp.size() * sizeof(double2),
+                           hipMemcpyHostToDevice, st));
+  HIPCHK(h, ems::launch_background(nrhs, npts, pts, h->d_tmp, (double2 *)u, st));
   HIPCHK(h, hipStreamSynchronize(st));
   return EMS_OK;
 }
@@ -1203,17 +1317,27 @@ extern "C" int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t 
 namespace {
 
 // Receivers must lie in the host layer (y < 0) and outside every enclosing disk.
+// Receivers: finite, off the interface, in the host outside every enclosing
+// disk, or (when substrate is non-null) in the substrate, counted there.
 int check_receivers(ems_handle *h, const double *pts, int npts, hipStream_t st,
-                    double *depth = nullptr) {
+                    double *depth = nullptr, int *substrate = nullptr) {
   std::vector<double> hp(2 * (size_t)npts);
   HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(h, hipStreamSynchronize(st));
   if (depth) *depth = HUGE_VAL;
+  if (substrate) *substrate = 0;
   for (int i = 0; i < npts; ++i) {
     const double x = hp[2 * i], y = hp[2 * i + 1];
-    if (depth) *depth = std::min(*depth, -y);
     if (!std::isfinite(x) || !std::isfinite(y)) return fail(h, EMS_ERR_NUMERIC, "non-finite receiver");
-    if (!(y < 0)) return fail(h, EMS_ERR_GEOMETRY, "receiver not in the host layer (y < 0)");
+    if (depth) *depth = std::min(*depth, -y);
+    if (substrate && y > 0) {
+      ++*substrate;
+      continue;
+    }
+    if (!(y < 0))
+      return fail(h, EMS_ERR_GEOMETRY,
+                  substrate ? "receiver on the interface (y = 0)"
+                            : "receiver not in the host layer (y < 0)");
     for (int m = 0; m < h->n; ++m) {
       const double dx = x - h->xy[2 * m], dy = y - h->xy[2 * m + 1];
       if (dx * dx + dy * dy <= h->R[m] * h->R[m])
@@ -1256,7 +1380,8 @@ extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   hipStream_t st = (hipStream_t)stream;
   double dr = 0.0;
-  int rc = check_receivers(h, pts, npts, st, &dr);
+  int nsub = 0;
+  int rc = check_receivers(h, pts, npts, st, &dr, &nsub);
   if (rc) return rc;
   if ((rc = ensure_ws(h, nrhs))) return rc;
   const int *kc = nullptr, *jr = nullptr;
@@ -1272,6 +1397,12 @@ extern "C" int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs
   {
     ems::ProfScope ps(h, "field_refl", st);
     HIPCHK(h, ems::launch_field_refl(h, nrhs, npts, pts, uo, st));
+  }
+  if (nsub > 0) {
+    // substrate receivers: the same aggregate through T(xi) instead of R(xi)
+    HIPCHK(h, ems::launch_somm_reflect(h, nrhs, false, st, true));
+    ems::ProfScope ps(h, "field_trans", st);
+    HIPCHK(h, ems::launch_field_trans(h, nrhs, npts, pts, uo, st));
   }
   return EMS_OK;
 }
@@ -1360,6 +1491,10 @@ extern "C" int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t
   if (!h || !waves || !gamma || !lam || !pts || !res || !dxy || !dlame || nrhs <= 0 || npts <= 0)
     return fail(h, EMS_ERR_ARG, "bad gradient arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  for (int r = 0; r < nrhs; ++r)
+    if (waves[r].wave != 0 && waves[r].wave != 1)
+      return fail(h, EMS_ERR_UNIMPLEMENTED,
+                  "gradient for waves sent from the substrate (dT/dtheta) is not built");
   hipStream_t st = (hipStream_t)stream;
   double dr = 0.0;
   int rc = check_receivers(h, pts, npts, st, &dr);

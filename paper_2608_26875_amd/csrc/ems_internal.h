@@ -84,6 +84,12 @@ void node_s(cd xi, double bp, double d, const Media &md, cd out[4]);
 // with the four branch values s given (node_s) or formed from xi.
 int reflection(cd xi, const Media &md, cd R[4]);
 int reflection_s(cd xi, const cd s[4], const Media &md, cd R[4]);
+// The same system with the transmitted (substrate upgoing) potentials T too,
+// and for waves sent from the substrate: Td = host downgoing (transmitted),
+// Rb = substrate upgoing (reflected) potentials per unit downgoing P / S.
+int reflect_transmit_s(cd xi, const cd s4[4], const Media &md, cd R[4], cd T[4]);
+int from_substrate_s(cd xi, const cd s4[4], const Media &md, cd Td[4], cd Rb[4]);
+int from_substrate(cd xi, const Media &md, cd Td[4], cd Rb[4]);
 int reflection_deriv_s(cd xi, const cd s4[4], const Media &md, cd R[4], cd dR[8]);
 int reflection_deriv(cd xi, const Media &md, cd R[4], cd dR[8]);
 
@@ -177,6 +183,8 @@ struct ems_handle {
   double2 *d_xi = nullptr, *d_w = nullptr, *d_sp = nullptr, *d_ss = nullptr;
   double2 *d_R = nullptr;        // [q][4]
   double2 *d_dR = nullptr;       // [q][8]: dR/dlambda_b, dR/dmu_b (substrate), row-major 2x2
+  double2 *d_Tu = nullptr;       // [q][4]: transmission into the substrate, row-major 2x2
+  double2 *d_spb = nullptr, *d_ssb = nullptr;  // [q]: s of the substrate's P and S waves
   double2 *d_Vp = nullptr, *d_Vs = nullptr;  // [q][2 PMb + 1]: (-i zeta)^n, |n| <= pmax, 0 beyond
   double2 *d_Eagg = nullptr, *d_Edis = nullptr;  // tabulated exponentials (optional)
   float2 *d_Eagg32 = nullptr, *d_Edis32 = nullptr;  // complex64 copies for the mixed form (optional)
@@ -300,7 +308,8 @@ hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec
                                          hipStream_t st, bool adj = false,
                                          const int *cut = nullptr);
 int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb);
-hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st);
+hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st,
+                               bool transmit = false);
 hipError_t launch_etables(ems_handle *h, hipStream_t st);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut = nullptr);
@@ -350,6 +359,8 @@ hipError_t launch_field_direct_adjoint(const ems_handle *h, const double2 *res, 
                                        int npts, const double *pts, double2 *g, hipStream_t st);
 hipError_t launch_field_refl_adjoint(const ems_handle *h, const double2 *res, int nrhs, int npts,
                                      const double *pts, hipStream_t st);
+hipError_t launch_field_trans(const ems_handle *h, int nrhs, int npts, const double *pts,
+                              double2 *u, hipStream_t st);
 hipError_t launch_field_refl(const ems_handle *h, int nrhs, int npts, const double *pts,
                              double2 *u, hipStream_t st);
 

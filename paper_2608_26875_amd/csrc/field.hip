@@ -1,4 +1,5 @@
-// Scattered displacement at host points (Section 4, coupled representation):
+// Scattered displacement at host points (y < 0; Section 4, coupled
+// representation; substrate points y > 0 see the transmitted part only):
 //   u(x) = sum_m sum_n alpha^m_n grad v_n^{kp}(x - x_m) + beta^m_n grad^perp v_n^{ks}(x - x_m)
 //          + grad phi_R + grad^perp psi_R,
 // v_n^k = H_n(k r) e^{i n theta}, d_x v_n = (k/2)(v_{n-1} - v_{n+1}),
@@ -24,7 +25,9 @@ __global__ __launch_bounds__(256) void field_direct_kernel(
   const double px = pts[2 * ipc], py = pts[2 * ipc + 1];
   const double2 *g = gam + (int64_t)r * ldg;
   double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
-  for (int m = 0; m < n; ++m) {
+  // receivers in the substrate (y > 0) see only the transmitted field
+  const int nm = py < 0.0 ? n : 0;
+  for (int m = 0; m < nm; ++m) {
     const double dx = px - xy[2 * m], dy = py - xy[2 * m + 1];
     const double rr = sqrt(dx * dx + dy * dy);
     const double th = atan2(dy, dx);
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(256) void field_refl_kernel(
   const int r = blockIdx.y;
   if (ip >= npts) return;
   const double px = pts[2 * ip], py = pts[2 * ip + 1];
+  if (!(py < 0.0)) return;  // host receivers only
   const double2 *RP = g + (int64_t)(r * 2 + 0) * q;
   const double2 *RS = g + (int64_t)(r * 2 + 1) * q;
   double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
@@ -113,6 +117,36 @@ __global__ __launch_bounds__(256) void field_refl_kernel(
   o[1] = cadd(o[1], uy);
 }
 
+
+// Transmitted part at substrate receivers (y > 0): the particles' upgoing
+// potentials cross the interface as e^{i xi x - s_b y} TP_j (P) and TS_j (S),
+// the substrate's upgoing potentials (weights included); grad -> (i xi,
+// -s_pb), grad^perp -> (s_sb, i xi).
+__global__ __launch_bounds__(256) void field_trans_kernel(
+    int q, int npts, const double2 *__restrict__ xi_t, const double2 *__restrict__ spb_t,
+    const double2 *__restrict__ ssb_t, const double2 *__restrict__ g,
+    const double *__restrict__ pts, double2 *__restrict__ u) {
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (ip >= npts) return;
+  const double px = pts[2 * ip], py = pts[2 * ip + 1];
+  if (!(py > 0.0)) return;
+  const double2 *TP = g + (int64_t)(r * 2 + 0) * q;
+  const double2 *TS = g + (int64_t)(r * 2 + 1) * q;
+  double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
+  for (int j = 0; j < q; ++j) {
+    const double2 xi = xi_t[j], sp = spb_t[j], ss = ssb_t[j];
+    const double2 ixi = make_double2(-xi.y, xi.x);
+    // e^{i xi x - s y}
+    const double2 ep = cmul(cexp(make_double2(-xi.y * px - sp.x * py, xi.x * px - sp.y * py)), TP[j]);
+    const double2 es = cmul(cexp(make_double2(-xi.y * px - ss.x * py, xi.x * px - ss.y * py)), TS[j]);
+    ux = cadd(ux, cadd(cmul(ixi, ep), cmul(ss, es)));
+    uy = cadd(uy, csub(cmul(ixi, es), cmul(sp, ep)));
+  }
+  double2 *o = u + ((int64_t)r * npts + ip) * 2;
+  o[0] = cadd(o[0], ux);
+  o[1] = cadd(o[1], uy);
+}
 
 // Adjoint of the field evaluation, g = F^H res (the right-hand side of the
 // adjoint system of a receiver misfit).  Direct part, lane = particle, one
@@ -302,6 +336,14 @@ hipError_t launch_field_refl_adjoint(const ems_handle *h, const double2 *res, in
   dim3 grid((h->q + 255) / 256, nrhs);
   hipLaunchKernelGGL(field_refl_adjoint_kernel, grid, dim3(256), 0, st, h->q, npts, h->agg_chunks,
                      h->d_xi, h->d_sp, h->d_ss, pts, res, h->d_agg);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_trans(const ems_handle *h, int nrhs, int npts, const double *pts,
+                              double2 *u, hipStream_t st) {
+  dim3 grid((npts + 255) / 256, nrhs);
+  hipLaunchKernelGGL(field_trans_kernel, grid, dim3(256), 0, st, h->q, npts, h->d_xi, h->d_spb,
+                     h->d_ssb, h->d_refl, pts, u);
   return hipGetLastError();
 }
 

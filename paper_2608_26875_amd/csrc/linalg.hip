@@ -146,6 +146,46 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
   return hipGetLastError();
 }
 
+// Background displacement of plane waves at receivers of either layer.
+// comp [nrhs][6][3]: per component {A, q, (xi0, code)}, the potential
+// A e^{i xi0 x + q y}; code = 2 layer + kind (layer 0 host y < 0, 1
+// substrate y > 0; kind 0 P: grad -> (i xi0, q), kind 1 S: grad^perp ->
+// (-q, i xi0)), code < 0 an unused slot.
+__global__ void background_kernel(int npts, const double *__restrict__ pts,
+                                  const double2 *__restrict__ comp, double2 *__restrict__ u) {
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (ip >= npts) return;
+  const double x = pts[2 * ip], y = pts[2 * ip + 1];
+  const int layer = y < 0.0 ? 0 : 1;
+  double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
+  for (int c = 0; c < 6; ++c) {
+    const double2 *C = comp + ((int64_t)r * 6 + c) * 3;
+    const int code = (int)C[2].y;
+    if (code < 0 || (code >> 1) != layer) continue;
+    const double2 q = C[1];
+    const double2 ixi = make_double2(0.0, C[2].x);
+    const double2 e = cmul(C[0], cexp(make_double2(q.x * y, C[2].x * x + q.y * y)));
+    if ((code & 1) == 0) {
+      ux = cadd(ux, cmul(ixi, e));
+      uy = cadd(uy, cmul(q, e));
+    } else {
+      ux = csub(ux, cmul(q, e));
+      uy = cadd(uy, cmul(ixi, e));
+    }
+  }
+  double2 *o = u + ((int64_t)r * npts + ip) * 2;
+  o[0] = ux;
+  o[1] = uy;
+}
+
+hipError_t launch_background(int nrhs, int npts, const double *pts, const double2 *comp,
+                             double2 *u, hipStream_t st) {
+  hipLaunchKernelGGL(background_kernel, dim3((npts + 255) / 256, nrhs), dim3(256), 0, st, npts,
+                     pts, comp, u);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // GMRES vector kernels.  Reductions write one partial per block and are
 // finished by a single-block kernel in a fixed order (reproducible).

@@ -405,7 +405,12 @@ int reflection(cd xi, const Media &md, cd R[4]) {
   return reflection_s(xi, s, md, R);
 }
 
-int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
+// The four continuity conditions (u_x, u_y, t_xy, t_yy at y = 0, Section
+// 2.2) for potentials at one xi.  Unknowns: host downgoing P, S (e^{+s y})
+// and substrate upgoing P, S (e^{-s_b y}); M = [P_h(+s_p), S_h(+s_s),
+// -P_b(-s_pb), -S_b(-s_sb)], X = M^{-1} B for the two columns of B.
+static int interface_solve(cd xi, const cd s4[4], const Media &md, const cd B[4][2],
+                           cd X[4][2]) {
   const cd sp = s4[0], ss = s4[1], spb = s4[2], ssb = s4[3];
   cd M[4][6];
   cd c[4];
@@ -417,10 +422,10 @@ int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
   for (int r = 0; r < 4; ++r) M[r][2] = -c[r];
   scol(xi, -ssb, md.lam_b, md.mu_b, c);
   for (int r = 0; r < 4; ++r) M[r][3] = -c[r];
-  pcol(xi, -sp, md.lam_h, md.mu_h, c);
-  for (int r = 0; r < 4; ++r) M[r][4] = -c[r];
-  scol(xi, -ss, md.lam_h, md.mu_h, c);
-  for (int r = 0; r < 4; ++r) M[r][5] = -c[r];
+  for (int r = 0; r < 4; ++r) {
+    M[r][4] = B[r][0];
+    M[r][5] = B[r][1];
+  }
   // Gaussian elimination with partial pivoting on the 4x4 block, 2 RHS.
   for (int k = 0; k < 4; ++k) {
     int piv = k;
@@ -434,20 +439,65 @@ int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
       for (int cc = k; cc < 6; ++cc) M[r][cc] -= f * M[k][cc];
     }
   }
-  cd X[4][2];
   for (int col = 0; col < 2; ++col)
     for (int k = 3; k >= 0; --k) {
       cd s = M[k][4 + col];
       for (int cc = k + 1; cc < 4; ++cc) s -= M[k][cc] * X[cc][col];
       X[k][col] = s / M[k][k];
     }
-  R[0] = X[0][0];
-  R[1] = X[0][1];
-  R[2] = X[1][0];
-  R[3] = X[1][1];
-  for (int i = 0; i < 4; ++i)
-    if (!std::isfinite(R[i].real()) || !std::isfinite(R[i].imag())) return EMS_ERR_NUMERIC;
+  for (int k = 0; k < 4; ++k)
+    for (int col = 0; col < 2; ++col)
+      if (!std::isfinite(X[k][col].real()) || !std::isfinite(X[k][col].imag()))
+        return EMS_ERR_NUMERIC;
   return EMS_OK;
+}
+
+// Waves from the host: a unit upgoing P (column 0) or S (column 1) potential
+// e^{i xi x - s y}; R = host downgoing, T = substrate upgoing potentials.
+int reflect_transmit_s(cd xi, const cd s4[4], const Media &md, cd R[4], cd T[4]) {
+  cd B[4][2], c[4], X[4][2];
+  pcol(xi, -s4[0], md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) B[r][0] = -c[r];
+  scol(xi, -s4[1], md.lam_h, md.mu_h, c);
+  for (int r = 0; r < 4; ++r) B[r][1] = -c[r];
+  const int rc = interface_solve(xi, s4, md, B, X);
+  if (rc) return rc;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      R[2 * a + b] = X[a][b];
+      if (T) T[2 * a + b] = X[2 + a][b];
+    }
+  return EMS_OK;
+}
+
+int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
+  return reflect_transmit_s(xi, s4, md, R, nullptr);
+}
+
+// Waves from the substrate (Section 6.3's plane-wave setup): a unit
+// downgoing P (column 0) or S (column 1) potential e^{i xi x + s_b y}; the
+// continuity conditions move it to the right-hand side.  Td = host
+// downgoing (transmitted), Rb = substrate upgoing (reflected) potentials.
+int from_substrate_s(cd xi, const cd s4[4], const Media &md, cd Td[4], cd Rb[4]) {
+  cd B[4][2], c[4], X[4][2];
+  pcol(xi, s4[2], md.lam_b, md.mu_b, c);
+  for (int r = 0; r < 4; ++r) B[r][0] = c[r];
+  scol(xi, s4[3], md.lam_b, md.mu_b, c);
+  for (int r = 0; r < 4; ++r) B[r][1] = c[r];
+  const int rc = interface_solve(xi, s4, md, B, X);
+  if (rc) return rc;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      Td[2 * a + b] = X[a][b];
+      if (Rb) Rb[2 * a + b] = X[2 + a][b];
+    }
+  return EMS_OK;
+}
+
+int from_substrate(cd xi, const Media &md, cd Td[4], cd Rb[4]) {
+  cd s[4];
+  node_s(xi, 0.0, 0.0, md, s);
+  return from_substrate_s(xi, s, md, Td, Rb);
 }
 
 // ---------------------------------------------------------------------------

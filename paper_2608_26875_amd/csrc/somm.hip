@@ -621,10 +621,13 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   return hipGetLastError();
 }
 
-hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st) {
+hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st,
+                               bool transmit) {
   dim3 grid((h->q + 255) / 256, nrhs);
+  // transmit: the substrate's upgoing potentials (T in place of R)
   hipLaunchKernelGGL(somm_reflect_kernel, grid, dim3(256), 0, st, h->q, h->agg_chunks, h->d_agg,
-                     h->d_w, h->d_sp, h->d_ss, h->d_R, h->d_refl, adjoint ? 1 : 0);
+                     h->d_w, h->d_sp, h->d_ss, transmit ? h->d_Tu : h->d_R, h->d_refl,
+                     adjoint ? 1 : 0);
   return hipGetLastError();
 }
 

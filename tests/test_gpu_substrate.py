@@ -1,0 +1,119 @@
+"""GPU parity of the waves sent from the substrate (Section 6.3's plane-wave
+setup, (bplan)) and of the field in the substrate, against the oracle:
+
+* right-hand sides of P and SV waves from the substrate, including angles
+  past the critical one (an evanescent transmitted P wave), 1e-12;
+* background field of all four wave kinds at points of both layers, 1e-13;
+* scattered field at substrate points (the transmitted Sommerfeld field) and
+  at mixed host + substrate receivers in one call, 1e-11;
+* a GMRES solve driven by a wave from the substrate, backward residual under
+  the oracle's operator <= 1e-9;
+* the calls that are not built for these cases fail with a clear error.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import oracle_media, product_operator, rel, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2608_26875_amd as E  # noqa: E402
+from oracle import field, incident, operator, smatrix  # noqa: E402
+
+WAVES = [(2, math.radians(10.0)), (2, math.radians(-40.0)), (3, math.radians(25.0)),
+         (3, math.radians(-70.0))]
+
+
+@pytest.mark.parametrize("case", ["c0", "ragged"])
+def test_substrate_rhs_parity(case):
+    if case == "c0":
+        w = W.c0_circles()
+    else:
+        w = W.small_cloud(40, seed=13, p=6, omega=5.0, width=30.0, depth=(1.0, 9.0), ragged=True)
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    op = product_operator(w)
+    op.build()
+    b = to_np(op.incident(WAVES))
+    for r, (wv, ang) in enumerate(WAVES):
+        e = rel(b[r], incident.rhs(w, m, S, wv, ang))
+        print(case, "rhs", wv, ang, e, flush=True)
+        assert e < 1e-12
+    # past the critical angle the transmitted P wave is evanescent
+    assert m.ksb * math.sin(math.radians(70.0)) > m.kp
+
+
+def test_background_field_parity_both_layers():
+    w = W.c0_circles()
+    m = oracle_media(w)
+    op = product_operator(w)
+    op.build()
+    rng = np.random.default_rng(3)
+    pts = np.stack([rng.uniform(-5.0, 25.0, 60), rng.uniform(-12.0, 6.0, 60)], axis=1)
+    pts = pts[np.abs(pts[:, 1]) > 1e-3]
+    waves = WAVES + [(0, math.radians(30.0)), (1, math.radians(-50.0))]
+    u = to_np(op.background_field(waves, pts))
+    for r, (wv, ang) in enumerate(waves):
+        e = rel(u[r], incident.background_field(m, wv, ang, pts))
+        print("background", wv, ang, e, flush=True)
+        assert e < 1e-13
+
+
+def test_scattered_field_in_substrate_parity():
+    w = W.small_cloud(12, seed=6, p=6, omega=4.0, width=14.0, depth=(1.0, 4.0))
+    m = oracle_media(w)
+    op = product_operator(w)
+    op.build()
+    g = W.random_coeffs(w.n_coeff, 78, nrhs=2)
+    up = np.stack([np.linspace(0.0, 14.0, 15), np.linspace(0.2, 3.0, 15)], 1)
+    down = np.stack([np.linspace(0.5, 13.5, 8), np.full(8, -0.3)], 1)
+    far = np.min(np.hypot(down[:, None, 0] - w.xy[None, :, 0], down[:, None, 1] - w.xy[None, :, 1])
+                 - w.radius[None, :], axis=1)
+    down = down[far > 0.05]
+    pts = np.concatenate([up, down])
+    u = to_np(op.scattered_field(to_gpu(g), pts))
+    u_up = to_np(op.scattered_field(to_gpu(g), up))
+    for r in range(2):
+        ref = field.scattered(w, m, g[r], pts, tol=1e-13)
+        e = rel(u[r], ref)
+        eu = rel(u[r, :len(up)], ref[:len(up)])
+        print("field both layers", e, "substrate only", eu, flush=True)
+        assert e <= 1e-11 and eu <= 1e-11
+    assert rel(u_up, u[:, :len(up)]) < 1e-15
+
+
+def test_solve_with_wave_from_substrate():
+    w = W.c0_circles()
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    op = product_operator(w)
+    op.build()
+    wave, ang = 3, math.radians(35.0)
+    b_orc = incident.rhs(w, m, S, wave, ang)
+    x, info = op.solve(op.incident([(wave, ang)]), tol=1e-10, restart=200, maxit=400)
+    print("substrate-wave solve", info, flush=True)
+    assert info["converged"] == 1
+    r = b_orc - operator.apply(w, m, S, to_np(x)[0], tol=1e-13)
+    assert np.linalg.norm(r) / np.linalg.norm(b_orc) <= 1e-9
+
+
+def test_unbuilt_cases_fail_clearly():
+    w = W.small_cloud(3, seed=2, p=3)
+    op = product_operator(w)
+    op.build()
+    g = to_gpu(W.random_coeffs(w.n_coeff, 5, nrhs=1))
+    pts = np.array([[1.0, 0.5], [2.0, -0.2]])
+    res = torch.zeros((1, 2, 2), dtype=torch.complex128, device="cuda")
+    with pytest.raises(E.EmsError, match="host layer"):
+        op.scattered_field_adjoint(res, pts)
+    with pytest.raises(E.EmsError, match="interface"):
+        op.scattered_field(g, np.array([[1.0, 0.0]]))
+    with pytest.raises(E.EmsError, match="substrate"):
+        op.param_vjp([(2, 0.1)], g, g, pts[1:], res[:, 1:])
