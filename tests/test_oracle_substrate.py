@@ -21,35 +21,9 @@ import pytest
 
 import workloads as W
 from oracle import field, incident, interface, media
+from tests.helpers import at_interface as _at_interface
 
 M0 = media.Media(2.0, 1.0, 1.0, 4.0, 2.0, 1.5, 4.0)
-
-
-def _traction(ufun, x, y, lam, mu, h=2e-5):
-    """(u, t) at points (x, y) with 4th-order central differences of ufun."""
-    def d(dx, dy):
-        c = np.array([1.0, -8.0, 8.0, -1.0]) / (12.0 * h)
-        offs = (-2, -1, 1, 2)
-        return sum(ci * ufun(x + o * dx * h, y + o * dy * h) for ci, o in zip(c, offs))
-    u = ufun(x, y)
-    ux, uy = d(1, 0), d(0, 1)
-    t1 = mu * (uy[:, 0] + ux[:, 1])
-    t2 = (lam + 2 * mu) * uy[:, 1] + lam * ux[:, 0]
-    return u, np.stack([t1, t2], axis=1)
-
-
-def _at_interface(ufun, x, side, lam, mu):
-    """(u, t) at y = 0 from one side (side = -1 host, +1 substrate): cubic
-    extrapolation from four depths inside the layer."""
-    ds = np.array([1.0, 2.0, 3.0, 4.0]) * 1e-4
-    us, ts = [], []
-    for dlt in ds:
-        u, t = _traction(ufun, x, np.full_like(x, side * dlt), lam, mu)
-        us.append(u)
-        ts.append(t)
-    # Lagrange weights of the cubic through ds at 0
-    wts = [np.prod([-dj / (di - dj) for dj in ds if dj != di]) for di in ds]
-    return sum(wi * u for wi, u in zip(wts, us)), sum(wi * t for wi, t in zip(wts, ts))
 
 
 def test_identical_layers_transmit_everything():
