@@ -104,6 +104,14 @@ typedef struct {
   double angle;
 } ems_plane_wave;
 
+/* Elastic point source in the substrate (Section 2.3): position (x0, y0)
+ * with y0 > 0 (paper frame), polarisation (alpha1, alpha2); the incident
+ * field is Phi(x, x0) alpha with Phi the substrate's Green's tensor
+ * 1/(rho omega^2) (ks^2 g_ks I + grad grad^T (g_ks - g_kp)), g_k = (i/4) H_0(k r). */
+typedef struct {
+  double x0, y0, alpha1, alpha2;
+} ems_point_source;
+
 typedef struct {
   double tol;        /* relative residual target ||b - A x|| / ||b||          */
   int32_t restart;   /* Krylov dimension before a restart                      */
@@ -284,6 +292,24 @@ int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
  * [npts][2] doubles; u device [nrhs][npts][2] complex128. */
 int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t npts,
                        const double *pts, void *u, ems_stream_t stream);
+
+/* Right-hand side of the S-preconditioned system for nrhs point sources
+ * (Section 2.3; the point-source workload of Section 6): S_m times the local
+ * expansions, about every particle, of the source field transmitted into
+ * the host, formed by Jacobi-Anger (Section 4.3, (ja)) on a Sommerfeld node
+ * rule laid out for the source-to-particle pairs.  rhs device
+ * [nrhs][n_coeff].  Errors: EMS_ERR_GEOMETRY (y0 <= 0), EMS_ERR_ARG,
+ * EMS_ERR_STATE, EMS_ERR_NUMERIC, EMS_ERR_HIP.  Synchronous. */
+int ems_incident_point(ems_handle *h, const ems_point_source *src, int32_t nrhs, void *rhs,
+                       ems_stream_t stream);
+
+/* Background displacement of nrhs point sources (no particles) at npts
+ * points of either layer: host (y < 0), the transmitted field; substrate
+ * (y > 0), the Green's tensor field plus its interface reflection.  pts
+ * device [npts][2] (y != 0, not at a source), u device [nrhs][npts][2]
+ * complex128.  Synchronous. */
+int ems_eval_background_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
+                              int32_t npts, const double *pts, void *u, ems_stream_t stream);
 
 /* Background displacement of nrhs plane waves (no particles; Section 6.3,
  * (bplan)) at npts points of either layer: in the layer the wave is sent

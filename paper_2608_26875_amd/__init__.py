@@ -60,6 +60,11 @@ class Sommerfeld(ctypes.Structure):
                 ("tail_factor", ctypes.c_double), ("depth_cut", ctypes.c_double)]
 
 
+class PointSource(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double)]
+
+
 class PlaneWave(ctypes.Structure):
     _fields_ = [("wave", ctypes.c_int32), ("angle", ctypes.c_double)]
 
@@ -118,6 +123,8 @@ def _load():
                                P], I32),
         "ems_eval_scattered": ([P, P, I32, I32, P, P, P], I32),
         "ems_eval_background": ([P, ctypes.POINTER(PlaneWave), I32, I32, P, P, P], I32),
+        "ems_incident_point": ([P, ctypes.POINTER(PointSource), I32, P, P], I32),
+        "ems_eval_background_point": ([P, ctypes.POINTER(PointSource), I32, I32, P, P, P], I32),
         "ems_eval_scattered_adjoint": ([P, P, I32, I32, P, P, P], I32),
         "ems_autotune": ([P, I32, ctypes.POINTER(ctypes.c_int32), P], I32),
         "ems_apply_graph": ([P, P, P, I32, I32, I32, P], I32),
@@ -145,7 +152,8 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
             "ems_apply_graph",
-            "ems_eval_scattered", "ems_eval_background", "ems_sommerfeld_nodes",
+            "ems_eval_scattered", "ems_eval_background", "ems_incident_point",
+            "ems_eval_background_point", "ems_sommerfeld_nodes",
             "ems_sommerfeld_depth_cuts",
             "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm")
@@ -342,6 +350,29 @@ class Operator:
         out = torch.empty((len(waves), self.n_coeff), dtype=torch.complex128, device="cuda")
         self._check(_lib.ems_incident(self.h, arr, len(waves), ctypes.c_void_p(out.data_ptr()),
                                       _stream_ptr(stream)))
+        return out
+
+    def incident_point(self, sources, stream=None):
+        """Right-hand sides [nsrc, n_coeff] of point sources in the substrate:
+        sources = list of (x0, y0, alpha1, alpha2) with y0 > 0."""
+        import torch
+        arr = (PointSource * len(sources))(*[PointSource(*map(float, s)) for s in sources])
+        out = torch.empty((len(sources), self.n_coeff), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_incident_point(self.h, arr, len(sources),
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def background_field_point(self, sources, pts, stream=None):
+        """Background displacement [nsrc, npts, 2] of point sources at points of
+        either layer (y != 0)."""
+        import torch
+        arr = (PointSource * len(sources))(*[PointSource(*map(float, s)) for s in sources])
+        p = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64)).cuda()
+        out = torch.empty((len(sources), p.shape[0], 2), dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_eval_background_point(self.h, arr, len(sources), int(p.shape[0]),
+                                                   ctypes.c_void_p(p.data_ptr()),
+                                                   ctypes.c_void_p(out.data_ptr()),
+                                                   _stream_ptr(stream)))
         return out
 
     def background_field(self, waves, pts, stream=None):

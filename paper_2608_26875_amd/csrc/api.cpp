@@ -18,6 +18,11 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
                               hipStream_t st);
 hipError_t launch_background(int nrhs, int npts, const double *pts, const double2 *comp,
                              double2 *u, hipStream_t st);
+hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
+                              int nrhs, double2 *c, hipStream_t st);
+hipError_t launch_point_field(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
+                              const double *src, int nrhs, int npts, const double *pts,
+                              double2 *u, hipStream_t st);
 }  // namespace ems
 
 using ems::cd;
@@ -86,6 +91,71 @@ int plane_wave_parts(const ems::Media &md, const ems_plane_wave &w, PwParts &out
     out.comp.push_back({1, 1, true, Y[2 + c] * A, -s[3]});
     out.comp.push_back({0, 0, false, X[0 + c] * A, s[0]});
     out.comp.push_back({0, 1, false, X[2 + c] * A, s[1]});
+  }
+  return EMS_OK;
+}
+
+// Point sources in the substrate (Section 2.3): a node rule of their own and
+// the per-node potentials.  The rule is the handle's Sommerfeld rule laid out
+// for the source-to-target pairs: horizontal spread from the sources and the
+// targets (particles or receivers), depth sums y0 + |y| (two stand-in points
+// at half those sums, since the rule is designed for pairs of equal depth).
+// Per node and source, with c = 1/(4 pi rho_b omega^2) and the substrate's s:
+//   downgoing P potential  -c (i xi a1 + s_pb a2) e^{-s_pb y0} / s_pb e^{-i xi x0},
+//   downgoing S potential   c (s_sb a1 - i xi a2) e^{-s_sb y0} / s_sb e^{-i xi x0}
+// (the Green's tensor split into grad phi + grad^perp psi below the source);
+// the host sees w Td of them, the substrate w Rb of them going up.
+struct PointNodes {
+  ems::NodeTable nt;
+  std::vector<double2> nd;   // [q][5]: xi, s_p, s_s, s_pb, s_sb
+  std::vector<double2> amp;  // [nsrc][q][4]: host P, S, substrate P, S
+};
+
+int point_nodes(ems_handle *h, const ems_point_source *src, int nsrc, double xlo, double xhi,
+                double dlo, double dhi, PointNodes &out) {
+  double slo = HUGE_VAL, shi = -HUGE_VAL;
+  for (int r = 0; r < nsrc; ++r) {
+    const ems_point_source &s = src[r];
+    if (!std::isfinite(s.x0) || !std::isfinite(s.y0) || !std::isfinite(s.alpha1) ||
+        !std::isfinite(s.alpha2))
+      return fail(h, EMS_ERR_ARG, "non-finite point source");
+    if (!(s.y0 > 0)) return fail(h, EMS_ERR_GEOMETRY, "point source not in the substrate (y0 > 0)");
+    xlo = std::min(xlo, s.x0);
+    xhi = std::max(xhi, s.x0);
+    slo = std::min(slo, s.y0);
+    shi = std::max(shi, s.y0);
+  }
+  const std::vector<double> xy = {xlo, -0.5 * (slo + dlo), xhi, -0.5 * (shi + dhi)};
+  const std::vector<int> pp = {h->pmax, h->pmax};
+  int rc = ems::build_nodes(h->somm, h->md, xy, pp, out.nt, h->err);
+  if (rc) return rc;
+  const int q = (int)out.nt.xi.size();
+  out.nd.resize(5 * (size_t)q);
+  out.amp.resize(4 * (size_t)q * nsrc);
+  const ems::Media &md = h->md;
+  const cd I(0.0, 1.0);
+  const double c = 1.0 / (4.0 * 3.14159265358979323846 * md.rho_b * md.omega * md.omega);
+  for (int j = 0; j < q; ++j) {
+    const cd xi = out.nt.xi[j], w = out.nt.w[j];
+    cd s4[4], Td[4], Rb[4];
+    ems::node_s(xi, out.nt.bp[j], out.nt.d[j], md, s4);
+    if (ems::from_substrate_s(xi, s4, md, Td, Rb))
+      return fail(h, EMS_ERR_NUMERIC, "singular interface system at a point-source node");
+    const cd v[5] = {xi, s4[0], s4[1], s4[2], s4[3]};
+    for (int k = 0; k < 5; ++k) out.nd[5 * (size_t)j + k] = make_double2(v[k].real(), v[k].imag());
+    for (int r = 0; r < nsrc; ++r) {
+      const ems_point_source &s = src[r];
+      const cd ph = std::exp(-I * xi * s.x0);
+      const cd P = -c * (I * xi * s.alpha1 + s4[2] * s.alpha2) * std::exp(-s4[2] * s.y0) / s4[2] * ph;
+      const cd S = c * (s4[3] * s.alpha1 - I * xi * s.alpha2) * std::exp(-s4[3] * s.y0) / s4[3] * ph;
+      const cd a[4] = {w * (Td[0] * P + Td[1] * S), w * (Td[2] * P + Td[3] * S),
+                       w * (Rb[0] * P + Rb[1] * S), w * (Rb[2] * P + Rb[3] * S)};
+      for (int k = 0; k < 4; ++k) {
+        if (!std::isfinite(a[k].real()) || !std::isfinite(a[k].imag()))
+          return fail(h, EMS_ERR_NUMERIC, "non-finite point-source amplitude at a node");
+        out.amp[((size_t)r * q + j) * 4 + k] = make_double2(a[k].real(), a[k].imag());
+      }
+    }
   }
   return EMS_OK;
 }
@@ -991,6 +1061,89 @@ int ems_eval_background(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs
   HIPCHK(h, hipMemcpyAsync(h->d_tmp, comp.data(), comp.size() * sizeof(double2),
                            hipMemcpyHostToDevice, st));
   HIPCHK(h, ems::launch_background(nrhs, npts, pts, h->d_tmp, (double2 *)u, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  return EMS_OK;
+}
+
+int ems_incident_point(ems_handle *h, const ems_point_source *src, int32_t nrhs, void *rhs,
+                       ems_stream_t stream) {
+  if (!h || !src || !rhs || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad point-source arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  double xlo = HUGE_VAL, xhi = -HUGE_VAL, dlo = HUGE_VAL, dhi = -HUGE_VAL;
+  for (int m = 0; m < h->n; ++m) {
+    xlo = std::min(xlo, h->xy[2 * m]);
+    xhi = std::max(xhi, h->xy[2 * m]);
+    dlo = std::min(dlo, -h->xy[2 * m + 1]);
+    dhi = std::max(dhi, -h->xy[2 * m + 1]);
+  }
+  PointNodes pn;
+  int rc = point_nodes(h, src, nrhs, xlo, xhi, dlo, dhi, pn);
+  if (rc) return rc;
+  const int q = (int)pn.nt.xi.size();
+  const size_t nvec = (size_t)nrhs * h->ncoef;
+  const size_t nd3 = 3 * (size_t)q, na = 2 * (size_t)q * nrhs;
+  if ((rc = ensure_tmp(h, sizeof(double2) * (nvec + nd3 + na)))) return rc;
+  std::vector<double2> nd(nd3), amp(na);
+  for (int jj = 0; jj < q; ++jj)
+    for (int k = 0; k < 3; ++k) nd[3 * (size_t)jj + k] = pn.nd[5 * (size_t)jj + k];
+  for (int r = 0; r < nrhs; ++r)
+    for (int jj = 0; jj < q; ++jj)
+      for (int k = 0; k < 2; ++k)
+        amp[((size_t)r * q + jj) * 2 + k] = pn.amp[((size_t)r * q + jj) * 4 + k];
+  double2 *c = h->d_tmp, *dnd = c + nvec, *damp = dnd + nd3;
+  HIPCHK(h, hipMemcpyAsync(dnd, nd.data(), nd3 * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(damp, amp.data(), na * sizeof(double2), hipMemcpyHostToDevice, st));
+  {
+    ems::ProfScope ps(h, "point_local", st);
+    HIPCHK(h, ems::launch_point_local(h, q, dnd, damp, nrhs, c, st));
+  }
+  HIPCHK(h, ems::launch_s_apply(h, c, (double2 *)rhs, nrhs, false, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  return EMS_OK;
+}
+
+int ems_eval_background_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
+                              int32_t npts, const double *pts, void *u, ems_stream_t stream) {
+  if (!h || !src || !pts || !u || nrhs <= 0 || npts <= 0)
+    return fail(h, EMS_ERR_ARG, "bad point-source field arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> hp(2 * (size_t)npts);
+  HIPCHK(h, hipMemcpyAsync(hp.data(), pts, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  double xlo = HUGE_VAL, xhi = -HUGE_VAL, dlo = HUGE_VAL, dhi = -HUGE_VAL;
+  for (int i = 0; i < npts; ++i) {
+    const double x = hp[2 * i], y = hp[2 * i + 1];
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(h, EMS_ERR_NUMERIC, "non-finite point");
+    if (y == 0.0) return fail(h, EMS_ERR_GEOMETRY, "point on the interface (y = 0)");
+    for (int r = 0; r < nrhs; ++r)
+      if (std::hypot(x - src[r].x0, y - src[r].y0) < 1e-9)
+        return fail(h, EMS_ERR_GEOMETRY, "point at a source");
+    xlo = std::min(xlo, x);
+    xhi = std::max(xhi, x);
+    dlo = std::min(dlo, std::fabs(y));
+    dhi = std::max(dhi, std::fabs(y));
+  }
+  PointNodes pn;
+  int rc = point_nodes(h, src, nrhs, xlo, xhi, dlo, dhi, pn);
+  if (rc) return rc;
+  const int q = (int)pn.nt.xi.size();
+  const size_t nd5 = pn.nd.size(), na = pn.amp.size(), ns = 2 * (size_t)nrhs;
+  if ((rc = ensure_tmp(h, sizeof(double2) * (nd5 + na + ns)))) return rc;
+  std::vector<double> sv(4 * (size_t)nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    sv[4 * r] = src[r].x0;
+    sv[4 * r + 1] = src[r].y0;
+    sv[4 * r + 2] = src[r].alpha1;
+    sv[4 * r + 3] = src[r].alpha2;
+  }
+  double2 *dnd = h->d_tmp, *damp = dnd + nd5;
+  double *dsrc = reinterpret_cast<double *>(damp + na);
+  HIPCHK(h, hipMemcpyAsync(dnd, pn.nd.data(), nd5 * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(damp, pn.amp.data(), na * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dsrc, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(h, ems::launch_point_field(h, q, dnd, damp, dsrc, nrhs, npts, pts, (double2 *)u, st));
   HIPCHK(h, hipStreamSynchronize(st));
   return EMS_OK;
 }

@@ -146,6 +146,150 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
   return hipGetLastError();
 }
 
+// Point source in the substrate (Section 2.3): local expansions of its field
+// transmitted into the host, over a node list of its own.  nd [q][3] = (xi,
+// s_p, s_s); amp [nrhs][q][2] = w_j (Td A_inc)_{P,S}, the host's downgoing
+// potentials per node (weights, e^{-i xi x0} and the source's depth factor
+// included).  Local coefficient of particle m, wave w, order n:
+//   sum_j amp_w(j) e^{i xi_j x_m + s_w y_m} (i (xi_j - s_w)/k_w)^n  (Jacobi-Anger).
+// Block = particle, lane = (wave, order); the exponentials of a tile of
+// nodes are formed once per block in LDS.
+constexpr int kPtTile = 256;
+__global__ void point_local_kernel(int n, int q, const double *__restrict__ xy,
+                                   const int *__restrict__ p, const int64_t *__restrict__ off,
+                                   const double2 *__restrict__ nd, const double2 *__restrict__ amp,
+                                   double kp, double ks, double2 *__restrict__ c, int64_t ncoef) {
+  __shared__ double2 se[2][kPtTile], sz[2][kPtTile];
+  const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int pm = p[m];
+  const int N = 2 * pm + 1;
+  const bool active = lane < 2 * N;
+  const int wave = lane < N ? 0 : 1;
+  const int nn = (wave ? lane - N : lane) - pm;
+  const double x = xy[2 * m], y = xy[2 * m + 1];
+  const double2 *A = amp + (int64_t)r * q * 2;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int j0 = 0; j0 < q; j0 += kPtTile) {
+    for (int t = threadIdx.x; t < kPtTile; t += blockDim.x) {
+      const int j = j0 + t;
+      if (j < q) {
+        const double2 xi = nd[3 * (int64_t)j];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const double2 s = nd[3 * (int64_t)j + 1 + w];
+          const double k = w ? ks : kp;
+          // e^{i xi x + s y}
+          se[w][t] = cmul(A[2 * (int64_t)j + w],
+                          cexp(make_double2(-xi.y * x + s.x * y, xi.x * x + s.y * y)));
+          // i (xi - s) / k
+          const double2 d = csub(xi, s);
+          sz[w][t] = make_double2(-d.y / k, d.x / k);
+        }
+      } else {
+        se[0][t] = se[1][t] = make_double2(0.0, 0.0);
+        sz[0][t] = sz[1][t] = make_double2(1.0, 0.0);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const int tn = min(kPtTile, q - j0);
+      for (int t = 0; t < tn; ++t) cfma(acc, se[wave][t], cpow_int(sz[wave][t], nn));
+    }
+    __syncthreads();
+  }
+  if (active) c[(int64_t)r * ncoef + off[m] + lane] = acc;
+}
+
+hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
+                              int nrhs, double2 *c, hipStream_t st) {
+  hipLaunchKernelGGL(point_local_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->n, q,
+                     h->d_xy, h->d_p, h->d_off, nd, amp, h->md.kp, h->md.ks, c, h->ncoef);
+  return hipGetLastError();
+}
+
+// Background displacement of point sources at receivers of either layer.
+// Host (y < 0): the transmitted potentials amp_h = w (Td A_inc) on e^{i xi x
+// + s y}; substrate (y > 0): the Green's tensor (closed form, Hankel
+// functions of the substrate's wavenumbers) plus the reflected potentials
+// amp_b = w (Rb A_inc) on e^{i xi x - s_b y}.  nd [q][5] = (xi, s_p, s_s,
+// s_pb, s_sb); amp [nrhs][q][4] = (amp_h P, S, amp_b P, S); src [nrhs][4] =
+// (x0, y0, alpha1, alpha2).
+__global__ void point_field_kernel(int npts, int q, const double *__restrict__ pts,
+                                   const double2 *__restrict__ nd, const double2 *__restrict__ amp,
+                                   const double *__restrict__ src, double kpb, double ksb,
+                                   double inv_rw2, double2 *__restrict__ u) {
+  const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (ip >= npts) return;
+  const double x = pts[2 * ip], y = pts[2 * ip + 1];
+  const bool host = y < 0.0;
+  const double2 *A = amp + (int64_t)r * q * 4 + (host ? 0 : 2);
+  double2 ux = make_double2(0.0, 0.0), uy = make_double2(0.0, 0.0);
+  for (int j = 0; j < q; ++j) {
+    const double2 xi = nd[5 * (int64_t)j];
+    const double2 ixi = make_double2(-xi.y, xi.x);
+    // P: q = +s_p (host) or -s_pb (substrate); S likewise
+    double2 qp = nd[5 * (int64_t)j + (host ? 1 : 3)];
+    double2 qs = nd[5 * (int64_t)j + (host ? 2 : 4)];
+    if (!host) {
+      qp = cscale(qp, -1.0);
+      qs = cscale(qs, -1.0);
+    }
+    const double2 ep = cmul(A[4 * (int64_t)j], cexp(make_double2(-xi.y * x + qp.x * y, xi.x * x + qp.y * y)));
+    const double2 es = cmul(A[4 * (int64_t)j + 1], cexp(make_double2(-xi.y * x + qs.x * y, xi.x * x + qs.y * y)));
+    // grad (i xi, q) and grad^perp (-q, i xi)
+    ux = cadd(ux, csub(cmul(ixi, ep), cmul(qs, es)));
+    uy = cadd(uy, cadd(cmul(qp, ep), cmul(ixi, es)));
+  }
+  if (!host) {
+    // Green's tensor 1/(rho w^2) (ks^2 g_s I + grad grad^T (g_s - g_p)) alpha,
+    // g = (i/4) H0(k r); d_i d_j g = (i/4) k^2 [d2 e_i e_j + (d1 / z)(delta_ij - e_i e_j)],
+    // d1 = -H1(z), d2 = -H0(z) + H1(z)/z
+    const double *S = src + 4 * r;
+    const double dx = x - S[0], dy = y - S[1];
+    const double rr = sqrt(dx * dx + dy * dy);
+    const double ex = dx / rr, ey = dy / rr;
+    const double a1 = S[2], a2 = S[3];
+    const double ea = ex * a1 + ey * a2;
+    double2 gx = make_double2(0.0, 0.0), gy = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const double k = w ? kpb : ksb;
+      const double sg = w ? -1.0 : 1.0;
+      const double z = k * rr;
+      const double2 h0 = make_double2(j0(z), y0(z)), h1 = make_double2(j1(z), y1(z));
+      const double2 d1 = cscale(h1, -1.0);
+      const double2 d2 = cadd(cscale(h0, -1.0), cscale(h1, 1.0 / z));
+      // (i/4) k^2 [d2 (e.a) e + (d1/z)(a - (e.a) e)]
+      const double2 f = cscale(make_double2(0.0, 0.25), sg * k * k);
+      const double2 cx = cadd(cscale(d2, ea * ex), cscale(d1, (a1 - ea * ex) / z));
+      const double2 cy = cadd(cscale(d2, ea * ey), cscale(d1, (a2 - ea * ey) / z));
+      gx = cadd(gx, cmul(f, cx));
+      gy = cadd(gy, cmul(f, cy));
+      if (w == 0) {
+        // ks^2 g_s alpha
+        const double2 g = cmul(make_double2(0.0, 0.25 * k * k), h0);
+        gx = cadd(gx, cscale(g, a1));
+        gy = cadd(gy, cscale(g, a2));
+      }
+    }
+    ux = cadd(ux, cscale(gx, inv_rw2));
+    uy = cadd(uy, cscale(gy, inv_rw2));
+  }
+  double2 *o = u + ((int64_t)r * npts + ip) * 2;
+  o[0] = ux;
+  o[1] = uy;
+}
+
+hipError_t launch_point_field(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
+                              const double *src, int nrhs, int npts, const double *pts,
+                              double2 *u, hipStream_t st) {
+  const double inv_rw2 = 1.0 / (h->md.rho_b * h->md.omega * h->md.omega);
+  hipLaunchKernelGGL(point_field_kernel, dim3((npts + 255) / 256, nrhs), dim3(256), 0, st, npts,
+                     q, pts, nd, amp, src, h->md.kpb, h->md.ksb, inv_rw2, u);
+  return hipGetLastError();
+}
+
 // Background displacement of plane waves at receivers of either layer.
 // comp [nrhs][6][3]: per component {A, q, (xi0, code)}, the potential
 // A e^{i xi0 x + q y}; code = 2 layer + kind (layer 0 host y < 0, 1

@@ -1,0 +1,87 @@
+"""GPU parity of the point-source incidence (Section 2.3; the point-source
+workload of Section 6) against the oracle, which solves the paper's density
+system A_xi sigma = b_xi by adaptive quadrature:
+
+* right-hand sides S (local expansions of the transmitted source field) for
+  two sources, one with the paper's polarisation (cos pi/4, sin pi/4);
+* background field of the sources at points of both layers (transmitted in
+  the host; Green's tensor plus reflection in the substrate);
+* a GMRES solve driven by a point source, backward residual under the
+  oracle's operator <= 1e-9;
+* sources outside the substrate are rejected.
+Tolerances: the library integrates on its own node rule and the oracle
+adaptively to 1e-13, as for the reflected part of the operator.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import oracle_media, product_operator, rel, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2608_26875_amd as E  # noqa: E402
+from oracle import operator, point_source, smatrix  # noqa: E402
+
+C = math.cos(math.pi / 4)
+SOURCES = [(5.0, 3.0, C, C), (12.0, 1.5, 0.0, 1.0)]
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def c0():
+    w = W.c0_circles()
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    op = product_operator(w)
+    op.build()
+    return w, m, S, op
+
+
+def test_point_source_rhs_parity(c0):
+    w, m, S, op = c0
+    b = to_np(op.incident_point(SOURCES))
+    for r, (x0, y0, a1, a2) in enumerate(SOURCES):
+        ref = point_source.rhs(w, m, S, (x0, y0), (a1, a2))
+        e = rel(b[r], ref)
+        print("point rhs", r, e, flush=True)
+        assert e <= TOL
+
+
+def test_point_source_background_parity(c0):
+    w, m, S, op = c0
+    rng = np.random.default_rng(9)
+    host = np.stack([rng.uniform(-2.0, 22.0, 12), rng.uniform(-9.0, -0.2, 12)], 1)
+    sub = np.stack([rng.uniform(-2.0, 22.0, 10), rng.uniform(0.2, 1.2, 10)], 1)
+    pts = np.concatenate([host, sub])
+    u = to_np(op.background_field_point(SOURCES, pts))
+    for r, (x0, y0, a1, a2) in enumerate(SOURCES):
+        ref_h = point_source.transmitted_field(m, (x0, y0), (a1, a2), host)
+        ref_b = point_source.upper_field(m, (x0, y0), (a1, a2), sub)
+        eh = rel(u[r, :len(host)], ref_h)
+        eb = rel(u[r, len(host):], ref_b)
+        print("point background", r, eh, eb, flush=True)
+        assert eh <= TOL and eb <= TOL
+
+
+def test_solve_with_point_source(c0):
+    w, m, S, op = c0
+    x0, y0, a1, a2 = SOURCES[0]
+    b_orc = point_source.rhs(w, m, S, (x0, y0), (a1, a2))
+    x, info = op.solve(op.incident_point(SOURCES[:1]), tol=1e-10, restart=200, maxit=400)
+    print("point-source solve", info, flush=True)
+    assert info["converged"] == 1
+    r = b_orc - operator.apply(w, m, S, to_np(x)[0], tol=1e-13)
+    assert np.linalg.norm(r) / np.linalg.norm(b_orc) <= 1e-9
+
+
+def test_point_source_outside_substrate_rejected(c0):
+    w, m, S, op = c0
+    with pytest.raises(E.EmsError, match="substrate"):
+        op.incident_point([(1.0, -0.5, 1.0, 0.0)])
