@@ -347,6 +347,22 @@ def main():
         "setup_s": setup_s,
         "tiles": tiles,
     }
+    # right-hand-side builders (once each after one untimed call): the plane
+    # wave from the particle side, one sent from the substrate, and a point
+    # source in the substrate over the middle of the cloud with the
+    # polarisation (cos pi/4, sin pi/4); wall clock, each call synchronizes
+    src = [(float(np.mean(w.xy[:, 0])), 3.0, math.cos(math.pi / 4), math.sin(math.pi / 4))]
+    rhs_ms = {}
+    for name, fn in (("plane_wave_particle_side", lambda: op.incident([w.incidence[0]])),
+                     ("plane_wave_from_substrate", lambda: op.incident([(3, 0.3)])),
+                     ("point_source", lambda: op.incident_point(src))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        rhs_ms[name] = (time.perf_counter() - t0) * 1e3
+    out["rhs_ms"] = rhs_ms
     solve_its = 60 if args.solve_its is None else args.solve_its
     if args.solve or solve_its:
         # GMRES to 1e-9 within an iteration budget (restart = min(budget, 300)):
