@@ -297,11 +297,12 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   const int m0 = c * per_chunk, m1 = min(min(n, m0 + per_chunk), kc);
   C en[NT];
   double2 xn[NC];
-  auto fetch = [&](int m) {
+  // the particle index of a table row is loaded one step ahead of the
+  // coefficient reads that need it (a dependent load off the critical path)
+  auto fetch = [&](int m, int mo) {
     const int mc = min(m + kq, m1 - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
-    const int mo = sperm[mc];
     // uniform orders: the coefficient address needs no offset lookup
     const int pm = UNI ? PM : p[mo];
     const int64_t base = (UNI ? (int64_t)mo * 2 * nm : off[mo]) + wave * (2 * pm + 1) + pm;
@@ -316,7 +317,11 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       }
     }
   };
-  if (m0 < m1) fetch(m0);
+  int mo_next = 0;
+  if (m0 < m1) {
+    fetch(m0, sperm[min(m0 + kq, m1 - 1)]);
+    mo_next = sperm[min(m0 + 4 + kq, m1 - 1)];
+  }
   for (int m = m0; m < m1; m += 4) {
     const bool ok = m + kq < m1;
     T er[NT], ei[NT], br[NC], bi[NC];
@@ -330,7 +335,8 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       br[u] = ok ? (T)xn[u].x : T(0);
       bi[u] = ok ? (T)xn[u].y : T(0);
     }
-    fetch(m + 4);
+    fetch(m + 4, mo_next);
+    mo_next = sperm[min(m + 8 + kq, m1 - 1)];
     mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
   }
   // I_j = sum_k V[j][k] A[j][k]; the 16 lanes of a group hold the 16 columns
