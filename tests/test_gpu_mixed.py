@@ -84,3 +84,22 @@ def test_adjoint_solve_against_dense_oracle(precision):
     for r in range(2):
         res = b[r] - A.conj().T @ L[r]
         assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= 1e-9
+
+
+def test_mixed_fmm_close_to_fp64():
+    """2000 particles (FMM on): the mixed form runs the near-field Graf sums
+    in FP32 and keeps the FMM translations in FP64 (their Hankel symbols reach
+    1e39 at the finest M2L level, beyond FP32's range); its free part, forward
+    and adjoint, stays within the mixed tolerance of FP64."""
+    w = W.c1_cloud()
+    op = product_operator(w)
+    info = op.build()
+    assert info["fmm_levels"] > 0
+    x = to_gpu(W.random_coeffs(w.n_coeff, 33, nrhs=2))
+    for adjoint in (False, True):
+        for flags in (E.EMS_PART_FREE, Z):
+            z64 = to_np(op.apply(x, flags=flags, adjoint=adjoint))
+            z32 = to_np(op.apply(x, flags=flags | E.EMS_MIXED, adjoint=adjoint))
+            e = rel(z32, z64)
+            print("mixed fmm", adjoint, flags, e, flush=True)
+            assert 1e-10 < e <= TOL_MIXED, (adjoint, flags, e)
