@@ -248,14 +248,21 @@ __device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NC],
                                            typename Mfma<T>::Acc (&ai)[NT][NC],
                                            const T (&er)[NT], const T (&ei)[NT], const T (&br)[NC],
                                            const T (&bi)[NC]) {
+  // first the products of every accumulator, then the second ones: a
+  // dependent pair of MFMAs sits 2 NT NC issues apart
+#pragma unroll
+  for (int u = 0; u < NC; ++u)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      ar[t][u] = Mfma<T>::op(er[t], br[u], ar[t][u]);
+      ai[t][u] = Mfma<T>::op(er[t], bi[u], ai[t][u]);
+    }
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
     const T nb = -bi[u];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      ar[t][u] = Mfma<T>::op(er[t], br[u], ar[t][u]);
       ar[t][u] = Mfma<T>::op(ei[t], nb, ar[t][u]);
-      ai[t][u] = Mfma<T>::op(er[t], bi[u], ai[t][u]);
       ai[t][u] = Mfma<T>::op(ei[t], br[u], ai[t][u]);
     }
   }
