@@ -107,6 +107,25 @@ def test_single_particle_and_p1():
             assert rel(g[k], o[k]) <= TOL_APPLY
 
 
+def test_max_order_p16():
+    """The largest truncation order the kernels compile for (p = 16: 33
+    modes, three 16-mode matrix-core column tiles, 64-lane Graf rows),
+    uniform and ragged, against the oracle."""
+    for ragged in (False, True):
+        w = W.small_cloud(8, seed=5, p=16, omega=4.0, width=14.0, depth=(1.0, 4.0), ragged=ragged)
+        m = oracle_media(w)
+        S = smatrix.workload_blocks(w, m)
+        op = product_operator(w)
+        op.build()
+        x = W.random_coeffs(w.n_coeff, 11)[0]
+        g = _parts(op, x)
+        o = _oracle_parts(w, m, S, x)
+        for k in ("free", "s_refl", "z", "y"):
+            e = rel(g[k], o[k])
+            print("p16", ragged, k, e, flush=True)
+            assert e <= TOL_APPLY, (ragged, k, e)
+
+
 def test_batched_rhs_matches_single():
     w = W.small_cloud(30, seed=4, p=5, omega=4.0, width=30.0, depth=(1.0, 6.0))
     op = product_operator(w)
