@@ -302,11 +302,12 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) kc = max(kc, __shfl_xor(kc, o));
   const int m0 = c * per_chunk, m1 = min(min(n, m0 + per_chunk), kc);
-  C en[NT];
-  double2 xn[NC];
-  // the particle index of a table row is loaded one step ahead of the
-  // coefficient reads that need it (a dependent load off the critical path)
-  auto fetch = [&](int m, int mo) {
+  // Two operand slots, each refilled right after it is consumed: the loads
+  // of a step are issued two steps ahead of its products.  The particle index
+  // of a table row is loaded one refill earlier still (a dependent load).
+  C enA[NT], enB[NT];
+  double2 xnA[NC], xnB[NC];
+  auto fetch = [&](C (&en)[NT], double2 (&xn)[NC], int m, int mo) {
     const int mc = min(m + kq, m1 - 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
@@ -324,14 +325,9 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       }
     }
   };
-  int mo_next = 0;
-  if (m0 < m1) {
-    fetch(m0, sperm[min(m0 + kq, m1 - 1)]);
-    mo_next = sperm[min(m0 + 4 + kq, m1 - 1)];
-  }
-  for (int m = m0; m < m1; m += 4) {
+  auto take = [&](const C (&en)[NT], const double2 (&xn)[NC], int m, T (&er)[NT], T (&ei)[NT],
+                  T (&br)[NC], T (&bi)[NC]) {
     const bool ok = m + kq < m1;
-    T er[NT], ei[NT], br[NC], bi[NC];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       er[t] = en[t].x;
@@ -342,9 +338,31 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       br[u] = ok ? (T)xn[u].x : T(0);
       bi[u] = ok ? (T)xn[u].y : T(0);
     }
-    fetch(m + 4, mo_next);
-    mo_next = sperm[min(m + 8 + kq, m1 - 1)];
-    mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
+  };
+  auto row = [&](int m) { return sperm[min(m + kq, m1 - 1)]; };
+  int moA = 0, moB = 0;
+  if (m0 < m1) {
+    fetch(enA, xnA, m0, row(m0));
+    fetch(enB, xnB, m0 + 4, row(m0 + 4));
+    moA = row(m0 + 8);
+    moB = row(m0 + 12);
+  }
+  for (int m = m0; m < m1; m += 8) {
+    {
+      T er[NT], ei[NT], br[NC], bi[NC];
+      take(enA, xnA, m, er, ei, br, bi);
+      fetch(enA, xnA, m + 8, moA);
+      moA = row(m + 16);
+      mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
+    }
+    if (m + 4 >= m1) break;  // uniform over the wave
+    {
+      T er[NT], ei[NT], br[NC], bi[NC];
+      take(enB, xnB, m + 4, er, ei, br, bi);
+      fetch(enB, xnB, m + 12, moB);
+      moB = row(m + 20);
+      mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
+    }
   }
   // I_j = sum_k V[j][k] A[j][k]; the 16 lanes of a group hold the 16 columns
   const double2 *Vt = wave ? Vs_t : Vp_t;
