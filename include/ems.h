@@ -177,6 +177,30 @@ int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets);
  * Writes (4p+2)^2 complex128 row-major into host memory S_out. */
 int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double *S_out);
 
+/* Scattering matrices of non-circular particles (Section 3.3), generated on
+ * the GPU for the handle's particles (after ems_set_media and
+ * ems_set_particles; orders p from the particles).  Host arrays, one entry
+ * per particle: kind 0 circle of radius a, 1 ellipse with semi-axes a and
+ * a/2, 2 five-arm star r(t) = a (1 + 0.3 cos 5t), each about the particle
+ * centre and turned by theta0 (radians, counter-clockwise in the paper
+ * frame); bc 0 rigid (u = 0), 1 traction-free.  The shape must lie inside
+ * the enclosing radius R (a, a, 1.3 a), else EMS_ERR_GEOMETRY.
+ * Discretisation (the paper uses a boundary integral equation; here the
+ * method of fundamental solutions): npts compressional and npts shear
+ * monopoles H_0 at z(t_j + i delta), t_j = 2 pi j / npts, the boundary
+ * condition collocated at z(t_j), Graf's addition theorem projects the
+ * monopoles onto the outgoing coefficients.  npts a multiple of 8 in
+ * [16, 256] (0 = 256); delta <= 0 selects 0.3 / 0.2 / 0.12 by shape.
+ * S_out (device): the matrices in the packing ems_set_smatrices reads
+ * (row-major (4p_m+2)^2 per particle, particle m at complex offset
+ * sum_{l<m} (4p_l+2)^2).  Finishes before returning; allocates and frees
+ * its device workspace (about 16 (2 npts)(2 npts + 8 pmax + 4) bytes per
+ * particle, in batches of at most 6 GiB).  EMS_ERR_NUMERIC when a pivot of
+ * a collocation system is exactly zero. */
+int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, const double *theta0,
+                       const int32_t *bc, int32_t npts, double delta, void *S_out,
+                       ems_stream_t stream);
+
 /* Sommerfeld quadrature choice (Section 4.1); default kind 1 when never set. */
 int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s);
 

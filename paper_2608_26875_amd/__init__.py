@@ -112,6 +112,7 @@ def _load():
         "ems_set_particles": ([P, I32, P, P, P], I32),
         "ems_set_smatrices": ([P, P, P], I32),
         "ems_smatrix_disk": ([ctypes.POINTER(Media), D, I32, I32, P], I32),
+        "ems_smatrix_shapes": ([P, P, P, P, P, I32, D, P, P], I32),
         "ems_set_sommerfeld": ([P, ctypes.POINTER(Sommerfeld)], I32),
         "ems_build": ([P, P], I32),
         "ems_get_info": ([P, ctypes.POINTER(BuildInfo)], I32),
@@ -148,7 +149,8 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
-            "ems_set_smatrices", "ems_smatrix_disk", "ems_set_sommerfeld", "ems_build",
+            "ems_set_smatrices", "ems_smatrix_disk", "ems_smatrix_shapes", "ems_set_sommerfeld",
+            "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
             "ems_apply_graph",
@@ -287,6 +289,36 @@ class Operator:
             if key not in cache:
                 cache[key] = smatrix_disk(self.media, *key)
             out.append(cache[key])
+        return out
+
+    def shape_smatrices(self, kind, a, theta0, bc, npts=0, delta=0.0, stream=None):
+        """Scattering matrices of the particles' shapes, generated on the GPU
+        (Section 3.3; method of fundamental solutions, ems_smatrix_shapes):
+        kind 0 circle, 1 ellipse (semi-axes a, a/2), 2 five-arm star, turned by
+        theta0.  Returns a complex128 device tensor in the packing
+        set_smatrices reads (row-major (4p+2)^2 per particle)."""
+        import torch
+        n = self.n
+        kind = np.ascontiguousarray(np.broadcast_to(kind, n), dtype=np.int32)
+        a = np.ascontiguousarray(np.broadcast_to(a, n), dtype=np.float64)
+        theta0 = np.ascontiguousarray(np.broadcast_to(theta0, n), dtype=np.float64)
+        bc = np.ascontiguousarray(np.broadcast_to(bc, n), dtype=np.int32)
+        total = int(np.sum((4 * self.p.astype(np.int64) + 2) ** 2))
+        out = torch.empty(total, dtype=torch.complex128, device="cuda")
+        self._check(_lib.ems_smatrix_shapes(self.h, kind.ctypes.data, a.ctypes.data,
+                                            theta0.ctypes.data, bc.ctypes.data, int(npts),
+                                            float(delta), ctypes.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream)))
+        return out
+
+    def unpack_smatrices(self, flat):
+        """Per-particle (4p+2) x (4p+2) blocks (numpy) of a packed S store."""
+        flat = flat.cpu().numpy() if hasattr(flat, "cpu") else np.asarray(flat)
+        out, o = [], 0
+        for pm in self.p:
+            K = 4 * int(pm) + 2
+            out.append(flat[o: o + K * K].reshape(K, K))
+            o += K * K
         return out
 
     def set_smatrices(self, blocks):

@@ -581,6 +581,96 @@ int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double
   return EMS_OK;
 }
 
+namespace {
+// Device buffers of one ems_smatrix_shapes call, freed on every return path.
+struct ShapeBufs {
+  std::vector<void *> ptrs;
+  ~ShapeBufs() {
+    for (void *q : ptrs) (void)hipFree(q);
+  }
+  hipError_t get(void **out, size_t bytes) {
+    *out = nullptr;
+    const hipError_t e = hipMalloc(out, bytes);
+    if (e == hipSuccess) ptrs.push_back(*out);
+    return e;
+  }
+};
+}  // namespace
+
+int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, const double *theta0,
+                       const int32_t *bc, int32_t npts, double delta, void *S_out,
+                       ems_stream_t stream) {
+  if (!h || !kind || !a || !theta0 || !bc || !S_out)
+    return fail(h, EMS_ERR_ARG, "bad shape arguments");
+  if (!h->have_media || !h->have_particles)
+    return fail(h, EMS_ERR_STATE, "set media and particles before generating S-matrices");
+  const int N = npts == 0 ? 256 : npts;
+  if (N < 16 || N > 256 || N % 8 != 0)
+    return fail(h, EMS_ERR_ARG, "npts must be a multiple of 8 in [16, 256]");
+  if (!std::isfinite(delta)) return fail(h, EMS_ERR_ARG, "non-finite delta");
+  const int n = h->n;
+  static const double kDelta[3] = {0.3, 0.2, 0.12};
+  static const double kExtent[3] = {1.0, 1.0, 1.3};   // max |z(t)| / a
+  std::vector<int> hk(n), hbc(n);
+  std::vector<double> ha(n), hct(n), hst(n), hdl(n);
+  std::vector<int64_t> soff(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    if (kind[i] < 0 || kind[i] > 2) return fail(h, EMS_ERR_ARG, "shape kind must be 0, 1, 2");
+    if (bc[i] != 0 && bc[i] != 1) return fail(h, EMS_ERR_ARG, "bc must be 0 or 1");
+    if (!(a[i] > 0) || !std::isfinite(a[i]) || !std::isfinite(theta0[i]))
+      return fail(h, EMS_ERR_ARG, "shape size must be positive and finite");
+    if (a[i] * kExtent[kind[i]] > h->R[i] * (1.0 + 1e-12))
+      return fail(h, EMS_ERR_GEOMETRY, "shape leaves its enclosing disk");
+    hk[i] = kind[i];
+    hbc[i] = bc[i];
+    ha[i] = a[i];
+    hct[i] = std::cos(theta0[i]);
+    hst[i] = std::sin(theta0[i]);
+    hdl[i] = delta > 0 ? delta : kDelta[kind[i]];
+    const int64_t K = 4 * h->p[i] + 2;
+    soff[i + 1] = soff[i] + K * K;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int n2 = 2 * N, nrmax = 2 * (2 * h->pmax + 1);
+  const int64_t mstride = (int64_t)n2 * (n2 + nrmax), estride = (int64_t)nrmax * N;
+  const int64_t per = (int64_t)sizeof(double2) * (mstride + estride);
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(n, ((int64_t)6 << 30) / per));
+  ShapeBufs B;
+  void *d_i = nullptr, *d_d = nullptr, *d_off = nullptr, *d_W = nullptr, *d_E = nullptr,
+       *d_info = nullptr;
+  HIPCHK(h, B.get(&d_i, sizeof(int) * 3 * (size_t)n));
+  HIPCHK(h, B.get(&d_d, sizeof(double) * 4 * (size_t)n));
+  HIPCHK(h, B.get(&d_off, sizeof(int64_t) * (size_t)(n + 1)));
+  HIPCHK(h, B.get(&d_W, sizeof(double2) * (size_t)mstride * chunk));
+  HIPCHK(h, B.get(&d_E, sizeof(double2) * (size_t)estride * chunk));
+  HIPCHK(h, B.get(&d_info, sizeof(int) * (size_t)chunk));
+  int *di = (int *)d_i;
+  double *dd = (double *)d_d;
+  HIPCHK(h, hipMemcpyAsync(di, hk.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(di + n, h->p.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(di + 2 * n, hbc.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dd, ha.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dd + n, hct.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dd + 2 * n, hst.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(dd + 3 * n, hdl.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(d_off, soff.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice,
+                           st));
+  const ems::MfsBatch mb{&h->md, N, di, di + n, di + 2 * n, dd, dd + n, dd + 2 * n, dd + 3 * n,
+                         (const int64_t *)d_off};
+  std::vector<int> info(chunk);
+  for (int i0 = 0; i0 < n; i0 += chunk) {
+    const int cnt = std::min(chunk, n - i0);
+    HIPCHK(h, hipMemsetAsync(d_info, 0, sizeof(int) * cnt, st));
+    HIPCHK(h, ems::launch_mfs_smatrices(mb, i0, cnt, (double2 *)d_W, mstride, (double2 *)d_E,
+                                         estride, (int *)d_info, (double2 *)S_out, st));
+    HIPCHK(h, hipMemcpyAsync(info.data(), d_info, sizeof(int) * cnt, hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    for (int c = 0; c < cnt; ++c)
+      if (info[c]) return fail(h, EMS_ERR_NUMERIC, "singular collocation system of a particle");
+  }
+  return EMS_OK;
+}
+
 static int spec_from(const ems_sommerfeld *s, ems::SommerfeldSpec &o, std::string &err) {
   if (s->kind < 0 || s->kind > 3) {
     err = "sommerfeld kind must be 0, 1, 2, 3";

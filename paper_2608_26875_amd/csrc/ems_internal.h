@@ -364,4 +364,19 @@ hipError_t launch_field_trans(const ems_handle *h, int nrhs, int npts, const dou
 hipError_t launch_field_refl(const ems_handle *h, int nrhs, int npts, const double *pts,
                              double2 *u, hipStream_t st);
 
+// Scattering matrices of non-circular particles by fundamental solutions
+// (shapes.hip).  Per-particle device arrays: kind, a, e^{i theta0} as (ct, st),
+// source offset delta, p, bc; Soff [n+1] complex offsets of the packed
+// row-major output.
+struct MfsBatch {
+  const Media *md;
+  int npts;
+  const int *kind, *p, *bc;
+  const double *a, *ct, *st, *delta;
+  const int64_t *Soff;
+};
+hipError_t launch_mfs_smatrices(const MfsBatch &b, int i0, int cnt, double2 *W, int64_t mstride,
+                                double2 *E, int64_t estride, int *info, double2 *S,
+                                hipStream_t st);
+
 }  // namespace ems
