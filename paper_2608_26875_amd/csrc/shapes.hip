@@ -30,6 +30,7 @@ namespace {
 constexpr int kNB = 16;          // LU panel width
 constexpr int kLuLanes = 512;    // one row of the working matrix per lane
 constexpr int kRC = 32;          // right-hand sides per back-substitution pass
+constexpr int kCC = 192;         // trailing columns per LDS chunk of U12 (48 KB)
 constexpr int kMaxJ = kMaxP + 3; // J_0 .. J_{p+2}
 
 __device__ __forceinline__ double2 cinv(double2 d) {
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
                                                          int *__restrict__ info) {
   __shared__ double2 urow[kNB], krow[kNB];
   __shared__ double2 L11[kNB][kNB];
+  __shared__ double2 Us[kCC][kNB];
   __shared__ int ipiv[kNB];
   __shared__ double redv[kLuLanes / 64];
   __shared__ int redi[kLuLanes / 64];
@@ -372,40 +374,62 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
     }
     __syncthreads();
     const int c1 = k0 + kNB;
-    for (int c = c1 + r; c < ncol; c += kLuLanes) {
-      // keeps the L11 reads inside the loop (hoisted, 120 complex values would
-      // not fit in registers)
-      asm volatile("" ::: "memory");
-      double2 *col = A + (int64_t)c * n2;
-      for (int j = 0; j < kNB; ++j) {
-        const int pv = ipiv[j];
-        if (pv != k0 + j) {
-          const double2 t = col[k0 + j];
-          col[k0 + j] = col[pv];
-          col[pv] = t;
+    // columns right of the panel in chunks of kCC: row swaps and
+    // U12 = L11^{-1} A12 (lane per column, kept in LDS), then the trailing
+    // update A22 -= L21 U12 (lane per row, two columns per pass)
+    for (int cb = c1; cb < ncol; cb += kCC) {
+      const int cn = min(kCC, ncol - cb);
+      if (r < cn) {
+        // keeps the L11 reads inside the chunk loop (hoisted, 120 complex
+        // values would not fit in registers)
+        asm volatile("" ::: "memory");
+        double2 *col = A + (int64_t)(cb + r) * n2;
+        for (int j = 0; j < kNB; ++j) {
+          const int pv = ipiv[j];
+          if (pv != k0 + j) {
+            const double2 t = col[k0 + j];
+            col[k0 + j] = col[pv];
+            col[pv] = t;
+          }
+        }
+        double2 u[kNB];
+#pragma unroll
+        for (int jj = 0; jj < kNB; ++jj) u[jj] = col[k0 + jj];
+#pragma unroll
+        for (int jj = 1; jj < kNB; ++jj)
+#pragma unroll
+          for (int ii = 0; ii < jj; ++ii) u[jj] = csub(u[jj], cmul(L11[jj][ii], u[ii]));
+#pragma unroll
+        for (int jj = 0; jj < kNB; ++jj) {
+          col[k0 + jj] = u[jj];
+          Us[r][jj] = u[jj];
         }
       }
-      double2 u[kNB];
+      __syncthreads();
+      if (r >= c1 && r < n2) {
+        int q = 0;
+        for (; q + 1 < cn; q += 2) {
+          double2 *ca = A + (int64_t)(cb + q) * n2;
+          double2 *cc = ca + n2;
+          double2 a0 = ca[r], a1 = cc[r];
 #pragma unroll
-      for (int jj = 0; jj < kNB; ++jj) u[jj] = col[k0 + jj];
+          for (int jj = 0; jj < kNB; ++jj) {
+            a0 = csub(a0, cmul(pr[jj], Us[q][jj]));
+            a1 = csub(a1, cmul(pr[jj], Us[q + 1][jj]));
+          }
+          ca[r] = a0;
+          cc[r] = a1;
+        }
+        if (q < cn) {
+          double2 *ca = A + (int64_t)(cb + q) * n2;
+          double2 a0 = ca[r];
 #pragma unroll
-      for (int jj = 1; jj < kNB; ++jj)
-#pragma unroll
-        for (int ii = 0; ii < jj; ++ii) u[jj] = csub(u[jj], cmul(L11[jj][ii], u[ii]));
-#pragma unroll
-      for (int jj = 0; jj < kNB; ++jj) col[k0 + jj] = u[jj];
-    }
-    __syncthreads();
-    if (r >= c1 && r < n2) {
-      for (int c = c1; c < ncol; ++c) {
-        double2 *col = A + (int64_t)c * n2;
-        double2 acc = col[r];
-#pragma unroll
-        for (int jj = 0; jj < kNB; ++jj) acc = csub(acc, cmul(pr[jj], col[k0 + jj]));
-        col[r] = acc;
+          for (int jj = 0; jj < kNB; ++jj) a0 = csub(a0, cmul(pr[jj], Us[q][jj]));
+          ca[r] = a0;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
