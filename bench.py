@@ -43,6 +43,8 @@ def parse():
                          "0 switches the solve off; 300 for the gradient workload)")
     ap.add_argument("--nrhs", type=int, default=64, help="block size of the c3 measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip timing the S-matrix generation of the shapes cloud")
     ap.add_argument("--cpu-rows", type=int, default=2)
     ap.add_argument("--fmm-leaf", type=int, default=0, help="particles per FMM leaf (0 = library default)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -262,6 +264,32 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def shape_generation(omega):
+    """Scattering matrices of the 20000-particle cloud with one third each of
+    circles, ellipses (aspect 2) and five-arm stars, generated on the GPU
+    (fundamental solutions, 256 points per particle): wall clock of one call
+    after an untimed call on 64 particles."""
+    import numpy as np
+    import torch
+    import paper_2608_26875_amd as E
+    import workloads as W
+    ws = W.c2_cloud(shapes=True)
+    media = E.make_media(ws.host, ws.substrate, omega)
+    n0 = 64
+    small = E.Operator(ws.xy[:n0], ws.radius[:n0], ws.p[:n0], media, bc=ws.bc[:n0])
+    small.shape_smatrices(ws.shape[:n0], ws.a[:n0], ws.theta0[:n0], ws.bc[:n0])
+    ops = E.Operator(ws.xy, ws.radius, ws.p, media, bc=ws.bc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = ops.shape_smatrices(ws.shape, ws.a, ws.theta0, ws.bc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    del S
+    return {"ms": ms, "us_per_particle": ms * 1e3 / ws.n, "particles": int(ws.n),
+            "kinds": np.bincount(ws.shape, minlength=3).tolist(), "npts": 256,
+            "p": int(ws.p.max())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -363,6 +391,8 @@ def main():
         torch.cuda.synchronize()
         rhs_ms[name] = (time.perf_counter() - t0) * 1e3
     out["rhs_ms"] = rhs_ms
+    if args.workload == "c2" and not args.no_shapes:
+        out["smatrix_shapes"] = shape_generation(w.omega)
     solve_its = 60 if args.solve_its is None else args.solve_its
     if args.solve or solve_its:
         # GMRES to 1e-9 within an iteration budget (restart = min(budget, 300)):
