@@ -18,8 +18,9 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
                               hipStream_t st);
 hipError_t launch_background(int nrhs, int npts, const double *pts, const double2 *comp,
                              double2 *u, hipStream_t st);
+// V: workspace of 2 q (2 pmax + 1) complex values (the node powers).
 hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
-                              int nrhs, double2 *c, hipStream_t st);
+                              int nrhs, double2 *c, double2 *V, hipStream_t st);
 hipError_t launch_point_field(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
                               const double *src, int nrhs, int npts, const double *pts,
                               double2 *u, hipStream_t st);
@@ -1173,7 +1174,8 @@ int ems_incident_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
   const int q = (int)pn.nt.xi.size();
   const size_t nvec = (size_t)nrhs * h->ncoef;
   const size_t nd3 = 3 * (size_t)q, na = 2 * (size_t)q * nrhs;
-  if ((rc = ensure_tmp(h, sizeof(double2) * (nvec + nd3 + na)))) return rc;
+  const size_t nv = 2 * (size_t)q * (2 * h->pmax + 1);
+  if ((rc = ensure_tmp(h, sizeof(double2) * (nvec + nd3 + na + nv)))) return rc;
   std::vector<double2> nd(nd3), amp(na);
   for (int jj = 0; jj < q; ++jj)
     for (int k = 0; k < 3; ++k) nd[3 * (size_t)jj + k] = pn.nd[5 * (size_t)jj + k];
@@ -1186,7 +1188,7 @@ int ems_incident_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
   HIPCHK(h, hipMemcpyAsync(damp, amp.data(), na * sizeof(double2), hipMemcpyHostToDevice, st));
   {
     ems::ProfScope ps(h, "point_local", st);
-    HIPCHK(h, ems::launch_point_local(h, q, dnd, damp, nrhs, c, st));
+    HIPCHK(h, ems::launch_point_local(h, q, dnd, damp, nrhs, c, damp + na, st));
   }
   HIPCHK(h, ems::launch_s_apply(h, c, (double2 *)rhs, nrhs, false, st));
   HIPCHK(h, hipStreamSynchronize(st));

@@ -152,48 +152,76 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
 // potentials per node (weights, e^{-i xi x0} and the source's depth factor
 // included).  Local coefficient of particle m, wave w, order n:
 //   sum_j amp_w(j) e^{i xi_j x_m + s_w y_m} (i (xi_j - s_w)/k_w)^n  (Jacobi-Anger).
-// Block = particle, lane = (wave, order); the exponentials of a tile of
-// nodes are formed once per block in LDS.
-constexpr int kPtTile = 256;
-__global__ void point_local_kernel(int n, int q, const double *__restrict__ xy,
-                                   const int *__restrict__ p, const int64_t *__restrict__ off,
-                                   const double2 *__restrict__ nd, const double2 *__restrict__ amp,
-                                   double kp, double ks, double2 *__restrict__ c, int64_t ncoef) {
-  __shared__ double2 se[2][kPtTile], sz[2][kPtTile];
-  const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
-  const int pm = p[m];
+// The powers are node quantities: point_pow_kernel tabulates them once per
+// call, V [q][2][2 pmax + 1] (negative orders as the reciprocal of the
+// positive power).  point_local_kernel: a block holds G particles of L lanes
+// (lane = wave, order); per tile of kPtTile nodes the powers and the G x 2
+// exponentials go to LDS once and serve every particle of the block.
+constexpr int kPtTile = 32;
+constexpr int kPtLanes = 512;
+__global__ void point_pow_kernel(int q, int pmax, const double2 *__restrict__ nd, double kp,
+                                 double ks, double2 *__restrict__ V) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 2 * q) return;
+  const int j = id >> 1, w = id & 1;
+  const double2 xi = nd[3 * (int64_t)j], s = nd[3 * (int64_t)j + 1 + w];
+  const double k = w ? ks : kp;
+  const double2 d = csub(xi, s);
+  const double2 z = make_double2(-d.y / k, d.x / k);   // i (xi - s) / k
+  const int NP = 2 * pmax + 1;
+  double2 *out = V + (int64_t)id * NP + pmax;
+  double2 r = make_double2(1.0, 0.0);
+  out[0] = r;
+  for (int n = 1; n <= pmax; ++n) {
+    r = cmul(r, z);
+    out[n] = r;
+    const double dd = r.x * r.x + r.y * r.y;
+    out[-n] = make_double2(r.x / dd, -r.y / dd);
+  }
+}
+
+__global__ __launch_bounds__(kPtLanes) void point_local_kernel(
+    int n, int q, int pmax, int L, const double *__restrict__ xy, const int *__restrict__ p,
+    const int64_t *__restrict__ off, const double2 *__restrict__ nd,
+    const double2 *__restrict__ amp, const double2 *__restrict__ V, double2 *__restrict__ c,
+    int64_t ncoef) {
+  __shared__ double2 sv[2 * kPtTile * kMaxModes];
+  __shared__ double2 se[(kPtLanes / 64) * 2 * kPtTile];
+  const int G = kPtLanes / L;
+  const int g = threadIdx.x / L, lane = threadIdx.x % L;
+  const int m = blockIdx.x * G + g, r = blockIdx.y;
+  const int NP = 2 * pmax + 1;
+  const int pm = m < n ? p[m] : 0;
   const int N = 2 * pm + 1;
-  const bool active = lane < 2 * N;
+  const bool active = m < n && lane < 2 * N;
   const int wave = lane < N ? 0 : 1;
-  const int nn = (wave ? lane - N : lane) - pm;
-  const double x = xy[2 * m], y = xy[2 * m + 1];
+  const int col = (wave ? lane - N : lane) - pm + pmax;   // order index into V
   const double2 *A = amp + (int64_t)r * q * 2;
   double2 acc = make_double2(0.0, 0.0);
   for (int j0 = 0; j0 < q; j0 += kPtTile) {
-    for (int t = threadIdx.x; t < kPtTile; t += blockDim.x) {
-      const int j = j0 + t;
-      if (j < q) {
-        const double2 xi = nd[3 * (int64_t)j];
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-          const double2 s = nd[3 * (int64_t)j + 1 + w];
-          const double k = w ? ks : kp;
-          // e^{i xi x + s y}
-          se[w][t] = cmul(A[2 * (int64_t)j + w],
-                          cexp(make_double2(-xi.y * x + s.x * y, xi.x * x + s.y * y)));
-          // i (xi - s) / k
-          const double2 d = csub(xi, s);
-          sz[w][t] = make_double2(-d.y / k, d.x / k);
-        }
-      } else {
-        se[0][t] = se[1][t] = make_double2(0.0, 0.0);
-        sz[0][t] = sz[1][t] = make_double2(1.0, 0.0);
+    const int tn = min(kPtTile, q - j0);
+    // powers of the tile: contiguous [t][w][order] block of V
+    for (int e = threadIdx.x; e < tn * 2 * NP; e += kPtLanes) sv[e] = V[(int64_t)j0 * 2 * NP + e];
+    // exponentials amp_w(j) e^{i xi x_m + s_w y_m}, one per (particle, wave, node)
+    for (int e = threadIdx.x; e < G * 2 * kPtTile; e += kPtLanes) {
+      const int gg = e / (2 * kPtTile), rem = e % (2 * kPtTile), w = rem / kPtTile,
+                tt = rem % kPtTile;
+      const int mm = blockIdx.x * G + gg;
+      double2 v = make_double2(0.0, 0.0);
+      if (mm < n && tt < tn) {
+        const int j = j0 + tt;
+        const double x = xy[2 * mm], y = xy[2 * mm + 1];
+        const double2 xi = nd[3 * (int64_t)j], s = nd[3 * (int64_t)j + 1 + w];
+        v = cmul(A[2 * (int64_t)j + w],
+                 cexp(make_double2(-xi.y * x + s.x * y, xi.x * x + s.y * y)));
       }
+      se[e] = v;
     }
     __syncthreads();
     if (active) {
-      const int tn = min(kPtTile, q - j0);
-      for (int t = 0; t < tn; ++t) cfma(acc, se[wave][t], cpow_int(sz[wave][t], nn));
+      const double2 *ev = se + (g * 2 + wave) * kPtTile;
+      const double2 *pv = sv + wave * NP + col;
+      for (int t = 0; t < tn; ++t) cfma(acc, ev[t], pv[t * 2 * NP]);
     }
     __syncthreads();
   }
@@ -201,9 +229,13 @@ __global__ void point_local_kernel(int n, int q, const double *__restrict__ xy,
 }
 
 hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
-                              int nrhs, double2 *c, hipStream_t st) {
-  hipLaunchKernelGGL(point_local_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->n, q,
-                     h->d_xy, h->d_p, h->d_off, nd, amp, h->md.kp, h->md.ks, c, h->ncoef);
+                              int nrhs, double2 *c, double2 *V, hipStream_t st) {
+  const int pmax = h->pmax;
+  hipLaunchKernelGGL(point_pow_kernel, dim3((2 * q + 255) / 256), dim3(256), 0, st, q, pmax, nd,
+                     h->md.kp, h->md.ks, V);
+  const int L = part_threads(h), G = kPtLanes / L;
+  hipLaunchKernelGGL(point_local_kernel, dim3((h->n + G - 1) / G, nrhs), dim3(kPtLanes), 0, st,
+                     h->n, q, pmax, L, h->d_xy, h->d_p, h->d_off, nd, amp, V, c, h->ncoef);
   return hipGetLastError();
 }
 
