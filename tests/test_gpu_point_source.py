@@ -85,3 +85,19 @@ def test_point_source_outside_substrate_rejected(c0):
     w, m, S, op = c0
     with pytest.raises(E.EmsError, match="substrate"):
         op.incident_point([(1.0, -0.5, 1.0, 0.0)])
+
+
+def test_point_source_rhs_ragged_orders_up_to_16():
+    # orders 13..16: the 128-lane particle groups (4 particles per block)
+    w = W.small_cloud(7, seed=12, p=16, omega=4.0, width=10.0, depth=(1.0, 4.0), ragged=True)
+    assert int(w.p.max()) == 16
+    m = oracle_media(w)
+    S = smatrix.workload_blocks(w, m)
+    op = product_operator(w)
+    op.build()
+    b = to_np(op.incident_point(SOURCES[:1]))
+    x0, y0, a1, a2 = SOURCES[0]
+    ref = point_source.rhs(w, m, S, (x0, y0), (a1, a2))
+    e = rel(b[0], ref)
+    print("point rhs, orders", sorted(set(w.p.tolist())), e, flush=True)
+    assert e <= TOL

@@ -143,3 +143,25 @@ def test_rejected_arguments(cloud):
         op.shape_smatrices(w.shape, w.a, w.theta0, w.bc, npts=100)
     with pytest.raises(E.EmsError, match="kind"):
         op.shape_smatrices(np.full(w.n, 3), w.a, w.theta0, w.bc)
+
+
+def test_smallest_system_and_extreme_orders():
+    # 16 collocation points (2N = 32: two LU panels) and orders 1 and 16
+    xy = np.array([[0.0, -3.0], [4.0, -3.0], [8.0, -3.0]])
+    kind = np.array([1, 2, 0], np.int32)
+    a = np.array([0.4, 0.3, 0.5])
+    R = np.where(kind == 2, 1.3 * a, a)
+    th = np.array([0.4, 2.0, 0.0])
+    bc = np.array([0, 1, 1], np.int32)
+    p = np.array([1, 16, 16], np.int32)
+    media = E.make_media(W.HOST, W.SUBSTRATE, 8.0)
+    op = E.Operator(xy, R, p, media, bc=bc)
+    Sg = op.unpack_smatrices(op.shape_smatrices(kind, a, th, bc, npts=16))
+    m = media_o.Media(W.HOST.lam, W.HOST.mu, W.HOST.rho, W.SUBSTRATE.lam, W.SUBSTRATE.mu,
+                      W.SUBSTRATE.rho, 8.0)
+    for i in range(3):
+        So = shapes.smatrix(m, int(kind[i]), float(a[i]), int(p[i]), int(bc[i]),
+                            theta0=float(th[i]), npts=16)
+        e = np.abs(Sg[i] - So).max() / np.abs(So).max()
+        print("npts 16 particle", i, "p", p[i], e, flush=True)
+        assert e <= TOL
