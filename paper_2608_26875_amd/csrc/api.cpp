@@ -246,6 +246,8 @@ void free_device(ems_handle *h) {
   dfree(h->d_loc);
   dfree(h->d_nbr_ptr);
   dfree(h->d_nbr_idx);
+  dfree(h->d_nbr_off);
+  dfree(h->d_nbr_p);
   dfree(h->d_adj1);
   dfree(h->d_adj2);
   for (auto &D : h->fmm_dev) {
@@ -927,6 +929,18 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
     if ((rc = upload(h, h->d_pool, pool.data(), pool.size()))) return rc;
     if ((rc = upload(h, h->d_nbr_ptr, F.nbr_ptr.data(), F.nbr_ptr.size()))) return rc;
     if ((rc = upload(h, h->d_nbr_idx, F.nbr_idx.data(), std::max<size_t>(1, F.nbr_idx.size())))) return rc;
+    {
+      // partner offsets and orders per near pair: the near-field kernel reads
+      // them by pair position, one dependent load fewer per partner
+      std::vector<int64_t> noff(std::max<size_t>(1, F.nbr_idx.size()), 0);
+      std::vector<int> npp(noff.size(), 0);
+      for (size_t k = 0; k < F.nbr_idx.size(); ++k) {
+        noff[k] = h->off[F.nbr_idx[k]];
+        npp[k] = h->p[F.nbr_idx[k]];
+      }
+      if ((rc = upload(h, h->d_nbr_off, noff.data(), noff.size()))) return rc;
+      if ((rc = upload(h, h->d_nbr_p, npp.data(), npp.size()))) return rc;
+    }
     // near-pair symbols, tabulated once when they fit (forward near field)
     {
       const size_t nt = 4 * (size_t)ems::pm_bucket(h->pmax) + 1;

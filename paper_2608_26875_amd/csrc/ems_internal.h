@@ -227,6 +227,8 @@ struct ems_handle {
   double2 *d_fmm_part = nullptr;  // [nrhs][max_slots][kFmmRows] task-group partials
   double2 *d_nsym = nullptr;      // near-pair symbols [pair][2][4 PMb + 1] (optional)
   int *d_nbr_ptr = nullptr, *d_nbr_idx = nullptr;
+  int64_t *d_nbr_off = nullptr;  // per near pair: coefficient offset of the partner
+  int *d_nbr_p = nullptr;        // per near pair: order of the partner
   double2 *d_adj1 = nullptr, *d_adj2 = nullptr;  // adjoint free-part scratch
   size_t adj_bytes = 0;
 

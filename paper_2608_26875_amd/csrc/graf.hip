@@ -75,7 +75,8 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
     double2 *__restrict__ out, int64_t ldo, double kp, double ks, int adjoint,
     const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx,
-    const double2 *__restrict__ nsym) {
+    const double2 *__restrict__ nsym, const int64_t *__restrict__ nbr_off,
+    const int *__restrict__ nbr_p) {
   using T = typename CT<MIXED>::T;
   constexpr int NT = 4 * PM + 1;
   constexpr int NM = 2 * PM + 1;
@@ -103,6 +104,92 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
   // partners: every other particle, or the near list of b
   const int np = nbr_ptr ? nbr_ptr[b + 1] - nbr_ptr[b] : n;
   const int *nl = nbr_ptr ? nbr_idx + nbr_ptr[b] : nullptr;
+
+  if constexpr (STORED && RB == 1) {
+    // Software-pipelined form of the tabulated near field, one right-hand
+    // side: while batch k is multiplied out of LDS, the symbols and partner
+    // coefficients of batch k+1 are in flight into registers, and the
+    // partner offsets of batch k+2 (read by pair position) behind them, so
+    // no global-load chain is waited for between batches.
+    constexpr int TH = 2 * ROWS;
+    constexpr int NSY = SB * 2 * NT, NCF = SB * 2 * NM;
+    constexpr int PS = (NSY + TH - 1) / TH, PC = (NCF + TH - 1) / TH;
+    const int pb0 = nbr_ptr[b];
+    const double2 *xr = x + (int64_t)r0 * ldx;
+    int64_t po[PC];
+    int pp[PC];
+    double2 rs[PS], rc[PC];
+    auto load_off = [&](int base) {
+#pragma unroll
+      for (int q = 0; q < PC; ++q) {
+        const int e = lane + q * TH, s = e / (2 * NM);
+        const bool ok = e < NCF && base + s < np;
+        po[q] = ok ? nbr_off[pb0 + base + s] : -1;
+        pp[q] = ok ? nbr_p[pb0 + base + s] : -1;
+      }
+    };
+    auto load_val = [&](int base) {
+      const int ns = min(SB, np - base);
+      const double2 *src = nsym + ((int64_t)(pb0 + base) * 2) * NT;
+#pragma unroll
+      for (int q = 0; q < PS; ++q) {
+        const int e = lane + q * TH;
+        rs[q] = e < ns * 2 * NT ? src[e] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < PC; ++q) {
+        const int e = lane + q * TH;
+        const int rem = e % (2 * NM), ww = rem / NM, jj = rem - ww * NM - PM;
+        double2 v = make_double2(0.0, 0.0);
+        if (po[q] >= 0 && jj >= -pp[q] && jj <= pp[q])
+          v = xr[po[q] + ww * (2 * pp[q] + 1) + jj + pp[q]];
+        rc[q] = v;
+      }
+    };
+    load_off(0);
+    load_val(0);
+    load_off(SB);
+    for (int base = 0; base < np; base += SB) {
+#pragma unroll
+      for (int q = 0; q < PS; ++q) {
+        const int e = lane + q * TH;
+        if (e < NSY) {
+          const int s = e / (2 * NT), rem = e - s * 2 * NT;
+          const int ww = rem / NT, kk = rem - ww * NT;
+          t_lds[ww][s][kk] = CT<MIXED>::from(rs[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PC; ++q) {
+        const int e = lane + q * TH;
+        if (e < NCF) {
+          const int s = e / (2 * NM), rem = e - s * (2 * NM);
+          const int ww = rem / NM, jj = rem - ww * NM;
+          c_lds[s][ww][jj] = CT<MIXED>::from(rc[q]);
+        }
+      }
+      __syncthreads();
+      if (base + SB < np) {
+        load_val(base + SB);
+        load_off(base + 2 * SB);
+      }
+      if (i <= PM) {
+        for (int s = 0; s < SB; ++s) {
+#pragma unroll 8
+          for (int jj = 0; jj < NM; ++jj) {
+            const int nu = i - (jj - PM);
+            T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
+            cfma_any(acc[0], tv, c_lds[s][w][jj]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (i >= -pb && i <= pb && r0 < nrhs)
+      out[(int64_t)r0 * ldo + off[b] + w * (2 * pb + 1) + i + pb] =
+          make_double2((double)acc[0].x, (double)acc[0].y);
+    return;
+  }
 
   for (int base = 0; base < np; base += SB) {
     if (STORED) {
@@ -194,7 +281,7 @@ __global__ __launch_bounds__(256) void near_symbols_kernel(int npairs, const dou
   hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV, STV>),                                  \
                      dim3(h->n, (nrhs + RBV - 1) / RBV), dim3(graf_threads(PMV)), 0, st, h->n,   \
                      nrhs, h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,      \
-                     h->md.ks, adjoint ? 1 : 0, nptr, nidx, h->d_nsym)
+                     h->md.ks, adjoint ? 1 : 0, nptr, nidx, h->d_nsym, h->d_nbr_off, h->d_nbr_p)
 #define EMS_GRAF_RB(PMV, MIX, STV)                                                           \
   if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, MIX, 8, STV);                                           \
   else EMS_GRAF_LAUNCH(PMV, MIX, 1, STV);
