@@ -195,8 +195,8 @@ int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double
  * (row-major (4p_m+2)^2 per particle, particle m at complex offset
  * sum_{l<m} (4p_l+2)^2).  Finishes before returning; allocates and frees
  * its device workspace (about 16 (2 npts)(2 npts + 8 pmax + 4) bytes per
- * particle, in batches of at most 6 GiB).  EMS_ERR_NUMERIC when a pivot of
- * a collocation system is exactly zero. */
+ * particle, in batches of at most 6 GiB and 40 % of the free device memory).
+ * EMS_ERR_NUMERIC when a pivot of a collocation system is exactly zero. */
 int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, const double *theta0,
                        const int32_t *bc, int32_t npts, double delta, void *S_out,
                        ems_stream_t stream);

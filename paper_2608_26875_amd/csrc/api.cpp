@@ -637,7 +637,11 @@ int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, cons
   const int n2 = 2 * N, nrmax = 2 * (2 * h->pmax + 1);
   const int64_t mstride = (int64_t)n2 * (n2 + nrmax), estride = (int64_t)nrmax * N;
   const int64_t per = (int64_t)sizeof(double2) * (mstride + estride);
-  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(n, ((int64_t)6 << 30) / per));
+  // workspace batch: at most 6 GiB and 40 % of the free device memory
+  size_t fre = 0, tot = 0;
+  (void)hipMemGetInfo(&fre, &tot);
+  const int64_t cap = std::min<int64_t>((int64_t)6 << 30, (int64_t)(0.4 * (double)fre));
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(n, cap / per));
   ShapeBufs B;
   void *d_i = nullptr, *d_d = nullptr, *d_off = nullptr, *d_W = nullptr, *d_E = nullptr,
        *d_info = nullptr;
