@@ -31,6 +31,7 @@ constexpr int kNB = 16;          // LU panel width
 constexpr int kLuLanes = 512;    // one row of the working matrix per lane
 constexpr int kRC = 32;          // right-hand sides per back-substitution pass
 constexpr int kCC = 192;         // trailing columns per LDS chunk of U12 (48 KB)
+constexpr int kTG = 8;           // trailing columns per pipelined group
 constexpr int kMaxJ = kMaxP + 3; // J_0 .. J_{p+2}
 
 __device__ __forceinline__ double2 cinv(double2 d) {
@@ -292,6 +293,8 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
   __shared__ double2 L11[kNB][kNB];
   __shared__ double2 Us[kCC][kNB];
   __shared__ int ipiv[kNB];
+  __shared__ int prow[2 * kNB], psrc[2 * kNB];   // net row permutation of a panel
+  __shared__ int pcnt;
   __shared__ double redv[kLuLanes / 64];
   __shared__ int redi[kLuLanes / 64];
   const int mloc = blockIdx.x;
@@ -372,11 +375,36 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
 #pragma unroll
       for (int jj = 0; jj < kNB; ++jj) L11[r - k0][jj] = pr[jj];
     }
+    if (r == 0) {
+      // the panel's swaps (k0 + j <-> ipiv[j], in order) as one permutation of
+      // at most 2 kNB rows: after them row prow[i] holds the old row psrc[i];
+      // entries 0..kNB-1 are the panel rows themselves
+      int cnt = kNB;
+      for (int j = 0; j < kNB; ++j) prow[j] = psrc[j] = k0 + j;
+      for (int j = 0; j < kNB; ++j) {
+        const int pv = ipiv[j];
+        int b = -1;
+        if (pv < k0 + kNB) {
+          b = pv - k0;
+        } else {
+          for (int i = kNB; i < cnt; ++i)
+            if (prow[i] == pv) b = i;
+          if (b < 0) {
+            prow[cnt] = psrc[cnt] = pv;
+            b = cnt++;
+          }
+        }
+        const int tmp = psrc[j];
+        psrc[j] = psrc[b];
+        psrc[b] = tmp;
+      }
+      pcnt = cnt;
+    }
     __syncthreads();
     const int c1 = k0 + kNB;
     // columns right of the panel in chunks of kCC: row swaps and
     // U12 = L11^{-1} A12 (lane per column, kept in LDS), then the trailing
-    // update A22 -= L21 U12 (lane per row, two columns per pass)
+    // update A22 -= L21 U12 (lane per row, software-pipelined column groups)
     for (int cb = c1; cb < ncol; cb += kCC) {
       const int cn = min(kCC, ncol - cb);
       if (r < cn) {
@@ -384,17 +412,17 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
         // values would not fit in registers)
         asm volatile("" ::: "memory");
         double2 *col = A + (int64_t)(cb + r) * n2;
-        for (int j = 0; j < kNB; ++j) {
-          const int pv = ipiv[j];
-          if (pv != k0 + j) {
-            const double2 t = col[k0 + j];
-            col[k0 + j] = col[pv];
-            col[pv] = t;
-          }
-        }
-        double2 u[kNB];
+        // every load of the permutation first (independent), then the stores
+        const int cnt = pcnt;
+        double2 u[kNB], ext[kNB];
 #pragma unroll
-        for (int jj = 0; jj < kNB; ++jj) u[jj] = col[k0 + jj];
+        for (int jj = 0; jj < kNB; ++jj) u[jj] = col[psrc[jj]];
+#pragma unroll
+        for (int i = 0; i < kNB; ++i)
+          ext[i] = kNB + i < cnt ? col[psrc[kNB + i]] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < kNB; ++i)
+          if (kNB + i < cnt) col[prow[kNB + i]] = ext[i];
 #pragma unroll
         for (int jj = 1; jj < kNB; ++jj)
 #pragma unroll
@@ -407,25 +435,30 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
       }
       __syncthreads();
       if (r >= c1 && r < n2) {
-        int q = 0;
-        for (; q + 1 < cn; q += 2) {
-          double2 *ca = A + (int64_t)(cb + q) * n2;
-          double2 *cc = ca + n2;
-          double2 a0 = ca[r], a1 = cc[r];
+        // groups of kTG columns, the next group's loads in flight while the
+        // current one is updated
+        double2 cur[kTG], nxt[kTG];
 #pragma unroll
-          for (int jj = 0; jj < kNB; ++jj) {
-            a0 = csub(a0, cmul(pr[jj], Us[q][jj]));
-            a1 = csub(a1, cmul(pr[jj], Us[q + 1][jj]));
+        for (int u = 0; u < kTG; ++u)
+          cur[u] = u < cn ? A[(int64_t)(cb + u) * n2 + r] : make_double2(0.0, 0.0);
+        for (int q = 0; q < cn; q += kTG) {
+          if (q + kTG < cn) {
+#pragma unroll
+            for (int u = 0; u < kTG; ++u)
+              nxt[u] = q + kTG + u < cn ? A[(int64_t)(cb + q + kTG + u) * n2 + r]
+                                        : make_double2(0.0, 0.0);
           }
-          ca[r] = a0;
-          cc[r] = a1;
-        }
-        if (q < cn) {
-          double2 *ca = A + (int64_t)(cb + q) * n2;
-          double2 a0 = ca[r];
 #pragma unroll
-          for (int jj = 0; jj < kNB; ++jj) a0 = csub(a0, cmul(pr[jj], Us[q][jj]));
-          ca[r] = a0;
+          for (int u = 0; u < kTG; ++u) {
+            if (q + u < cn) {
+              double2 a0 = cur[u];
+#pragma unroll
+              for (int jj = 0; jj < kNB; ++jj) a0 = csub(a0, cmul(pr[jj], Us[q + u][jj]));
+              A[(int64_t)(cb + q + u) * n2 + r] = a0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kTG; ++u) cur[u] = nxt[u];
         }
       }
       __syncthreads();
