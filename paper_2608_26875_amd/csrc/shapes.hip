@@ -29,9 +29,10 @@ namespace {
 
 constexpr int kNB = 16;          // LU panel width
 constexpr int kLuLanes = 512;    // one row of the working matrix per lane
-constexpr int kRC = 32;          // right-hand sides per back-substitution pass
+constexpr int kRC = 31;          // right-hand sides per back-substitution pass (62 at p = 15)
 constexpr int kCC = 192;         // trailing columns per LDS chunk of U12 (48 KB)
 constexpr int kTG = 8;           // trailing columns per pipelined group
+constexpr int kBD = 4;           // back-substitution rows loaded ahead
 constexpr int kMaxJ = kMaxP + 3; // J_0 .. J_{p+2}
 
 __device__ __forceinline__ double2 cinv(double2 d) {
@@ -484,21 +485,31 @@ __global__ __launch_bounds__(kLuLanes) void mfs_backsolve_kernel(double2 *__rest
 #pragma unroll
     for (int q = 0; q < kRC; ++q)
       y[q] = (r < n2 && q < nc) ? A[(int64_t)(n2 + c0 + q) * n2 + r] : make_double2(0.0, 0.0);
-    for (int k = n2 - 1; k >= 0; --k) {
-      double2 *buf = xs[k & 1];
-      if (r == k) {
-        const double2 d = cinv(A[(int64_t)k * n2 + k]);
+    // column entries U[r][k] loaded kBD rows ahead (n2 is a multiple of kBD)
+    double2 ur[kBD];
 #pragma unroll
-        for (int q = 0; q < kRC; ++q) {
-          y[q] = cmul(y[q], d);
-          buf[q] = y[q];
+    for (int d = 0; d < kBD; ++d)
+      ur[d] = r < n2 ? A[(int64_t)(n2 - 1 - d) * n2 + r] : make_double2(0.0, 0.0);
+    for (int kb = n2 - 1; kb >= 0; kb -= kBD) {
+#pragma unroll
+      for (int d = 0; d < kBD; ++d) {
+        const int k = kb - d;
+        const double2 u = ur[d];   // U[r][k]; the diagonal for lane k
+        if (k - kBD >= 0 && r < n2) ur[d] = A[(int64_t)(k - kBD) * n2 + r];
+        double2 *buf = xs[k & 1];
+        if (r == k) {
+          const double2 di = cinv(u);
+#pragma unroll
+          for (int q = 0; q < kRC; ++q) {
+            y[q] = cmul(y[q], di);
+            buf[q] = y[q];
+          }
         }
-      }
-      __syncthreads();
-      if (r < k) {
-        const double2 u = A[(int64_t)k * n2 + r];
+        __syncthreads();
+        if (r < k) {
 #pragma unroll
-        for (int q = 0; q < kRC; ++q) y[q] = csub(y[q], cmul(u, buf[q]));
+          for (int q = 0; q < kRC; ++q) y[q] = csub(y[q], cmul(u, buf[q]));
+        }
       }
     }
     if (r < n2) {
