@@ -116,7 +116,7 @@ struct FmmLevel {
 constexpr int kFmmRows = 192;
 struct FmmLaunch {
   const char *name = "fmm";
-  int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0;
+  int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0, max_out_P = 0;
   double flops = 0.0;  // 8 (2 P_out + 1)(2 P_in + 1) summed over the tasks, per right-hand side
   std::vector<int> ptr, in_P, sym_L, sgn, out_P, item_out, item_row0;
   std::vector<int> item_t0, item_t1, item_slot;  // task range, partial slot (-1: direct)

@@ -405,6 +405,7 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
     }
     F.max_slots = std::max(F.max_slots, L.nslot);
     for (int t = 0; t < (int)L.in_P.size(); ++t) L.max_in_P = std::max(L.max_in_P, L.in_P[t]);
+    for (int o = 0; o < L.nout; ++o) L.max_out_P = std::max(L.max_out_P, L.out_P[o]);
     L.flops = 0.0;
     for (int o = 0; o < L.nout; ++o)
       for (int t = L.ptr[o]; t < L.ptr[o + 1]; ++t)

@@ -19,11 +19,14 @@ namespace ems {
 // entries across lanes, conflict-free for odd R) per R complex multiply-adds.
 // The input coefficient of column j is the same for every lane and is read
 // with scalar loads straight from the expansion array.
+// Launches whose outputs all have at most 64 rows (the particle-side L2P of
+// orders up to 31) take R = 1, one row per lane: with R = 3 only a third of
+// the lanes would hold rows.
 constexpr int kToepR = 3;
 constexpr int kToepRows = 64 * kToepR;
 static_assert(kToepRows == kFmmRows, "item chunk of the plan");
 
-template <int RB>
+template <int RB, int R>
 __global__ __launch_bounds__(64) void toep_task_kernel(
     const int *__restrict__ ptr, const int64_t *__restrict__ in_base,
     const int *__restrict__ in_P, const int64_t *__restrict__ sym_base,
@@ -35,12 +38,12 @@ __global__ __launch_bounds__(64) void toep_task_kernel(
     const double2 *__restrict__ in_alt, int64_t alt_stride, const double2 *__restrict__ pool,
     double2 *__restrict__ out, int64_t out_stride, double2 *__restrict__ part,
     int64_t part_stride, int accumulate, int max_in, int nrhs) {
-  constexpr int R = kToepR;
+  constexpr int ROWSR = 64 * R;            // rows of one item
   extern __shared__ double2 vs[];           // [2 max_in + kToepRows]
   const int item = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
   const int o = item_out[item], row0 = item_row0[item];
   const int Po = out_P[o];
-  const int rows = min(kToepRows, 2 * Po + 1 - row0);
+  const int rows = min(ROWSR, 2 * Po + 1 - row0);
   const int k_lo = -Po + row0, k_hi = k_lo + rows - 1;
   const int kb = k_lo + tid * R;            // first row of this lane
   const int b0 = k_hi - kb;                 // rows r <= b0 are inside the item
@@ -150,18 +153,22 @@ hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int n
     const size_t lds = sizeof(double2) * (size_t)(2 * L.max_in_P + kToepRows);
     ProfScope ps(const_cast<ems_handle *>(h), L.name, st, L.flops * nrhs);
     const int64_t pst = (int64_t)F.max_slots * kFmmRows;
-    if (nrhs > 1)
-      hipLaunchKernelGGL((toep_task_kernel<8>), dim3((unsigned)L.item_out.size(), (nrhs + 7) / 8),
-                         dim3(64), lds, st, D.ptr, D.in_base, D.in_P, D.sym_base, D.sym_L, D.sgn,
-                         D.out_base, D.out_P, D.item_out, D.item_row0, D.item_t0, D.item_t1,
-                         D.item_slot, in, in_stride, h->d_loc, F.exp_len, h->d_pool, out,
-                         out_stride, h->d_fmm_part, pst, L.accumulate, L.max_in_P, nrhs);
-    else
-      hipLaunchKernelGGL((toep_task_kernel<1>), dim3((unsigned)L.item_out.size(), 1), dim3(64),
-                         lds, st, D.ptr, D.in_base, D.in_P, D.sym_base, D.sym_L, D.sgn, D.out_base,
-                         D.out_P, D.item_out, D.item_row0, D.item_t0, D.item_t1, D.item_slot, in,
-                         in_stride, h->d_loc, F.exp_len, h->d_pool, out, out_stride,
-                         h->d_fmm_part, pst, L.accumulate, L.max_in_P, nrhs);
+    const bool narrow = 2 * L.max_out_P + 1 <= 64;
+#define EMS_TOEP_LAUNCH(RBV, RV)                                                               \
+  hipLaunchKernelGGL((toep_task_kernel<RBV, RV>),                                              \
+                     dim3((unsigned)L.item_out.size(), (nrhs + RBV - 1) / RBV), dim3(64), lds, st, \
+                     D.ptr, D.in_base, D.in_P, D.sym_base, D.sym_L, D.sgn, D.out_base, D.out_P,   \
+                     D.item_out, D.item_row0, D.item_t0, D.item_t1, D.item_slot, in, in_stride,   \
+                     h->d_loc, F.exp_len, h->d_pool, out, out_stride, h->d_fmm_part, pst,        \
+                     L.accumulate, L.max_in_P, nrhs)
+    if (nrhs > 1) {
+      if (narrow) EMS_TOEP_LAUNCH(8, 1);
+      else EMS_TOEP_LAUNCH(8, kToepR);
+    } else {
+      if (narrow) EMS_TOEP_LAUNCH(1, 1);
+      else EMS_TOEP_LAUNCH(1, kToepR);
+    }
+#undef EMS_TOEP_LAUNCH
     if (!L.red_out.empty())
       hipLaunchKernelGGL(fmm_reduce_kernel, dim3((unsigned)L.red_out.size(), nrhs), dim3(kFmmRows),
                          0, st, D.red_out, D.red_row0, D.red_slot0, D.red_g, D.out_P, D.out_base,
