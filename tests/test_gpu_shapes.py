@@ -165,3 +165,42 @@ def test_smallest_system_and_extreme_orders():
         e = np.abs(Sg[i] - So).max() / np.abs(So).max()
         print("npts 16 particle", i, "p", p[i], e, flush=True)
         assert e <= TOL
+
+
+def test_adjoint_apply_on_generated_matrices(cloud):
+    # a non-circular particle's S is not diagonal (nor symmetric), so this
+    # checks that the adjoint applies S^H, not S^T or S: <y, A x> with the
+    # oracle's forward operator against <A^H y, x> from the library
+    w, m, _, Sg = cloud
+    op = _operator(w, S_blocks=Sg)
+    op.build()
+    x = W.random_coeffs(w.n_coeff, seed=5)[0]
+    y = W.random_coeffs(w.n_coeff, seed=6)[0]
+    ax = operator.apply(w, m, Sg, x, tol=1e-13)
+    ahy = to_np(op.apply(to_gpu(y[None]), adjoint=True))[0]
+    lhs, rhs = np.vdot(y, ax), np.vdot(ahy, x)
+    print("adjoint identity", lhs, rhs, flush=True)
+    assert abs(lhs - rhs) <= 1e-11 * np.linalg.norm(y) * np.linalg.norm(ax)
+
+
+def test_gradient_on_generated_matrices():
+    from oracle import gradient as G
+    w = W.cloud(6, 14.0, (1.0, 4.0), seed=8, p=5, omega=4.0, shapes=True, min_z_clear=0.6,
+                name="shapes6")
+    m = oracle_media(w)
+    op = _operator(w)
+    Sg = op.unpack_smatrices(op.shape_smatrices(w.shape, w.a, w.theta0, w.bc, npts=128))
+    op.set_smatrices(Sg)
+    op.build()
+    pts = np.stack([np.linspace(-1.0, 15.0, 7), np.full(7, -0.4)], 1)
+    waves = [(0, np.radians(25.0)), (1, np.radians(-40.0))]
+    rng = np.random.default_rng(8)
+    u_obs = (rng.normal(size=(2, 7, 2)) + 1j * rng.normal(size=(2, 7, 2))) * 0.1
+    J0, gxy0, gl0 = G.gradient(w, m, Sg, waves, pts, u_obs)
+    J, gxy, gl, info = op.misfit_gradient(waves, pts, u_obs, tol=1e-12)
+    print("shapes gradient J", J, J0, "dxy", np.abs(gxy - gxy0).max(), np.abs(gxy0).max(),
+          "lame", gl, gl0, flush=True)
+    assert abs(J - J0) <= 1e-10 * J0
+    scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
+    assert np.abs(gxy - gxy0).max() <= 1e-8 * scale
+    assert np.abs(np.asarray(gl) - gl0).max() <= 1e-8 * scale
