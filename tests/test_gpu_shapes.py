@@ -9,7 +9,9 @@ solves it with numpy's LU:
 * circles against the closed-form disk matrix, and I + 2S unitary;
 * more particles than one workspace batch: identical shapes give identical
   matrices across the batch boundary;
-* the operator built on generated matrices against the oracle's operator;
+* the operator built on generated (non-diagonal) matrices against the
+  oracle's: forward apply, adjoint apply (inner-product identity), FP64 and
+  mixed GMRES (backward residual), misfit gradient;
 * rejected arguments (shape outside its enclosing disk, npts).
 
 Tolerance: 1e-11 relative to max |S| (measured: 2e-13 at worst).  The two
@@ -204,3 +206,23 @@ def test_gradient_on_generated_matrices():
     scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
     assert np.abs(gxy - gxy0).max() <= 1e-8 * scale
     assert np.abs(np.asarray(gl) - gl0).max() <= 1e-8 * scale
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_on_generated_matrices(cloud, precision):
+    # FP64 GMRES and the mixed form (complex64 copy of S in the inner solve)
+    # with non-diagonal S: plane-wave right-hand side against the oracle's,
+    # backward residual under the oracle's operator
+    from oracle import incident
+    w, m, _, Sg = cloud
+    op = _operator(w, S_blocks=Sg)
+    op.build()
+    wave, ang = w.incidence[0]
+    b = op.incident([(wave, ang)])
+    b_orc = incident.rhs(w, m, Sg, wave, ang)
+    assert rel(to_np(b)[0], b_orc) <= 1e-12
+    x, info = op.solve(b, tol=1e-11, restart=200, maxit=600, precision=precision)
+    print("shapes solve", precision, info, flush=True)
+    assert info["converged"] == 1
+    r = b_orc - operator.apply(w, m, Sg, to_np(x)[0], tol=1e-13)
+    assert np.linalg.norm(r) / np.linalg.norm(b_orc) <= 1e-9
