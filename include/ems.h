@@ -181,16 +181,19 @@ int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double
  * the GPU for the handle's particles (after ems_set_media and
  * ems_set_particles; orders p from the particles).  Host arrays, one entry
  * per particle: kind 0 circle of radius a, 1 ellipse with semi-axes a and
- * a/2, 2 five-arm star r(t) = a (1 + 0.3 cos 5t), each about the particle
- * centre and turned by theta0 (radians, counter-clockwise in the paper
- * frame); bc 0 rigid (u = 0), 1 traction-free.  The shape must lie inside
- * the enclosing radius R (a, a, 1.3 a), else EMS_ERR_GEOMETRY.
+ * a/2, 2 five-arm star r(t) = a (1 + 0.3 cos 5t), and the paper's family
+ * r(t) = a1 + a2 cos(a3 t) of Section 6 with a1 = a, a2 = a/4: 3 pear
+ * (a3 = 3), 4 starfish (a3 = 5); each about the particle centre and turned
+ * by theta0 (radians, counter-clockwise in the paper frame); bc 0 rigid
+ * (u = 0), 1 traction-free.  The shape must lie inside the enclosing radius
+ * R (a, a, 1.3 a, 1.25 a, 1.25 a), else EMS_ERR_GEOMETRY.
  * Discretisation (the paper uses a boundary integral equation; here the
  * method of fundamental solutions): npts compressional and npts shear
  * monopoles H_0 at z(t_j + i delta), t_j = 2 pi j / npts, the boundary
  * condition collocated at z(t_j), Graf's addition theorem projects the
  * monopoles onto the outgoing coefficients.  npts a multiple of 8 in
- * [16, 256] (0 = 256); delta <= 0 selects 0.3 / 0.2 / 0.12 by shape.
+ * [16, 256] (0 = 256); delta <= 0 selects 0.3 / 0.2 / 0.12 / 0.2 / 0.16 by
+ * kind.
  * S_out (device): the matrices in the packing ems_set_smatrices reads
  * (row-major (4p_m+2)^2 per particle, particle m at complex offset
  * sum_{l<m} (4p_l+2)^2).  Finishes before returning; allocates and frees

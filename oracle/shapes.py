@@ -21,7 +21,9 @@ so alpha_l = sum_j c_j J_l(kp |y_j|) e^{-i l th_j} and beta_l likewise with
 (d_j, ks).
 
 Shapes (paper frame, about the centre, turned by theta0): 0 circle of radius a;
-1 ellipse with semi-axes a and a/2; 2 five-arm star r(t) = a (1 + 0.3 cos 5t).
+1 ellipse with semi-axes a and a/2; 2 five-arm star r(t) = a (1 + 0.3 cos 5t);
+and the paper's own family r(t) = a1 + a2 cos(a3 t) (Section 6) with
+a2 = a1/4: 3 pear (a3 = 3), 4 starfish (a3 = 5), a = a1.
 """
 from __future__ import annotations
 
@@ -30,7 +32,9 @@ from scipy import special
 
 from .media import Media
 
-DELTA = {0: 0.3, 1: 0.2, 2: 0.12}
+DELTA = {0: 0.3, 1: 0.2, 2: 0.12, 3: 0.2, 4: 0.16}
+# rose curves r = a (1 + eps cos(m t)): kind -> (m, eps)
+ROSE = {2: (5, 0.3), 3: (3, 0.25), 4: (5, 0.25)}
 
 
 def boundary(kind: int, a: float, t, delta: float = 0.0):
@@ -41,9 +45,10 @@ def boundary(kind: int, a: float, t, delta: float = 0.0):
     elif kind == 1:
         z = a * np.cos(tt) + 0.5j * a * np.sin(tt)
         dz = -a * np.sin(tt) + 0.5j * a * np.cos(tt)
-    elif kind == 2:
-        r = a * (1 + 0.3 * np.cos(5 * tt))
-        dr = -1.5 * a * np.sin(5 * tt)
+    elif kind in ROSE:
+        mm, eps = ROSE[kind]
+        r = a * (1 + eps * np.cos(mm * tt))
+        dr = -eps * mm * a * np.sin(mm * tt)
         z, dz = r * np.exp(1j * tt), (dr + 1j * r) * np.exp(1j * tt)
     else:
         raise ValueError("unknown shape")

@@ -294,8 +294,9 @@ class Operator:
     def shape_smatrices(self, kind, a, theta0, bc, npts=0, delta=0.0, stream=None):
         """Scattering matrices of the particles' shapes, generated on the GPU
         (Section 3.3; method of fundamental solutions, ems_smatrix_shapes):
-        kind 0 circle, 1 ellipse (semi-axes a, a/2), 2 five-arm star, turned by
-        theta0.  Returns a complex128 device tensor in the packing
+        kind 0 circle, 1 ellipse (semi-axes a, a/2), 2 five-arm star, 3 pear,
+        4 starfish (the paper's a1 + a2 cos(a3 t), a2 = a1/4, a3 = 3, 5),
+        turned by theta0.  Returns a complex128 device tensor in the packing
         set_smatrices reads (row-major (4p+2)^2 per particle)."""
         import torch
         n = self.n

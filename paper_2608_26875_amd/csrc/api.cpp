@@ -612,13 +612,13 @@ int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, cons
     return fail(h, EMS_ERR_ARG, "npts must be a multiple of 8 in [16, 256]");
   if (!std::isfinite(delta)) return fail(h, EMS_ERR_ARG, "non-finite delta");
   const int n = h->n;
-  static const double kDelta[3] = {0.3, 0.2, 0.12};
-  static const double kExtent[3] = {1.0, 1.0, 1.3};   // max |z(t)| / a
+  static const double kDelta[5] = {0.3, 0.2, 0.12, 0.2, 0.16};
+  static const double kExtent[5] = {1.0, 1.0, 1.3, 1.25, 1.25};   // max |z(t)| / a
   std::vector<int> hk(n), hbc(n);
   std::vector<double> ha(n), hct(n), hst(n), hdl(n);
   std::vector<int64_t> soff(n + 1, 0);
   for (int i = 0; i < n; ++i) {
-    if (kind[i] < 0 || kind[i] > 2) return fail(h, EMS_ERR_ARG, "shape kind must be 0, 1, 2");
+    if (kind[i] < 0 || kind[i] > 4) return fail(h, EMS_ERR_ARG, "shape kind must be 0 .. 4");
     if (bc[i] != 0 && bc[i] != 1) return fail(h, EMS_ERR_ARG, "bc must be 0 or 1");
     if (!(a[i] > 0) || !std::isfinite(a[i]) || !std::isfinite(theta0[i]))
       return fail(h, EMS_ERR_ARG, "shape size must be positive and finite");

@@ -88,8 +88,10 @@ __device__ void bessel_jy(double x, int m, double *J, double &Y0, double &Y1) {
 }
 
 // Point z(t + i delta) of shape kind (0 circle radius a, 1 ellipse semi-axes
-// a and a/2, 2 star r = a (1 + 0.3 cos 5t)) turned by (ct, st) = e^{i theta0},
-// and dz/dt; complex numbers stand for points (Re, Im).
+// a and a/2, and the curves r = a (1 + eps cos(m t)): 2 star (m 5, eps 0.3),
+// 3 pear (m 3, eps 1/4), 4 starfish (m 5, eps 1/4), the last two the paper's
+// a1 + a2 cos(a3 t) with a2 = a1/4) turned by (ct, st) = e^{i theta0}, and
+// dz/dt; complex numbers stand for points (Re, Im).
 __device__ void shape_point(int kind, double a, double t, double delta, double ct, double st,
                             double2 &z, double2 &dz) {
   double s, c;
@@ -106,13 +108,14 @@ __device__ void shape_point(int kind, double a, double t, double delta, double c
     z = make_double2(a * cz.x - 0.5 * a * sz.y, a * cz.y + 0.5 * a * sz.x);
     dz = make_double2(-a * sz.x - 0.5 * a * cz.y, -a * sz.y + 0.5 * a * cz.x);
   } else {
+    const double m = kind == 3 ? 3.0 : 5.0, eps = kind == 2 ? 0.3 : 0.25;
     double s5, c5;
-    sincos(5.0 * t, &s5, &c5);
-    const double ch5 = cosh(5.0 * delta), sh5 = sinh(5.0 * delta);
-    const double2 c5z = make_double2(c5 * ch5, -s5 * sh5);
-    const double2 s5z = make_double2(s5 * ch5, c5 * sh5);
-    const double2 r = make_double2(a * (1.0 + 0.3 * c5z.x), a * 0.3 * c5z.y);
-    const double2 dr = cscale(s5z, -1.5 * a);
+    sincos(m * t, &s5, &c5);
+    const double ch5 = cosh(m * delta), sh5 = sinh(m * delta);
+    const double2 c5z = make_double2(c5 * ch5, -s5 * sh5);   // cos(m (t + i delta))
+    const double2 s5z = make_double2(s5 * ch5, c5 * sh5);    // sin(m (t + i delta))
+    const double2 r = make_double2(a * (1.0 + eps * c5z.x), a * eps * c5z.y);
+    const double2 dr = cscale(s5z, -eps * m * a);
     z = cmul(r, e);
     dz = cmul(make_double2(dr.x - r.y, dr.y + r.x), e);
   }

@@ -4,7 +4,8 @@ assembles the same collocation system with scipy's Bessel functions and
 solves it with numpy's LU:
 
 * a nine-particle cloud with circles, ellipses and stars, rigid and
-  traction-free, turned, ragged orders p in [5, 16], 256 points;
+  traction-free, turned, ragged orders p in [5, 16], 256 points; the
+  paper's pear and starfish;
 * 128 points (a second system size) and a user delta;
 * circles against the closed-form disk matrix, and I + 2S unitary;
 * more particles than one workspace batch: identical shapes give identical
@@ -144,7 +145,7 @@ def test_rejected_arguments(cloud):
     with pytest.raises(E.EmsError, match="npts"):
         op.shape_smatrices(w.shape, w.a, w.theta0, w.bc, npts=100)
     with pytest.raises(E.EmsError, match="kind"):
-        op.shape_smatrices(np.full(w.n, 3), w.a, w.theta0, w.bc)
+        op.shape_smatrices(np.full(w.n, 5), w.a, w.theta0, w.bc)
 
 
 def test_smallest_system_and_extreme_orders():
@@ -226,3 +227,25 @@ def test_solve_on_generated_matrices(cloud, precision):
     assert info["converged"] == 1
     r = b_orc - operator.apply(w, m, Sg, to_np(x)[0], tol=1e-13)
     assert np.linalg.norm(r) / np.linalg.norm(b_orc) <= 1e-9
+
+
+def test_pear_and_starfish_match_oracle():
+    # the paper's own shapes r = a1 + a2 cos(a3 t), a2 = a1/4, a3 = 3 and 5
+    xy = np.array([[0.0, -3.0], [4.0, -3.0], [8.0, -3.0], [12.0, -3.0]])
+    kind = np.array([3, 3, 4, 4], np.int32)
+    a = np.array([0.55, 0.4, 0.6, 0.35])
+    R = 1.25 * a
+    th = np.array([0.0, 2.2, 0.9, 4.0])
+    bc = np.array([0, 1, 0, 1], np.int32)
+    p = np.array([15, 12, 16, 10], np.int32)
+    media = E.make_media(W.HOST, W.SUBSTRATE, 8.0)
+    op = E.Operator(xy, R, p, media, bc=bc)
+    Sg = op.unpack_smatrices(op.shape_smatrices(kind, a, th, bc))
+    m = media_o.Media(W.HOST.lam, W.HOST.mu, W.HOST.rho, W.SUBSTRATE.lam, W.SUBSTRATE.mu,
+                      W.SUBSTRATE.rho, 8.0)
+    for i in range(4):
+        So = shapes.smatrix(m, int(kind[i]), float(a[i]), int(p[i]), int(bc[i]),
+                            theta0=float(th[i]))
+        e = np.abs(Sg[i] - So).max() / np.abs(So).max()
+        print("kind", kind[i], "bc", bc[i], "p", p[i], e, flush=True)
+        assert e <= TOL

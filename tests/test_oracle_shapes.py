@@ -32,7 +32,7 @@ def test_circle_matches_closed_form(bc, a):
     assert e < (1e-12 if bc == 0 else 1e-8)
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 3, 4])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_unitarity_residual_and_convergence(kind, bc):
     S, res = shapes.smatrix(M0, kind, 0.6, P, bc, residual=True)
@@ -44,7 +44,7 @@ def test_unitarity_residual_and_convergence(kind, bc):
     assert eu < 1e-8 and ec < 1e-8 and res < 1e-4
 
 
-@pytest.mark.parametrize("kind,bc", [(1, 0), (2, 1)])
+@pytest.mark.parametrize("kind,bc", [(1, 0), (2, 1), (3, 1), (4, 0)])
 def test_turned_particle_is_basis_rotation(kind, bc):
     th = 0.7
     S0 = shapes.smatrix(M0, kind, 0.5, P, bc)

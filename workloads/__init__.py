@@ -24,7 +24,7 @@ import math
 
 import numpy as np
 
-SHAPE_CIRCLE, SHAPE_ELLIPSE, SHAPE_STAR = 0, 1, 2
+SHAPE_CIRCLE, SHAPE_ELLIPSE, SHAPE_STAR, SHAPE_PEAR, SHAPE_STARFISH = 0, 1, 2, 3, 4
 BC_RIGID, BC_TRACTION_FREE = 0, 1
 
 
