@@ -172,6 +172,19 @@ int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *
  * offsets has n+1 entries counted in complex elements. */
 int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets);
 
+/* Per-particle scattering matrices as turned copies of a few prototypes
+ * (Section 3.3: finitely many distinct shapes, placed at any orientation):
+ * particle m gets S_m = D S_{which[m]} D^H with D = diag(e^{-i n theta0[m]})
+ * over [alpha_{-p..p}, beta_{-p..p}] (the coefficients of a shape turned by
+ * theta0 counter-clockwise).  Host data, read during the call: nproto
+ * prototypes packed row-major as in ems_set_smatrices, proto_off[nproto+1]
+ * complex offsets from 0; which[n] in [0, nproto) and theta0[n] per particle.
+ * A prototype's size must be (4 p_m + 2)^2 of every particle that uses it,
+ * else EMS_ERR_ARG.  Replaces any matrices set before. */
+int ems_set_smatrices_rotated(ems_handle *h, int32_t nproto, const double *S_proto,
+                              const int64_t *proto_off, const int32_t *which,
+                              const double *theta0);
+
 /* Closed-form scattering matrix of a disk of radius a (Section 3.1: boundary
  * condition imposed mode by mode; bc 0 rigid u = 0, bc 1 traction-free).
  * Writes (4p+2)^2 complex128 row-major into host memory S_out. */

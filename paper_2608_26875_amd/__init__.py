@@ -113,6 +113,7 @@ def _load():
         "ems_set_smatrices": ([P, P, P], I32),
         "ems_smatrix_disk": ([ctypes.POINTER(Media), D, I32, I32, P], I32),
         "ems_smatrix_shapes": ([P, P, P, P, P, I32, D, P, P], I32),
+        "ems_set_smatrices_rotated": ([P, I32, P, P, P, P], I32),
         "ems_set_sommerfeld": ([P, ctypes.POINTER(Sommerfeld)], I32),
         "ems_build": ([P, P], I32),
         "ems_get_info": ([P, ctypes.POINTER(BuildInfo)], I32),
@@ -149,7 +150,8 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems_set_particles",
-            "ems_set_smatrices", "ems_smatrix_disk", "ems_smatrix_shapes", "ems_set_sommerfeld",
+            "ems_set_smatrices", "ems_smatrix_disk", "ems_smatrix_shapes", "ems_set_smatrices_rotated",
+            "ems_set_sommerfeld",
             "ems_build",
             "ems_get_info", "ems_apply", "ems_apply_adjoint", "ems_incident", "ems_solve",
             "ems_solve_adjoint", "ems_eval_scattered_adjoint", "ems_param_vjp", "ems_autotune",
@@ -321,6 +323,20 @@ class Operator:
             out.append(flat[o: o + K * K].reshape(K, K))
             o += K * K
         return out
+
+    def set_smatrices_rotated(self, prototypes, which, theta0):
+        """Per-particle S as turned copies of prototype matrices (Section 3.3):
+        S_m = D prototypes[which[m]] D^H, D = diag(e^{-i n theta0[m]})."""
+        sizes = [np.asarray(b).size for b in prototypes]
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        flat = np.ascontiguousarray(np.concatenate(
+            [np.asarray(b, np.complex128).ravel() for b in prototypes]))
+        which = np.ascontiguousarray(np.broadcast_to(which, self.n), dtype=np.int32)
+        theta0 = np.ascontiguousarray(np.broadcast_to(theta0, self.n), dtype=np.float64)
+        self._check(_lib.ems_set_smatrices_rotated(self.h, len(prototypes), flat.ctypes.data,
+                                                   off.ctypes.data, which.ctypes.data,
+                                                   theta0.ctypes.data))
+        self.built = False
 
     def set_smatrices(self, blocks):
         sizes = [b.size for b in blocks]

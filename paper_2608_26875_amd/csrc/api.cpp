@@ -572,6 +572,48 @@ int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets) {
   return EMS_OK;
 }
 
+int ems_set_smatrices_rotated(ems_handle *h, int32_t nproto, const double *S_proto,
+                              const int64_t *proto_off, const int32_t *which,
+                              const double *theta0) {
+  if (!h || nproto <= 0 || !S_proto || !proto_off || !which || !theta0)
+    return fail(h, EMS_ERR_ARG, "bad prototype arguments");
+  if (!h->have_particles) return fail(h, EMS_ERR_STATE, "set particles before S-matrices");
+  for (int k = 0; k < nproto; ++k)
+    if (proto_off[k + 1] < proto_off[k] || proto_off[0] != 0)
+      return fail(h, EMS_ERR_ARG, "prototype offsets must increase from 0");
+  if (!finite_all(S_proto, 2 * (size_t)proto_off[nproto]))
+    return fail(h, EMS_ERR_NUMERIC, "non-finite prototype entry");
+  std::vector<int64_t> soff(h->n + 1, 0);
+  for (int i = 0; i < h->n; ++i) {
+    const int64_t K = 4 * h->p[i] + 2;
+    if (which[i] < 0 || which[i] >= nproto)
+      return fail(h, EMS_ERR_ARG, "prototype index out of range");
+    if (proto_off[which[i] + 1] - proto_off[which[i]] != K * K)
+      return fail(h, EMS_ERR_ARG, "prototype size does not match the particle's (4p+2)^2");
+    if (!std::isfinite(theta0[i])) return fail(h, EMS_ERR_NUMERIC, "non-finite orientation");
+    soff[i + 1] = soff[i] + K * K;
+  }
+  // S_m = D S D^H, D = diag(e^{-i n theta}) over [alpha_{-p..p}, beta_{-p..p}]
+  h->S_host.resize((size_t)soff[h->n]);
+  std::vector<cd> d;
+  for (int i = 0; i < h->n; ++i) {
+    const int pm = h->p[i], N = 2 * pm + 1, K = 2 * N;
+    d.resize(K);
+    for (int r = 0; r < K; ++r) d[r] = std::polar(1.0, -(double)((r % N) - pm) * theta0[i]);
+    const double *src = S_proto + 2 * proto_off[which[i]];
+    cd *dst = h->S_host.data() + soff[i];
+    for (int r = 0; r < K; ++r)
+      for (int c = 0; c < K; ++c) {
+        const size_t e = (size_t)r * K + c;
+        dst[e] = d[r] * cd(src[2 * e], src[2 * e + 1]) * std::conj(d[c]);
+      }
+  }
+  h->S_off = soff;
+  h->have_s = true;
+  h->built = false;
+  return EMS_OK;
+}
+
 int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double *S_out) {
   if (!m || !S_out || !(a > 0) || p < 0 || (bc != 0 && bc != 1)) return EMS_ERR_ARG;
   std::vector<cd> S;

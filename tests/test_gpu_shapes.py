@@ -249,3 +249,34 @@ def test_pear_and_starfish_match_oracle():
         e = np.abs(Sg[i] - So).max() / np.abs(So).max()
         print("kind", kind[i], "bc", bc[i], "p", p[i], e, flush=True)
         assert e <= TOL
+
+
+def test_rotated_prototypes_match_generated_matrices():
+    # the paper's use: a few prototype shapes, copies at any orientation
+    # (Section 3.3).  Operator on rotated prototypes (generated at theta0 = 0)
+    # against the operator on matrices generated for each turned particle.
+    n = 12
+    rng = np.random.default_rng(4)
+    xy = np.stack([np.arange(n) * 2.2, -1.5 - (np.arange(n) % 3) * 1.6], 1)
+    kind = np.array([3, 4] * (n // 2), np.int32)
+    a = np.where(kind == 3, 0.6, 0.55)
+    R = 1.25 * a
+    th = rng.uniform(0.0, 2 * np.pi, n)
+    bc = np.array([0, 0, 1, 1] * (n // 4), np.int32)
+    p = np.full(n, 12, np.int32)
+    media = E.make_media(W.HOST, W.SUBSTRATE, 8.0)
+    op_gen = E.Operator(xy, R, p, media, bc=bc)
+    op_gen.set_smatrices(op_gen.unpack_smatrices(op_gen.shape_smatrices(kind, a, th, bc)))
+    op_gen.build()
+    # prototypes: (pear, rigid), (starfish, rigid), (pear, free), (starfish, free)
+    proto_op = E.Operator(xy[:4], R[:4], p[:4], media, bc=bc[:4])
+    pk, pbc = np.array([3, 4, 3, 4], np.int32), np.array([0, 0, 1, 1], np.int32)
+    protos = proto_op.unpack_smatrices(proto_op.shape_smatrices(pk, a[:4], 0.0, pbc))
+    which = np.array([0, 1, 2, 3] * (n // 4), np.int32)
+    op_rot = E.Operator(xy, R, p, media, bc=bc)
+    op_rot.set_smatrices_rotated(protos, which, th)
+    op_rot.build()
+    x = to_gpu(W.random_coeffs(op_gen.n * 2 * 25, seed=12))
+    e = rel(to_np(op_rot.apply(x)), to_np(op_gen.apply(x)))
+    print("rotated prototypes vs generated", e, flush=True)
+    assert e <= 1e-12

@@ -151,3 +151,33 @@ def test_node_rule_integrates_lemma_high_order(case):
                 ex = special.hankel1(n, k * r) * np.exp(1j * n * th)
                 bound = 1e-12 * abs(ex) + 64 * eps * np.sum(np.abs(terms))
                 assert abs(val - ex) <= bound, (k, Xv, Y, n, abs(val - ex) / bound)
+
+
+def test_rotated_prototypes_validation_without_gpu():
+    import ctypes
+    lib = E.lib()
+    h = ctypes.c_void_p()
+    assert lib.ems_create(ctypes.byref(h)) == 0
+    m = E.make_media((2, 1, 1), (4, 2, 1.5), 4.0)
+    assert lib.ems_set_media(h, ctypes.byref(m)) == 0
+    xy = np.array([[0.0, -2.0], [3.0, -2.0], [6.0, -2.0]])
+    R = np.full(3, 0.4)
+    p = np.array([3, 3, 2], dtype=np.int32)
+    assert lib.ems_set_particles(h, 3, xy.ctypes.data, R.ctypes.data, p.ctypes.data) == 0
+    protos = np.zeros(14 * 14 + 10 * 10, complex)           # orders 3 and 2
+    off = np.array([0, 196, 296], dtype=np.int64)
+    th = np.array([0.1, 0.2, 0.3])
+    ok = np.array([0, 0, 1], dtype=np.int32)
+    assert lib.ems_set_smatrices_rotated(h, 2, protos.ctypes.data, off.ctypes.data,
+                                         ok.ctypes.data, th.ctypes.data) == 0
+    wrong_size = np.array([0, 1, 1], dtype=np.int32)          # order-2 prototype on p = 3
+    assert lib.ems_set_smatrices_rotated(h, 2, protos.ctypes.data, off.ctypes.data,
+                                         wrong_size.ctypes.data, th.ctypes.data) == -1
+    assert b"prototype size" in lib.ems_last_error(h)
+    out_of_range = np.array([0, 0, 2], dtype=np.int32)
+    assert lib.ems_set_smatrices_rotated(h, 2, protos.ctypes.data, off.ctypes.data,
+                                         out_of_range.ctypes.data, th.ctypes.data) == -1
+    nan_th = np.array([0.1, np.nan, 0.3])
+    assert lib.ems_set_smatrices_rotated(h, 2, protos.ctypes.data, off.ctypes.data,
+                                         ok.ctypes.data, nan_th.ctypes.data) == -6
+    lib.ems_destroy(h)
