@@ -146,7 +146,8 @@ __device__ __forceinline__ double2 source(const ShapeArgs &g, int m, int j, int 
   return z;
 }
 
-// Collocation matrix A: thread per (collocation point i, source j); rows
+// Collocation matrix A: thread per (collocation point i, source j), H_0 and
+// H_1 from the device library's Bessel functions of order 0 and 1; rows
 // comp * N + i (comp 0, 1 of u or sigma.nu), columns w * N + j (w 0: the
 // compressional monopole, w 1: the shear one).  For f = H_0(k rho) about the
 // source, grad f = -k H_1 e and Hess f = -k^2 H_0 e e^T + (k H_1 / rho)(2 e e^T - I),
@@ -171,9 +172,8 @@ __global__ __launch_bounds__(256) void mfs_matrix_kernel(ShapeArgs g, int i0, in
   double2 *Wm = W + (int64_t)mloc * mstride;
   for (int w = 0; w < 2; ++w) {
     const double k = w == 0 ? kp : ks;
-    double J[2], Y0, Y1;
-    bessel_jy(k * rho, 1, J, Y0, Y1);
-    const double2 H0 = make_double2(J[0], Y0), H1 = make_double2(J[1], Y1);
+    const double z = k * rho;
+    const double2 H0 = make_double2(j0(z), y0(z)), H1 = make_double2(j1(z), y1(z));
     const double2 gx = cscale(H1, -k * ex), gy = cscale(H1, -k * ey);
     const double2 c1 = cscale(H0, -k * k), c2 = cscale(H1, k / rho);
     const double2 hxx = cadd(cscale(c1, ex * ex), cscale(c2, 2.0 * ex * ex - 1.0));
