@@ -154,11 +154,13 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
 //   sum_j amp_w(j) e^{i xi_j x_m + s_w y_m} (i (xi_j - s_w)/k_w)^n  (Jacobi-Anger).
 // The powers are node quantities: point_pow_kernel tabulates them once per
 // call, V [q][2][2 pmax + 1] (negative orders as the reciprocal of the
-// positive power).  point_local_kernel: a block holds G particles of L lanes
-// (lane = wave, order); per tile of kPtTile nodes the powers and the G x 2
-// exponentials go to LDS once and serve every particle of the block.
+// positive power).  point_local_kernel: a block holds G groups of L lanes
+// (lane = wave, order), each lane serving kPtR particles; per tile of kPtTile
+// nodes the powers and the G kPtR x 2 exponentials go to LDS once, and a
+// lane's power read serves its kPtR particles.
 constexpr int kPtTile = 32;
 constexpr int kPtLanes = 512;
+constexpr int kPtR = 2;
 __global__ void point_pow_kernel(int q, int pmax, const double2 *__restrict__ nd, double kp,
                                  double ks, double2 *__restrict__ V) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -186,31 +188,42 @@ __global__ __launch_bounds__(kPtLanes) void point_local_kernel(
     const double2 *__restrict__ amp, const double2 *__restrict__ V, double2 *__restrict__ c,
     int64_t ncoef) {
   __shared__ double2 sv[2 * kPtTile * kMaxModes];
-  __shared__ double2 se[(kPtLanes / 64) * 2 * kPtTile];
+  __shared__ double2 se[(kPtLanes / 64) * kPtR * 2 * kPtTile];
   const int G = kPtLanes / L;
   const int g = threadIdx.x / L, lane = threadIdx.x % L;
-  const int m = blockIdx.x * G + g, r = blockIdx.y;
+  const int mb = blockIdx.x * G * kPtR, r = blockIdx.y;
   const int NP = 2 * pmax + 1;
-  const int pm = m < n ? p[m] : 0;
-  const int N = 2 * pm + 1;
-  const bool active = m < n && lane < 2 * N;
-  const int wave = lane < N ? 0 : 1;
-  const int col = (wave ? lane - N : lane) - pm + pmax;   // order index into V
+  // the kPtR particles of a lane: mb + rr G + g; they share the lane's order
+  // only when their orders agree, so each keeps its own (wave, column)
+  int mm[kPtR], colr[kPtR], wv[kPtR];
+  bool act[kPtR];
+#pragma unroll
+  for (int rr = 0; rr < kPtR; ++rr) {
+    mm[rr] = mb + rr * G + g;
+    const int pm = mm[rr] < n ? p[mm[rr]] : 0;
+    const int N = 2 * pm + 1;
+    act[rr] = mm[rr] < n && lane < 2 * N;
+    wv[rr] = lane < N ? 0 : 1;
+    colr[rr] = (wv[rr] ? lane - N : lane) - pm + pmax;
+  }
+  const bool same = kPtR == 1 || (wv[0] == wv[kPtR - 1] && colr[0] == colr[kPtR - 1]);
   const double2 *A = amp + (int64_t)r * q * 2;
-  double2 acc = make_double2(0.0, 0.0);
+  double2 acc[kPtR];
+#pragma unroll
+  for (int rr = 0; rr < kPtR; ++rr) acc[rr] = make_double2(0.0, 0.0);
   for (int j0 = 0; j0 < q; j0 += kPtTile) {
     const int tn = min(kPtTile, q - j0);
     // powers of the tile: contiguous [t][w][order] block of V
     for (int e = threadIdx.x; e < tn * 2 * NP; e += kPtLanes) sv[e] = V[(int64_t)j0 * 2 * NP + e];
     // exponentials amp_w(j) e^{i xi x_m + s_w y_m}, one per (particle, wave, node)
-    for (int e = threadIdx.x; e < G * 2 * kPtTile; e += kPtLanes) {
+    for (int e = threadIdx.x; e < G * kPtR * 2 * kPtTile; e += kPtLanes) {
       const int gg = e / (2 * kPtTile), rem = e % (2 * kPtTile), w = rem / kPtTile,
                 tt = rem % kPtTile;
-      const int mm = blockIdx.x * G + gg;
+      const int mp = mb + gg;   // block particle gg = rr G + g
       double2 v = make_double2(0.0, 0.0);
-      if (mm < n && tt < tn) {
+      if (mp < n && tt < tn) {
         const int j = j0 + tt;
-        const double x = xy[2 * mm], y = xy[2 * mm + 1];
+        const double x = xy[2 * mp], y = xy[2 * mp + 1];
         const double2 xi = nd[3 * (int64_t)j], s = nd[3 * (int64_t)j + 1 + w];
         v = cmul(A[2 * (int64_t)j + w],
                  cexp(make_double2(-xi.y * x + s.x * y, xi.x * x + s.y * y)));
@@ -218,14 +231,33 @@ __global__ __launch_bounds__(kPtLanes) void point_local_kernel(
       se[e] = v;
     }
     __syncthreads();
-    if (active) {
-      const double2 *ev = se + (g * 2 + wave) * kPtTile;
-      const double2 *pv = sv + wave * NP + col;
-      for (int t = 0; t < tn; ++t) cfma(acc, ev[t], pv[t * 2 * NP]);
+    // equal (wave, column) means equal orders, hence the same activity
+    if (same) {
+      if (act[0]) {
+        // one power read per node for all kPtR particles of the lane
+        const double2 *pv = sv + wv[0] * NP + colr[0];
+        for (int t = 0; t < tn; ++t) {
+          const double2 vp = pv[t * 2 * NP];
+#pragma unroll
+          for (int rr = 0; rr < kPtR; ++rr)
+            cfma(acc[rr], se[((rr * G + g) * 2 + wv[0]) * kPtTile + t], vp);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int rr = 0; rr < kPtR; ++rr) {
+        if (act[rr]) {
+          const double2 *ev = se + ((rr * G + g) * 2 + wv[rr]) * kPtTile;
+          const double2 *pv = sv + wv[rr] * NP + colr[rr];
+          for (int t = 0; t < tn; ++t) cfma(acc[rr], ev[t], pv[t * 2 * NP]);
+        }
+      }
     }
     __syncthreads();
   }
-  if (active) c[(int64_t)r * ncoef + off[m] + lane] = acc;
+#pragma unroll
+  for (int rr = 0; rr < kPtR; ++rr)
+    if (act[rr]) c[(int64_t)r * ncoef + off[mm[rr]] + lane] = acc[rr];
 }
 
 hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, const double2 *amp,
@@ -234,7 +266,8 @@ hipError_t launch_point_local(const ems_handle *h, int q, const double2 *nd, con
   hipLaunchKernelGGL(point_pow_kernel, dim3((2 * q + 255) / 256), dim3(256), 0, st, q, pmax, nd,
                      h->md.kp, h->md.ks, V);
   const int L = part_threads(h), G = kPtLanes / L;
-  hipLaunchKernelGGL(point_local_kernel, dim3((h->n + G - 1) / G, nrhs), dim3(kPtLanes), 0, st,
+  hipLaunchKernelGGL(point_local_kernel, dim3((h->n + G * kPtR - 1) / (G * kPtR), nrhs),
+                     dim3(kPtLanes), 0, st,
                      h->n, q, pmax, L, h->d_xy, h->d_p, h->d_off, nd, amp, V, c, h->ncoef);
   return hipGetLastError();
 }
