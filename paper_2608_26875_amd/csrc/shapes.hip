@@ -32,7 +32,7 @@ constexpr int kLuLanes = 512;    // one row of the working matrix per lane
 constexpr int kRC = 21;          // right-hand sides per back-substitution pass (no spills)
 constexpr int kCC = 192;         // trailing columns per LDS chunk of U12 (48 KB)
 constexpr int kTG = 8;           // trailing columns per pipelined group
-constexpr int kBD = 4;           // back-substitution rows loaded ahead
+constexpr int kBB = 16;          // back-substitution rows per block (n2 is a multiple)
 constexpr int kMaxJ = kMaxP + 3; // J_0 .. J_{p+2}
 
 __device__ __forceinline__ double2 cinv(double2 d) {
@@ -470,14 +470,18 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
   }
 }
 
-// Back substitution U X = Y on the right-hand-side columns, in place; lane r
-// holds row r of kRC columns in registers, x_k is broadcast through LDS
-// (double-buffered: one barrier per row).
+// Back substitution U X = Y on the right-hand-side columns, in place, by
+// blocks of kBB rows from the bottom: lane r holds row r of kRC columns in
+// registers; the rows of a block stage their values and the block's diagonal
+// U in LDS, lane q < kRC solves the small triangular system for column q,
+// and every row above subtracts the block's contribution (kBB independent
+// loads of its U entries).  Three barriers per block instead of one per row.
 __global__ __launch_bounds__(kLuLanes) void mfs_backsolve_kernel(double2 *__restrict__ W, int n2,
                                                                 int64_t mstride,
                                                                 const int *__restrict__ p,
                                                                 int i0) {
-  __shared__ double2 xs[2][kRC];
+  __shared__ double2 Ub[kBB][kBB];
+  __shared__ double2 yb[kBB][kRC];
   const int mloc = blockIdx.x;
   double2 *A = W + (int64_t)mloc * mstride;
   const int nr = 2 * (2 * p[i0 + mloc] + 1);
@@ -488,39 +492,44 @@ __global__ __launch_bounds__(kLuLanes) void mfs_backsolve_kernel(double2 *__rest
 #pragma unroll
     for (int q = 0; q < kRC; ++q)
       y[q] = (r < n2 && q < nc) ? A[(int64_t)(n2 + c0 + q) * n2 + r] : make_double2(0.0, 0.0);
-    // column entries U[r][k] loaded kBD rows ahead (n2 is a multiple of kBD)
-    double2 ur[kBD];
+    for (int k0 = n2 - kBB; k0 >= 0; k0 -= kBB) {   // n2 is a multiple of kBB
+      const bool blk = r >= k0 && r < k0 + kBB;
+      if (blk) {
 #pragma unroll
-    for (int d = 0; d < kBD; ++d)
-      ur[d] = r < n2 ? A[(int64_t)(n2 - 1 - d) * n2 + r] : make_double2(0.0, 0.0);
-    for (int kb = n2 - 1; kb >= 0; kb -= kBD) {
-#pragma unroll
-      for (int d = 0; d < kBD; ++d) {
-        const int k = kb - d;
-        const double2 u = ur[d];   // U[r][k]; the diagonal for lane k
-        if (k - kBD >= 0 && r < n2) ur[d] = A[(int64_t)(k - kBD) * n2 + r];
-        double2 *buf = xs[k & 1];
-        if (r == k) {
-          const double2 di = cinv(u);
-#pragma unroll
-          for (int q = 0; q < kRC; ++q) {
-            y[q] = cmul(y[q], di);
-            buf[q] = y[q];
-          }
-        }
-        __syncthreads();
-        if (r < k) {
-#pragma unroll
-          for (int q = 0; q < kRC; ++q) y[q] = csub(y[q], cmul(u, buf[q]));
+        for (int q = 0; q < kRC; ++q) yb[r - k0][q] = y[q];
+      }
+      if (r < kBB * kBB) {
+        const int i = r % kBB, j = r / kBB;
+        Ub[i][j] = A[(int64_t)(k0 + j) * n2 + k0 + i];
+      }
+      __syncthreads();
+      if (r < nc) {
+        for (int i = kBB - 1; i >= 0; --i) {
+          double2 s = yb[i][r];
+          for (int j = i + 1; j < kBB; ++j) s = csub(s, cmul(Ub[i][j], yb[j][r]));
+          yb[i][r] = cmul(s, cinv(Ub[i][i]));
         }
       }
+      __syncthreads();
+      if (blk) {
+#pragma unroll
+        for (int q = 0; q < kRC; ++q) y[q] = yb[r - k0][q];
+      } else if (r < k0) {
+        double2 u[kBB];
+#pragma unroll
+        for (int j = 0; j < kBB; ++j) u[j] = A[(int64_t)(k0 + j) * n2 + r];
+#pragma unroll
+        for (int j = 0; j < kBB; ++j)
+#pragma unroll
+          for (int q = 0; q < kRC; ++q) y[q] = csub(y[q], cmul(u[j], yb[j][q]));
+      }
+      __syncthreads();
     }
     if (r < n2) {
 #pragma unroll
       for (int q = 0; q < kRC; ++q)
         if (q < nc) A[(int64_t)(n2 + c0 + q) * n2 + r] = y[q];
     }
-    __syncthreads();
   }
 }
 
