@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kNB = 16;          // LU panel width
 constexpr int kLuLanes = 512;    // one row of the working matrix per lane
-constexpr int kRC = 21;          // right-hand sides per back-substitution pass (no spills)
+constexpr int kRC = 31;          // right-hand sides per back-substitution pass (62 at p = 15)
 constexpr int kCC = 192;         // trailing columns per LDS chunk of U12 (48 KB)
 constexpr int kTG = 8;           // trailing columns per pipelined group
 constexpr int kBB = 16;          // back-substitution rows per block (n2 is a multiple)
