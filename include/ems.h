@@ -10,8 +10,8 @@
  * vector crossing this ABI is complex128, interleaved (re, im), laid out as
  * [nrhs][sum_m 2(2 p_m + 1)], and per particle [alpha_{-p..p}, beta_{-p..p}]
  * (outgoing coefficients of grad H_n(kp r) e^{i n th} and
- * grad^perp H_n(ks r) e^{i n th}, Section 3.1; truncation Z_p, Section 3.1
- * remark; block order of the multiple-scattering system, Section 3.2).
+ * grad^perp H_n(ks r) e^{i n th}, Section 4.1; truncation Z_p, Section 4.1
+ * remark; block order of the multiple-scattering system, Section 4.2).
  *
  * Ownership: the caller owns every buffer passed in; "host" pointers are read
  * (or written) during the call only; "device" pointers must stay valid until
@@ -58,7 +58,7 @@ typedef struct {
   double omega;
 } ems_media;
 
-/* Sommerfeld quadrature on the xi axis (Section 4.1).
+/* Sommerfeld quadrature on the xi axis (Section 5.1).
  *  kind 0: the paper's hyperbolic-tangent contour xi(t) = t - i delta tanh t,
  *          t in [-t_max, t_max], trapezoidal rule with q nodes;
  *  kind 1: real axis; around the branch points (+-kp, +-ks of both layers)
@@ -96,7 +96,7 @@ typedef struct {
  *          d = (sin a, cos a) in the paper frame, d e^{i kp d.x};
  *  wave 1: SV from the particle side, d_perp e^{i ks d.x}, d_perp = (-d2, d1);
  *  wave 2: P sent from the substrate, d = (sin a, -cos a), d e^{i kpb d.x}
- *          (Section 6.3's plane-wave setup: the particles see the wave
+ *          (Section 7.3's plane-wave setup: the particles see the wave
  *          transmitted through the interface);
  *  wave 3: SV sent from the substrate, d_perp e^{i ksb d.x}. */
 typedef struct {
@@ -104,7 +104,7 @@ typedef struct {
   double angle;
 } ems_plane_wave;
 
-/* Elastic point source in the substrate (Section 2.3): position (x0, y0)
+/* Elastic point source in the substrate (Section 3.2): position (x0, y0)
  * with y0 > 0 (paper frame), polarisation (alpha1, alpha2); the incident
  * field is Phi(x, x0) alpha with Phi the substrate's Green's tensor
  * 1/(rho omega^2) (ks^2 g_ks I + grad grad^T (g_ks - g_kp)), g_k = (i/4) H_0(k r). */
@@ -144,8 +144,8 @@ typedef struct {
 } ems_build_info;
 
 /* Parts of the operator selected by ems_apply's flags. */
-#define EMS_PART_FREE 1      /* T_free: Graf translations (Section 3.2)          */
-#define EMS_PART_REFL 2      /* T_refl: Sommerfeld reflected part (Section 4)    */
+#define EMS_PART_FREE 1      /* T_free: Graf translations (Section 4.2)          */
+#define EMS_PART_REFL 2      /* T_refl: Sommerfeld reflected part (Section 5)    */
 #define EMS_PART_S 4         /* multiply by the particle S-matrices              */
 #define EMS_PART_IDENTITY 8  /* y = x - (...); requires EMS_PART_S               */
 #define EMS_APPLY_ALL 15
@@ -159,21 +159,21 @@ const char *ems_last_error(const ems_handle *h);
 /* Materials and frequency (Section 2).  Host data. */
 int ems_set_media(ems_handle *h, const ems_media *m);
 
-/* Particles (Section 2, well-separated enclosing disks, Section 3.3): n centres
+/* Particles (Section 2, well-separated enclosing disks, Section 4.3): n centres
  * xy[n][2] in the paper frame, enclosing radii R[n], truncation orders
  * p[n] in [1, 16].  Host data, copied.  Validation at ems_build:
  * |x_m - x_l| > R_m + R_l and y_m + R_m < 0, else EMS_ERR_GEOMETRY. */
 int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *R,
                       const int32_t *p);
 
-/* Per-particle scattering matrices (Section 3.1 and 3.3), host data, copied:
+/* Per-particle scattering matrices (Section 4.1 and 4.3), host data, copied:
  * S + 2*offsets[m] doubles hold particle m's (4p_m+2)^2 complex matrix,
  * row-major, rows and columns in the [alpha, beta] / [a, b] order above.
  * offsets has n+1 entries counted in complex elements. */
 int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets);
 
 /* Per-particle scattering matrices as turned copies of a few prototypes
- * (Section 3.3: finitely many distinct shapes, placed at any orientation):
+ * (Section 4.3: finitely many distinct shapes, placed at any orientation):
  * particle m gets S_m = D S_{which[m]} D^H with D = diag(e^{-i n theta0[m]})
  * over [alpha_{-p..p}, beta_{-p..p}] (the coefficients of a shape turned by
  * theta0 counter-clockwise).  Host data, read during the call: nproto
@@ -185,17 +185,17 @@ int ems_set_smatrices_rotated(ems_handle *h, int32_t nproto, const double *S_pro
                               const int64_t *proto_off, const int32_t *which,
                               const double *theta0);
 
-/* Closed-form scattering matrix of a disk of radius a (Section 3.1: boundary
+/* Closed-form scattering matrix of a disk of radius a (Section 4.1: boundary
  * condition imposed mode by mode; bc 0 rigid u = 0, bc 1 traction-free).
  * Writes (4p+2)^2 complex128 row-major into host memory S_out. */
 int ems_smatrix_disk(const ems_media *m, double a, int32_t p, int32_t bc, double *S_out);
 
-/* Scattering matrices of non-circular particles (Section 3.3), generated on
+/* Scattering matrices of non-circular particles (Section 4.3), generated on
  * the GPU for the handle's particles (after ems_set_media and
  * ems_set_particles; orders p from the particles).  Host arrays, one entry
  * per particle: kind 0 circle of radius a, 1 ellipse with semi-axes a and
  * a/2, 2 five-arm star r(t) = a (1 + 0.3 cos 5t), and the paper's family
- * r(t) = a1 + a2 cos(a3 t) of Section 6 with a1 = a, a2 = a/4: 3 pear
+ * r(t) = a1 + a2 cos(a3 t) of Section 7 with a1 = a, a2 = a/4: 3 pear
  * (a3 = 3), 4 starfish (a3 = 5); each about the particle centre and turned
  * by theta0 (radians, counter-clockwise in the paper frame); bc 0 rigid
  * (u = 0), 1 traction-free.  The shape must lie inside the enclosing radius
@@ -217,7 +217,7 @@ int ems_smatrix_shapes(ems_handle *h, const int32_t *kind, const double *a, cons
                        const int32_t *bc, int32_t npts, double delta, void *S_out,
                        ems_stream_t stream);
 
-/* Sommerfeld quadrature choice (Section 4.1); default kind 1 when never set. */
+/* Sommerfeld quadrature choice (Section 5.1); default kind 1 when never set. */
 int ems_set_sommerfeld(ems_handle *h, const ems_sommerfeld *s);
 
 /* Host-only: the node table that ems_build would use for this cloud (same
@@ -233,7 +233,7 @@ int ems_sommerfeld_nodes(const ems_media *m, const ems_sommerfeld *s, int32_t n,
 
 /* Host-only: the depth truncation ems_build applies to the tabulated
  * Sommerfeld contractions of this cloud (rule: ems_sommerfeld.depth_cut;
- * Section 4.1 places t_max by the same decay bound).  q must be the node
+ * Section 5.1 places t_max by the same decay bound).  q must be the node
  * count ems_sommerfeld_nodes reports.  Outputs, caller-owned host arrays:
  * perm_out[n] = particle indices by increasing depth; kcut_out[2 q] = for
  * wave w (0 P, 1 S) and node j, entry w q + j: how many particles of that
@@ -246,11 +246,11 @@ int ems_sommerfeld_depth_cuts(const ems_media *m, const ems_sommerfeld *s, int32
                               int32_t *kcut_out, int32_t *range_out, double *kept_out);
 
 /* Host-only: the 2x2 reflection R(xi) of upgoing P / S potentials at the
- * welded interface (Section 2.2, the 4x4 continuity system per Fourier mode,
+ * welded interface (Section 3.2, the 4x4 continuity system per Fourier mode,
  * density kept), row-major complex128 into R_out[8]. */
 int ems_reflection(const ems_media *m, double xi_re, double xi_im, double *R_out);
 
-/* Free-space part (Section 3.2 gives the Graf translations and names the
+/* Free-space part (Section 4.2 gives the Graf translations and names the
  * FMM; the library builds a uniform-quadtree Graf FMM).
  *  mode 0: automatic (FMM when n > 1500), 1: direct sum over all pairs,
  *  2: FMM.  leaf: target particles per leaf box (0 = 6); top_boxes: the
@@ -267,7 +267,7 @@ typedef struct {
 int ems_set_fmm(ems_handle *h, const ems_fmm *f);
 
 /* Validate, build the node table and the per-node 2x2 reflection R(xi_j)
- * (the 4x4 interface system of Section 2.2 solved per node), pack the S
+ * (the 4x4 interface system of Section 3.2 solved per node), pack the S
  * store, allocate device workspace.  Synchronous. */
 int ems_build(ems_handle *h, ems_stream_t stream);
 int ems_get_info(const ems_handle *h, ems_build_info *out);
@@ -275,8 +275,8 @@ int ems_get_info(const ems_handle *h, ems_build_info *out);
 /* Operator apply on device buffers x, y (complex128, [nrhs][n_coeff], may not
  * alias): with flags = EMS_APPLY_ALL,
  *   y_m = x_m - S_m ( (T_free x)_m + (T_refl x)_m )
- * the Schur-complement operator of Section 4.2 (free part: Section 3.2,
- * reflected part: Sections 4.3-4.4).  Fewer part bits give the pieces
+ * the Schur-complement operator of Section 5.2 (free part: Section 4.2,
+ * reflected part: Sections 5.3-5.4).  Fewer part bits give the pieces
  * (e.g. EMS_PART_REFL alone returns the raw reflected local coefficients).
  * EMS_MIXED runs the contractions in FP32. */
 int ems_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
@@ -300,13 +300,13 @@ int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32
 
 /* Right-hand side S_m (a0^m, b0^m) of the S-preconditioned system (Section
  * 3.2) for nrhs plane waves, into device memory rhs [nrhs][n_coeff]: the
- * local expansions of the background field in the host (Section 6.3,
+ * local expansions of the background field in the host (Section 7.3,
  * (bplan)): incident + interface-reflected waves for waves 0 and 1, the
  * transmitted waves for waves 2 and 3. */
 int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void *rhs,
                  ems_stream_t stream);
 
-/* GMRES on the operator (Sections 3.2 and 4.2): x0 = 0, nrhs independent
+/* GMRES on the operator (Sections 4.2 and 5.2): x0 = 0, nrhs independent
  * systems advanced in lock-step.  b, x device memory [nrhs][n_coeff].
  * precision 0: every apply in FP64.  precision 1 (mixed): iterative
  * refinement, i.e. an FP64 outer residual b - A x and update x += d, with d
@@ -323,7 +323,7 @@ int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_sol
 int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
                       const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream);
 
-/* Scattered displacement at npts points (Section 4, coupled
+/* Scattered displacement at npts points (Section 5, coupled
  * representation).  Host points (y < 0, outside every enclosing disk):
  * outgoing particle fields plus the reflected Sommerfeld field; substrate
  * points (y > 0): the particles' field transmitted through the interface
@@ -334,9 +334,9 @@ int ems_eval_scattered(ems_handle *h, const void *gamma, int32_t nrhs, int32_t n
                        const double *pts, void *u, ems_stream_t stream);
 
 /* Right-hand side of the S-preconditioned system for nrhs point sources
- * (Section 2.3; the point-source workload of Section 6): S_m times the local
+ * (Section 3.2; the point-source workload of Section 7): S_m times the local
  * expansions, about every particle, of the source field transmitted into
- * the host, formed by Jacobi-Anger (Section 4.3, (ja)) on a Sommerfeld node
+ * the host, formed by Jacobi-Anger (Section 5.3, (ja)) on a Sommerfeld node
  * rule laid out for the source-to-particle pairs.  rhs device
  * [nrhs][n_coeff].  Errors: EMS_ERR_GEOMETRY (y0 <= 0), EMS_ERR_ARG,
  * EMS_ERR_STATE, EMS_ERR_NUMERIC, EMS_ERR_HIP.  Synchronous. */
@@ -351,7 +351,7 @@ int ems_incident_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
 int ems_eval_background_point(ems_handle *h, const ems_point_source *src, int32_t nrhs,
                               int32_t npts, const double *pts, void *u, ems_stream_t stream);
 
-/* Background displacement of nrhs plane waves (no particles; Section 6.3,
+/* Background displacement of nrhs plane waves (no particles; Section 7.3,
  * (bplan)) at npts points of either layer: in the layer the wave is sent
  * from, incident + reflected; in the other layer, transmitted.  pts device
  * [npts][2] (y != 0), u device [nrhs][npts][2] complex128.  The total field
@@ -370,7 +370,7 @@ int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_t nrhs, int
 /* Gradient of a receiver misfit J = 1/2 sum_r sum_rcv |u_r(x_rcv) - u_obs|^2
  * with respect to the particle centres and the substrate's Lame parameters
  * (adjoint method; the derivative identities of the translation, plane-wave
- * and interface operators of Sections 3-4 applied to the Schur system).
+ * and interface operators of Sections 4-5 applied to the Schur system).
  * Inputs, all for the same nrhs plane waves `waves` (host array):
  *   gamma  device [nrhs][n_coeff]: solutions of A gamma = b (b from ems_incident),
  *   lam    device [nrhs][n_coeff]: solutions of A^H lam = F^H res

@@ -10,19 +10,19 @@ What it computes (paper frame: particles in y < 0, interface y = 0):
 
 * ``media``        wavenumbers (Section 2, Helmholtz split; density kept).
 * ``smatrix``      closed-form disk scattering matrices, rigid and
-                   traction-free (Section 3.1), and basis rotation (Section 3.3).
-* ``graf``         dense O(N^2) free-space translations (Section 3.2, Graf).
+                   traction-free (Section 4.1), and basis rotation (Section 4.3).
+* ``graf``         dense O(N^2) free-space translations (Section 4.2, Graf).
 * ``interface``    the per-node 2x2 P-SV reflection of the welded interface
-                   (Section 2.2, the 4x4 system solved per Fourier mode).
+                   (Section 3.2, the 4x4 system solved per Fourier mode).
 * ``sommerfeld``   the layered reflected part: multipole-to-Sommerfeld
-                   (Lemma, Section 4.4), reflection, Sommerfeld-to-local
-                   (Jacobi-Anger, Section 4.3), integrated by adaptive
+                   (Lemma, Section 5.4), reflection, Sommerfeld-to-local
+                   (Jacobi-Anger, Section 5.3), integrated by adaptive
                    Gauss-Kronrod quadrature on the real axis.
-* ``incident``     plane-wave right-hand side (Section 6.3).
+* ``incident``     plane-wave right-hand side (Section 7.3).
 * ``operator``     y = x - S (T_free + T_refl) x, the Schur-complement operator
-                   of Section 4.2, and its conjugate transpose.
+                   of Section 5.2, and its conjugate transpose.
 * ``gmres``        textbook GMRES (Saad-Schultz) with CGS2 Arnoldi.
-* ``field``        scattered displacement at receivers (Section 4, coupled
+* ``field``        scattered displacement at receivers (Section 5, coupled
                    representation).
 
 Parity unpinned: nothing in this package; each part is pinned by the tests in

@@ -1,15 +1,15 @@
-"""Scattered displacement (Section 4, coupled representation): host points
+"""Scattered displacement (Section 5, coupled representation): host points
 (y < 0) and, transmitted through the interface, substrate points (y > 0).
 
 u^sc(x) = sum_m sum_n alpha^m_n grad(H_n(kp r_m) e^{i n theta_m})
                   + beta^m_n grad^perp(H_n(ks r_m) e^{i n theta_m})
           + grad phi_R + grad^perp psi_R,
 with phi_R = int e^{i xi x + s_p y} RP(xi) dxi and psi_R likewise with RS, the
-reflected potentials of Section 4 (see ``sommerfeld``).
+reflected potentials of Section 5 (see ``sommerfeld``).
 
 Derivatives of v_n = Z_n(k r) e^{i n theta} (standard cylinder-function
 identities, the same structure as the density-to-coefficient formula of
-Section 3.3):
+Section 4.3):
   d_x v_n = (k/2)(v_{n-1} - v_{n+1}),  d_y v_n = (i k/2)(v_{n-1} + v_{n+1});
 grad^perp = (-d_y, d_x).
 """

@@ -1,4 +1,4 @@
-"""Textbook GMRES (Saad and Schultz 1986), the solver named in Sections 3.2 and 4.2.
+"""Textbook GMRES (Saad and Schultz 1986), the solver named in Sections 4.2 and 5.2.
 
 x0 = 0; Arnoldi with classical Gram-Schmidt applied twice; Givens rotations
 G = [[c, s], [-conj(s), conj(c)]] on the Hessenberg matrix; stop when the relative residual estimate

@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE ONLY: a plain dense computation for small clouds.
 
 Misfit J = 1/2 sum_r sum_rcv |u_r(x_rcv) - u_obs,r|^2 with u_r = F gamma_r,
-A gamma_r = b_r the Schur system of Sections 3.2 and 4.2 (A = I - S (T_free +
-T_refl), b = S a0 with a0 the background local coefficients, Section 6.3),
-F the scattered-field map (Section 4, coupled representation).  Parameters:
+A gamma_r = b_r the Schur system of Sections 4.2 and 5.2 (A = I - S (T_free +
+T_refl), b = S a0 with a0 the background local coefficients, Section 7.3),
+F the scattered-field map (Section 5, coupled representation).  Parameters:
 every centre coordinate and the substrate's (lambda_b, mu_b).  For each
 parameter theta the tangent gamma' = A^{-1} (b' - A' gamma) gives
   dJ/dtheta = Re sum_r res_r^H (F' gamma_r + F gamma'_r),
@@ -19,7 +19,7 @@ with every derivative taken from its definition:
     polar chain rule and Bessel's equation;
   * background coefficients: i xi0 and -+s on the down-/up-going plane waves,
     dR(xi0) for the reflected one.
-dR comes from differentiating the interface system M X = rhs of Section 2.2:
+dR comes from differentiating the interface system M X = rhs of Section 3.2:
 dX = -M^{-1} (dM) X, only the substrate columns depending on (lambda_b, mu_b)
 (explicitly and through s_pb, s_sb).
 """

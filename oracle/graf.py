@@ -1,4 +1,4 @@
-"""Dense free-space multiple-scattering translations (Section 3.2).
+"""Dense free-space multiple-scattering translations (Section 4.2).
 
 The incoming coefficients of particle m collect, from every other particle l,
 T^{ml} applied to (alpha^l, beta^l), with T^{ml} = diag(A, B):

@@ -1,7 +1,7 @@
-"""Plane-wave right-hand side (Section 6.3 and the preconditioned system of Section 3.2).
+"""Plane-wave right-hand side (Section 7.3 and the preconditioned system of Section 4.2).
 
 The background field in the host is the incident plane wave plus its
-interface reflection (Section 2: total = background + scattered; Section 6.3:
+interface reflection (Section 2: total = background + scattered; Section 7.3:
 reflected and transmitted fields of a plane wave are plane waves).  Waves are
 sent from the particle side towards the interface: paper-frame direction
 d = (sin th, cos th).  A P wave of unit displacement d e^{i kp d.x} is grad of
@@ -15,7 +15,7 @@ centre (x_m, y_m): e^{i xi x_m - s y_m} (i (xi + s)/k)^n; of e^{i xi x + s y}:
 e^{i xi x_m + s y_m} (i (xi - s)/k)^n.  The right-hand side of the
 S-preconditioned system is S_m (a0, b0) for every particle.
 
-Waves sent from the substrate (Section 6.3's own setup, (bplan)): direction
+Waves sent from the substrate (Section 7.3's own setup, (bplan)): direction
 (sin th, -cos th), unit displacement, potential A e^{i xi0 x + s_b y} with A =
 1/(i k_b), xi0 = k_b sin th; the host sees the transmitted potentials Td A
 (``interface.from_substrate``), the substrate the incident and reflected ones.
@@ -34,7 +34,7 @@ def _waves(m: Media, wave: int, angle: float):
     """(xi0, [(layer, kind, A, q)]) of the background field of one plane wave:
     potentials A e^{i xi0 x + q y}, layer 0 host (y < 0) / 1 substrate, kind 0
     P (grad) / 1 S (grad^perp).  Waves 0, 1 come from the host side (Section
-    6.3 reading: towards the interface, direction (sin th, cos th)); waves 2,
+    7.3 reading: towards the interface, direction (sin th, cos th)); waves 2,
     3 from the substrate (direction (sin th, -cos th)) and reach the
     particles transmitted."""
     k = (m.kp, m.ks, m.kpb, m.ksb)[wave]

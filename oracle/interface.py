@@ -1,6 +1,6 @@
 """Welded-interface reflection of plane-wave potentials, one Fourier mode at a time.
 
-Section 2.2: the Sommerfeld representation diagonalises the tangential
+Section 3.2: the Sommerfeld representation diagonalises the tangential
 variable, so continuity of displacement and traction T_y across y = 0 is
 imposed per mode xi (the paper's 4x4 system A_xi sigma = b_xi, written there
 with rho = 1 for densities on the interface).  The oracle writes the same four
@@ -92,7 +92,7 @@ def reflect_transmit(xi, m: Media, svals=None):
 
 
 def from_substrate(xi, m: Media, svals=None):
-    """(Td, Rb), each 2x2, for waves sent from the substrate (Section 6.3's
+    """(Td, Rb), each 2x2, for waves sent from the substrate (Section 7.3's
     plane-wave setup): a unit downgoing potential e^{i xi x + s_b y} (column
     0 P, column 1 S) meets the same four continuity conditions with the
     unknowns host downgoing (Td, e^{i xi x + s y}) and substrate upgoing (Rb,

@@ -1,7 +1,7 @@
-"""The multiple-scattering operator of the Schur-complement system (Section 4.2).
+"""The multiple-scattering operator of the Schur-complement system (Section 5.2).
 
-Section 3.2 gives the S-preconditioned free-space system (identity on the
-diagonal blocks, -S_m T^{ml} off it).  Section 4.2 eliminates the interface
+Section 4.2 gives the S-preconditioned free-space system (identity on the
+diagonal blocks, -S_m T^{ml} off it).  Section 5.2 eliminates the interface
 densities (A is block diagonal, inverted directly) and leaves
 [D - C A^{-1} B] gamma = rhs on the multipole unknowns only.  Applied to a
 coefficient vector x:

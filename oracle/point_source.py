@@ -1,4 +1,4 @@
-"""Point-source incidence (Section 2.3; the point-source workload of Section 6).
+"""Point-source incidence (Section 3.2; the point-source workload of Section 7).
 TEST INFRASTRUCTURE ONLY: nothing in the product imports this module.
 
 An elastic point source at x0 = (x0, y0), y0 > 0, in the substrate (the
@@ -23,7 +23,7 @@ The particles see u2.  Its Helmholtz split, per xi (grad -> (i xi, s)):
   P:  phi = -1/(rho omega^2) (i xi sigma_21 + s_p sigma_22) g~2_kp,
   S:  psi =  1/(rho omega^2) (s_s sigma_21 - i xi sigma_22) g~2_ks
 (u = grad phi + grad^perp psi, grad^perp = (-d_y, d_x)), and Jacobi-Anger
-(Section 4.3, (ja)) turns e^{i xi x + s y} into local coefficients about
+(Section 5.3, (ja)) turns e^{i xi x + s y} into local coefficients about
 (x_m, y_m): e^{i xi x_m + s y_m} (i (xi - s)/k)^n.
 """
 from __future__ import annotations

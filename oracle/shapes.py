@@ -1,11 +1,11 @@
-"""Scattering matrices of non-circular particles (Section 3.3).
+"""Scattering matrices of non-circular particles (Section 4.3).
 TEST INFRASTRUCTURE ONLY: nothing in the product imports this module.
 
 S maps the incoming coefficients (a_n, b_n) of grad(J_n(kp r) e^{i n th}) and
 grad^perp(J_n(ks r) e^{i n th}) about the enclosing-disk centre to the outgoing
 coefficients (alpha_n, beta_n) of grad(H_n(kp r) e^{i n th}) and
-grad^perp(H_n(ks r) e^{i n th}) of the field the particle scatters (Section 3.1
-definition, extended to any shape in Section 3.3).
+grad^perp(H_n(ks r) e^{i n th}) of the field the particle scatters (Section 4.1
+definition, extended to any shape in Section 4.3).
 
 Discretisation (the paper solves a boundary integral equation by a Nystrom
 rule; here, method of fundamental solutions): the scattered field is a sum of
@@ -22,7 +22,7 @@ so alpha_l = sum_j c_j J_l(kp |y_j|) e^{-i l th_j} and beta_l likewise with
 
 Shapes (paper frame, about the centre, turned by theta0): 0 circle of radius a;
 1 ellipse with semi-axes a and a/2; 2 five-arm star r(t) = a (1 + 0.3 cos 5t);
-and the paper's own family r(t) = a1 + a2 cos(a3 t) (Section 6) with
+and the paper's own family r(t) = a1 + a2 cos(a3 t) (Section 7) with
 a2 = a1/4: 3 pear (a3 = 3), 4 starfish (a3 = 5), a = a1.
 """
 from __future__ import annotations

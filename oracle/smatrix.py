@@ -1,6 +1,6 @@
 """Closed-form scattering matrices of a disk and basis rotation.
 
-Section 3.1: the incoming field near a particle is sum_n a_n grad u_n^{kp} +
+Section 4.1: the incoming field near a particle is sum_n a_n grad u_n^{kp} +
 b_n grad^perp u_n^{ks} with u_n^k = J_n(k r) e^{i n theta}; the scattered field
 is sum_n alpha_n grad v_n^{kp} + beta_n grad^perp v_n^{ks} with
 v_n^k = H_n^{(1)}(k r) e^{i n theta}; S maps (a, b) to (alpha, beta).  For a disk
@@ -14,7 +14,7 @@ Polar components, with f(r) e^{i n theta}:
 Rigid (u = 0 on r = a): M_Z = [[kp Z_n'(kp a), -(i n/a) Z_n(ks a)],
                                 [(i n/a) Z_n(kp a), ks Z_n'(ks a)]]
 and [alpha; beta] = -M_H^{-1} M_J [a; b].  M_H is the matrix of the paper's
-direct projection formula (Section 3.3, remark on EBCM / projection).
+direct projection formula (Section 4.3, remark on EBCM / projection).
 
 Traction-free (sigma . r_hat = 0 on r = a): columns (sigma_rr, sigma_rtheta) of
 the P potential f = Z_n(kp r) and of the S potential g = Z_n(ks r):
@@ -22,10 +22,10 @@ the P potential f = Z_n(kp r) and of the S potential g = Z_n(ks r):
   S: sigma_rr = -2 mu (i n / r)(g' - g / r), sigma_rt = mu (g'' - g'/r + n^2 g / r^2)
 and [alpha; beta] = -N_H^{-1} N_J [a; b].
 
-Coefficient layout of one particle: [alpha_{-p..p}, beta_{-p..p}] (Section 3.2,
+Coefficient layout of one particle: [alpha_{-p..p}, beta_{-p..p}] (Section 4.2,
 truncation remark and the matrix form of the MS system).  S is (4p+2)^2.
 
-Rotation (Section 3.3: rotated copies by a rotation of the basis): a particle
+Rotation (Section 4.3: rotated copies by a rotation of the basis): a particle
 turned by theta0 has S_rot[n, n'] = e^{-i n theta0} S[n, n'] e^{i n' theta0} on
 each of the four (2p+1)^2 sub-blocks.
 """
@@ -93,7 +93,7 @@ def rotate(S: np.ndarray, p: int, theta0: float) -> np.ndarray:
 
 
 def projection_matrix(m: Media, R: float, n: int) -> np.ndarray:
-    """M_H of the direct projection formula (Section 3.3 remark)."""
+    """M_H of the direct projection formula (Section 4.3 remark)."""
     kp, ks = m.kp, m.ks
     return np.array([[kp * special.h1vp(n, kp * R), -(1j * n / R) * special.hankel1(n, ks * R)],
                      [(1j * n / R) * special.hankel1(n, kp * R), ks * special.h1vp(n, ks * R)]])

@@ -1,6 +1,6 @@
-"""Layered reflected part of the operator by Sommerfeld integrals (Section 4).
+"""Layered reflected part of the operator by Sommerfeld integrals (Section 5).
 
-Multipole-to-Sommerfeld (Section 4.4, Lemma): for y > y_m,
+Multipole-to-Sommerfeld (Section 5.4, Lemma): for y > y_m,
   H_n(k r) e^{i n theta} = ((-1)^n / (i pi)) int e^{s (y_m - y)} / s
                             e^{i xi (x - x_m)} ((s - xi)/(i k))^n dxi,
 with s = sqrt(xi^2 - k^2).  Since (-1)^n ((s - xi)/(i k))^n = (-i zeta)^n with
@@ -9,11 +9,11 @@ zeta = (xi - s)/k, the upgoing P potential of all particles is
   I_p(xi) = sum_m e^{s_p y_m - i xi x_m} / (i pi s_p) sum_n alpha^m_n (-i zeta_p)^n,
 and the S potential the same with (beta, ks).
 
-Reflection (Section 2.2 per mode; the Schur complement of Section 4.2 applies
+Reflection (Section 3.2 per mode; the Schur complement of Section 5.2 applies
 A^{-1} node by node): [RP; RS] = R(xi) [I_p; I_s] are the amplitudes of the
 reflected potentials e^{i xi x + s y} in the host.
 
-Sommerfeld-to-local (Section 4.3, Jacobi-Anger): e^{i xi x + s y} =
+Sommerfeld-to-local (Section 5.3, Jacobi-Anger): e^{i xi x + s y} =
 e^{i xi x_l + s y_l} sum_n (i zeta)^n J_n(k r_l) e^{i n theta_l}, hence
   a^l_n = int e^{i xi x_l + s_p y_l} (i zeta_p)^n RP(xi) dxi,
   b^l_n = int e^{i xi x_l + s_s y_l} (i zeta_s)^n RS(xi) dxi,
@@ -21,7 +21,7 @@ for every particle l, the particle itself included (the Schur complement
 couples every pair through the interface).
 
 The oracle integrates on the real xi axis (the paper's contour is a
-deformation of it, Section 4.1) with adaptive Gauss-Kronrod quadrature
+deformation of it, Section 5.1) with adaptive Gauss-Kronrod quadrature
 (scipy.integrate.quad_vec, a library primitive), breaking at every branch point
 +-kp, +-ks, +-kpb, +-ksb and substituting xi = k +- u^2 on a short piece next to
 each branch point so that the 1/sqrt singularities become smooth.  The tails

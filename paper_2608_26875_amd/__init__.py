@@ -45,6 +45,17 @@ class EmsError(RuntimeError):
         self.code = code
 
 
+class NotConvergedError(RuntimeError):
+    """A solve inside a composite call (misfit and gradient) stopped at its
+    iteration limit before reaching the tolerance; ``info`` is its report."""
+
+    def __init__(self, which, info):
+        super().__init__(f"{which} solve did not converge: {info['iters']} iterations, "
+                         f"relative residual {info['relres']:.3e}")
+        self.which = which
+        self.info = info
+
+
 class Medium(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
 
@@ -295,7 +306,7 @@ class Operator:
 
     def shape_smatrices(self, kind, a, theta0, bc, npts=0, delta=0.0, stream=None):
         """Scattering matrices of the particles' shapes, generated on the GPU
-        (Section 3.3; method of fundamental solutions, ems_smatrix_shapes):
+        (Section 4.3; method of fundamental solutions, ems_smatrix_shapes):
         kind 0 circle, 1 ellipse (semi-axes a, a/2), 2 five-arm star, 3 pear,
         4 starfish (the paper's a1 + a2 cos(a3 t), a2 = a1/4, a3 = 3, 5),
         turned by theta0.  Returns a complex128 device tensor in the packing
@@ -325,7 +336,7 @@ class Operator:
         return out
 
     def set_smatrices_rotated(self, prototypes, which, theta0):
-        """Per-particle S as turned copies of prototype matrices (Section 3.3):
+        """Per-particle S as turned copies of prototype matrices (Section 4.3):
         S_m = D prototypes[which[m]] D^H, D = diag(e^{-i n theta0[m]})."""
         sizes = [np.asarray(b).size for b in prototypes]
         off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -474,12 +485,16 @@ class Operator:
         import torch
         b = self.incident(waves)
         gam, i1 = self.solve(b, tol=tol, restart=restart, maxit=maxit, precision=precision)
+        if not i1["converged"]:
+            raise NotConvergedError("forward", i1)
         u = self.scattered_field(gam, pts)
         res = u - torch.as_tensor(u_obs, dtype=torch.complex128).to(u.device)
         J = 0.5 * float(torch.sum(torch.abs(res) ** 2))
         g = self.scattered_field_adjoint(res, pts)
         lam, i2 = self.solve(g, tol=tol, restart=restart, maxit=maxit, precision=precision,
                              adjoint=True)
+        if not i2["converged"]:
+            raise NotConvergedError("adjoint", i2)
         dxy, dl = self.param_vjp(waves, gam, lam, pts, res)
         return J, dxy.cpu().numpy(), dl, {"forward": i1, "adjoint": i2}
 

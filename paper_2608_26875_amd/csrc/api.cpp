@@ -36,7 +36,7 @@ int fail(ems_handle *h, int code, const std::string &msg) {
 }
 
 // The plane waves that make up the background field of one incident plane
-// wave (Section 6.3, (bplan)): potentials A e^{i xi0 x + q y} in the host
+// wave (Section 7.3, (bplan)): potentials A e^{i xi0 x + q y} in the host
 // (layer 0) or the substrate (layer 1), P (kind 0) or S (kind 1); `up` marks
 // a wave travelling towards y > 0 (q = -s), else q = +s.
 struct PwComp {
@@ -96,7 +96,7 @@ int plane_wave_parts(const ems::Media &md, const ems_plane_wave &w, PwParts &out
   return EMS_OK;
 }
 
-// Point sources in the substrate (Section 2.3): a node rule of their own and
+// Point sources in the substrate (Section 3.2): a node rule of their own and
 // the per-node potentials.  The rule is the handle's Sommerfeld rule laid out
 // for the source-to-target pairs: horizontal spread from the sources and the
 // targets (particles or receivers), depth sums y0 + |y| (two stand-in points
@@ -532,37 +532,48 @@ int ems_set_media(ems_handle *h, const ems_media *m) {
 
 int ems_set_particles(ems_handle *h, int32_t n, const double *xy, const double *R,
                       const int32_t *p) {
-  if (!h || n <= 0 || !xy || !R || !p) return fail(h, EMS_ERR_ARG, "bad particle arguments");
+  if (!h) return EMS_ERR_ARG;
+  // any failure leaves the handle without particles: nothing set before
+  // survives a rejected call
+  h->have_particles = false;
+  h->have_s = false;
+  h->built = false;
+  if (n <= 0 || !xy || !R || !p) return fail(h, EMS_ERR_ARG, "bad particle arguments");
   if (!finite_all(xy, 2 * (size_t)n) || !finite_all(R, n))
     return fail(h, EMS_ERR_NUMERIC, "non-finite particle data");
+  std::vector<int64_t> off(n + 1, 0);
+  int pmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (p[i] < 1 || p[i] > ems::kMaxP)
+      return fail(h, EMS_ERR_UNIMPLEMENTED, "truncation order must be in [1, 16]");
+    if (!(R[i] > 0)) return fail(h, EMS_ERR_ARG, "enclosing radii must be positive");
+    off[i + 1] = off[i] + 2 * (2 * p[i] + 1);
+    pmax = std::max(pmax, p[i]);
+  }
   h->n = n;
   h->xy.assign(xy, xy + 2 * (size_t)n);
   h->R.assign(R, R + n);
   h->p.assign(p, p + n);
-  h->off.assign(n + 1, 0);
-  h->pmax = 0;
-  for (int i = 0; i < n; ++i) {
-    if (p[i] < 1 || p[i] > ems::kMaxP)
-      return fail(h, EMS_ERR_UNIMPLEMENTED, "truncation order must be in [1, 16]");
-    h->off[i + 1] = h->off[i] + 2 * (2 * p[i] + 1);
-    h->pmax = std::max(h->pmax, p[i]);
-  }
+  h->off = std::move(off);
+  h->pmax = pmax;
   h->ncoef = h->off[n];
   h->have_particles = true;
-  h->have_s = false;
-  h->built = false;
   return EMS_OK;
 }
 
 int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets) {
-  if (!h || !S || !offsets) return fail(h, EMS_ERR_ARG, "null S");
+  if (!h) return EMS_ERR_ARG;
+  h->have_s = false;
+  h->built = false;
+  if (!S || !offsets) return fail(h, EMS_ERR_ARG, "null S");
   if (!h->have_particles) return fail(h, EMS_ERR_STATE, "set particles before S-matrices");
-  h->S_off.assign(offsets, offsets + h->n + 1);
+  if (offsets[0] != 0) return fail(h, EMS_ERR_ARG, "S offsets must start at 0");
   for (int i = 0; i < h->n; ++i) {
     const int64_t K = 4 * h->p[i] + 2;
     if (offsets[i + 1] - offsets[i] != K * K)
       return fail(h, EMS_ERR_ARG, "S offsets do not match (4p+2)^2 blocks");
   }
+  h->S_off.assign(offsets, offsets + h->n + 1);
   const size_t tot = (size_t)offsets[h->n];
   if (!finite_all(S, 2 * tot)) return fail(h, EMS_ERR_NUMERIC, "non-finite S entry");
   h->S_host.resize(tot);
@@ -575,7 +586,10 @@ int ems_set_smatrices(ems_handle *h, const double *S, const int64_t *offsets) {
 int ems_set_smatrices_rotated(ems_handle *h, int32_t nproto, const double *S_proto,
                               const int64_t *proto_off, const int32_t *which,
                               const double *theta0) {
-  if (!h || nproto <= 0 || !S_proto || !proto_off || !which || !theta0)
+  if (!h) return EMS_ERR_ARG;
+  h->have_s = false;
+  h->built = false;
+  if (nproto <= 0 || !S_proto || !proto_off || !which || !theta0)
     return fail(h, EMS_ERR_ARG, "bad prototype arguments");
   if (!h->have_particles) return fail(h, EMS_ERR_STATE, "set particles before S-matrices");
   for (int k = 0; k < nproto; ++k)
@@ -843,6 +857,9 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   if (!h) return EMS_ERR_ARG;
   if (!h->have_media || !h->have_particles || !h->have_s)
     return fail(h, EMS_ERR_STATE, "set media, particles and S-matrices before build");
+  for (int i = 0; i < h->n; ++i)
+    if (h->p[i] < 1 || h->p[i] > ems::kMaxP || h->p[i] > h->pmax)
+      return fail(h, EMS_ERR_STATE, "particle orders outside [1, 16]");
   int rc = check_geometry(h);
   if (rc) return rc;
   free_device(h);

@@ -1,4 +1,4 @@
-// Scattered displacement at host points (y < 0; Section 4, coupled
+// Scattered displacement at host points (y < 0; Section 5, coupled
 // representation; substrate points y > 0 see the transmitted part only):
 //   u(x) = sum_m sum_n alpha^m_n grad v_n^{kp}(x - x_m) + beta^m_n grad^perp v_n^{ks}(x - x_m)
 //          + grad phi_R + grad^perp psi_R,

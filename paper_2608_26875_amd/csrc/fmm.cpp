@@ -1,6 +1,6 @@
 // Host set-up of the free-space fast multipole method (two scalar Helmholtz
 // FMMs, kp acting on the alpha coefficients and ks on beta; the paper cites
-// the FMM for the particle translations without describing it, Section 3.2).
+// the FMM for the particle translations without describing it, Section 4.2).
 //
 // Uniform quadtree on the bounding square, leaf side chosen for about
 // `leaf` particles per box.  Above the leaves, levels are kept up to a top
@@ -15,7 +15,7 @@
 //     polar form of (destination centre - source centre) for P2M / M2M and of
 //     (destination - source) for L2L / L2P (Graf's theorem for J and H);
 //   M2L: s_nu = t_{-nu} with t_nu = H_nu(k d) e^{-i nu (th - pi)}, the same
-//     symbol as the particle-to-particle translation of Section 3.2.
+//     symbol as the particle-to-particle translation of Section 4.2.
 // The symbols are tabulated here once per geometry and frequency.
 #include <algorithm>
 #include <cmath>

@@ -1,13 +1,13 @@
 // Gradient of a receiver misfit with respect to the particle centres and the
 // substrate's Lame parameters (adjoint method on the Schur-complement system
-// of Sections 3.2 and 4.2).
+// of Sections 4.2 and 5.2).
 //
 // Centres.  Both translation parts satisfy the same two identities, which
 // follow from d_x (Z_n e^{i n th}) = (k/2)(Z_{n-1} e^{i(n-1)th} - Z_{n+1} e^{i(n+1)th})
 // and d_y = (i k/2)(... + ...) for Hankel and Bessel waves, and from
 // i xi (i zeta)^n = (k/2)((i zeta)^{n+1} - (i zeta)^{n-1}),
 // s (i zeta)^n = (i k/2)((i zeta)^{n+1} + (i zeta)^{n-1}) for the plane waves
-// of Section 4 (xi = (k/2)(zeta + 1/zeta), s = (k/2)(1/zeta - zeta)):
+// of Section 5 (xi = (k/2)(zeta + 1/zeta), s = (k/2)(1/zeta - zeta)):
 //  * moving a receiving centre shifts its regular expansion a:
 //      D_x a_n = (k/2)(a_{n+1} - a_{n-1}),  D_y a_n = (i k/2)(a_{n+1} + a_{n-1});
 //  * moving a source centre is the same operator applied to the shifted

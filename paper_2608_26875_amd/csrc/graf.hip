@@ -1,4 +1,4 @@
-// Free-space particle-particle translations (Section 3.2, Graf's addition
+// Free-space particle-particle translations (Section 4.2, Graf's addition
 // theorem), evaluated directly for every pair.
 //
 // Incoming coefficients of the target m collect from every source l != m

@@ -1,6 +1,6 @@
-// S-matrix apply and the final combination of the operator (Section 3.2 and
+// S-matrix apply and the final combination of the operator (Section 4.2 and
 // 4.2: y_m = x_m - S_m (T_free x + T_refl x)_m), the plane-wave right-hand
-// side (Section 6.3), and the vector kernels of the GMRES driver.
+// side (Section 7.3), and the vector kernels of the GMRES driver.
 //
 // The S store is packed per particle column-major (S^T row-major), so the
 // 4p+2 lanes of one wavefront read one column of S_m in a single coalesced
@@ -95,7 +95,7 @@ hipError_t launch_s_multiply(const ems_handle *h, const double2 *c, double2 *y, 
 }
 
 // ---------------------------------------------------------------------------
-// Plane-wave local coefficients (Section 6.3 background field; Jacobi-Anger).
+// Plane-wave local coefficients (Section 7.3 background field; Jacobi-Anger).
 // Per right-hand side r the host supplies pw[r] = {xi0, s_p, s_s, Ain_p,
 // Ain_s, Ar_p, Ar_s} (complex), and
 //   a_n = Ar_p e^{i xi0 x + s_p y} (i (xi0 - s_p)/kp)^n + Ain_p e^{i xi0 x - s_p y} (i (xi0 + s_p)/kp)^n
@@ -146,7 +146,7 @@ hipError_t launch_incident_pw(const ems_handle *h, const double2 *pw, int nrhs, 
   return hipGetLastError();
 }
 
-// Point source in the substrate (Section 2.3): local expansions of its field
+// Point source in the substrate (Section 3.2): local expansions of its field
 // transmitted into the host, over a node list of its own.  nd [q][3] = (xi,
 // s_p, s_s); amp [nrhs][q][2] = w_j (Td A_inc)_{P,S}, the host's downgoing
 // potentials per node (weights, e^{-i xi x0} and the source's depth factor

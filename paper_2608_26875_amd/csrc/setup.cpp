@@ -172,7 +172,7 @@ int build_nodes(const SommerfeldSpec &spec, const Media &md, const std::vector<d
     return EMS_OK;
   }
   if (spec.kind == 0) {
-    // Section 4.1: xi(t) = t - i delta tanh(t), trapezoidal rule in t.
+    // Section 5.1: xi(t) = t - i delta tanh(t), trapezoidal rule in t.
     const int q = spec.q > 1 ? spec.q : 512;
     const double h = 2.0 * T / (q - 1);
     for (int j = 0; j < q; ++j) {
@@ -338,7 +338,7 @@ void depth_cuts(const NodeTable &nodes, const Media &md, const std::vector<doubl
 }
 
 // ---------------------------------------------------------------------------
-// Welded interface, one Fourier mode (Section 2.2, written for potentials).
+// Welded interface, one Fourier mode (Section 3.2, written for potentials).
 // A potential e^{i xi x + q y} in (lambda, mu) gives (u1, u2, t1, t2) with
 // t = T_y u: P: (i xi, q, 2 mu i xi q, (lambda + 2 mu) q^2 - lambda xi^2),
 //            S: (-q, i xi, -mu (q^2 + xi^2), 2 mu i xi q).
@@ -474,7 +474,7 @@ int reflection_s(cd xi, const cd s4[4], const Media &md, cd R[4]) {
   return reflect_transmit_s(xi, s4, md, R, nullptr);
 }
 
-// Waves from the substrate (Section 6.3's plane-wave setup): a unit
+// Waves from the substrate (Section 7.3's plane-wave setup): a unit
 // downgoing P (column 0) or S (column 1) potential e^{i xi x + s_b y}; the
 // continuity conditions move it to the right-hand side.  Td = host
 // downgoing (transmitted), Rb = substrate upgoing (reflected) potentials.
@@ -501,7 +501,7 @@ int from_substrate(cd xi, const Media &md, cd Td[4], cd Rb[4]) {
 }
 
 // ---------------------------------------------------------------------------
-// Closed-form disk scattering matrix (Section 3.1, boundary condition imposed
+// Closed-form disk scattering matrix (Section 4.1, boundary condition imposed
 // mode by mode).  Z in {J, H}; f(r) = Z_n(kp r), g(r) = Z_n(ks r).
 // Rigid: rows (u_r, u_theta): grad phi -> (f', (i n / a) f),
 //        grad^perp psi -> (-(i n / a) g, g').
@@ -581,7 +581,7 @@ int disk_smatrix(const Media &md, double a, int p, int bc, std::vector<cd> &S) {
 }
 
 // R(xi) and its derivatives with respect to the substrate's lambda and mu
-// (Section 2.2 system differentiated): with M X = -B, only the substrate
+// (Section 3.2 system differentiated): with M X = -B, only the substrate
 // columns of M depend on (lambda_b, mu_b), explicitly and through
 // s_pb = sqrt(xi^2 - kpb^2), s_sb = sqrt(xi^2 - ksb^2), kpb^2 = w^2 rho_b /
 // (lambda_b + 2 mu_b), ksb^2 = w^2 rho_b / mu_b; then dX = -M^{-1} (dM) X.

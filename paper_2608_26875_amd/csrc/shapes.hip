@@ -1,4 +1,4 @@
-// Scattering matrices of non-circular particles (Section 3.3), generated on
+// Scattering matrices of non-circular particles (Section 4.3), generated on
 // the GPU, one particle per workgroup, by the method of fundamental
 // solutions: the scattered field of a particle is carried by N compressional
 // and N shear monopoles H_0(k |x - y_j|) at sources y_j = z(t_j + i delta)

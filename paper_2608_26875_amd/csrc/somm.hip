@@ -1,10 +1,10 @@
-// Layered reflected part of the operator on a Sommerfeld node set (Section 4).
+// Layered reflected part of the operator on a Sommerfeld node set (Section 5).
 //
-//   aggregate   (multipole-to-Sommerfeld, Section 4.4 Lemma):
+//   aggregate   (multipole-to-Sommerfeld, Section 5.4 Lemma):
 //       I_w(j) = sum_m e^{s_w(j) y_m - i xi_j x_m} sum_n c^m_{w,n} (-i zeta_w(j))^n
-//   reflect     (interface, Section 2.2 per node; Schur complement, Section 4.2):
+//   reflect     (interface, Section 3.2 per node; Schur complement, Section 5.2):
 //       [RP; RS]_j = w_j R(xi_j) [I_p / (i pi s_p); I_s / (i pi s_s)]
-//   disaggregate (Sommerfeld-to-local, Section 4.3, Jacobi-Anger):
+//   disaggregate (Sommerfeld-to-local, Section 5.3, Jacobi-Anger):
 //       a^l_{w,n} = sum_j e^{i xi_j x_l + s_w(j) y_l} (i zeta_w(j))^n RW_j
 // with w in {P, S}, zeta = (xi - s)/k, and (i zeta)^n = (-1)^n (-i zeta)^n so a
 // single power table V[j][n] = (-i zeta_w(j))^n serves both contractions (the

@@ -1,7 +1,7 @@
 """Host-side checks of the depth truncation of the tabulated Sommerfeld
 contractions (no GPU).
 
-Each real node of the Sommerfeld rule (Section 4.1) keeps a prefix of the
+Each real node of the Sommerfeld rule (Section 5.1) keeps a prefix of the
 particles in depth order; each particle keeps a node range.  Pinned here
 against quantities computed independently from the node table:
 
@@ -62,7 +62,7 @@ def test_truncation_off_and_complex_nodes_keep_everything():
     w = W.c1_cloud()
     _, (perm, kcut, rng, kept) = _cuts(w, depth_cut=-1.0)
     assert kept == 1.0 and np.all(kcut == len(perm))
-    # the tanh contour of Section 4.1 has complex nodes: no truncation
+    # the tanh contour of Section 5.1 has complex nodes: no truncation
     w0 = W.c0_circles()
     _, (perm0, kcut0, _, kept0) = _cuts(w0, kind=0)
     assert kept0 == 1.0 and np.all(kcut0 == len(perm0))

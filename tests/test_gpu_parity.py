@@ -68,7 +68,7 @@ def test_c0_apply_parity():
 
 
 def test_c0_paper_contour_parity():
-    """The paper's tanh contour (Section 4.1) with q = 1024 nodes meets the bound too."""
+    """The paper's tanh contour (Section 5.1) with q = 1024 nodes meets the bound too."""
     w = W.c0_circles()
     m = oracle_media(w)
     S = smatrix.workload_blocks(w, m)

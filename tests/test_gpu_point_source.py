@@ -1,5 +1,5 @@
-"""GPU parity of the point-source incidence (Section 2.3; the point-source
-workload of Section 6) against the oracle, which solves the paper's density
+"""GPU parity of the point-source incidence (Section 3.2; the point-source
+workload of Section 7) against the oracle, which solves the paper's density
 system A_xi sigma = b_xi by adaptive quadrature:
 
 * right-hand sides S (local expansions of the transmitted source field) for

@@ -1,5 +1,5 @@
 """GPU parity of the scattering matrices of non-circular particles (Section
-3.3; generated on the GPU by fundamental solutions) against the oracle, which
+4.3; generated on the GPU by fundamental solutions) against the oracle, which
 assembles the same collocation system with scipy's Bessel functions and
 solves it with numpy's LU:
 
@@ -253,7 +253,7 @@ def test_pear_and_starfish_match_oracle():
 
 def test_rotated_prototypes_match_generated_matrices():
     # the paper's use: a few prototype shapes, copies at any orientation
-    # (Section 3.3).  Operator on rotated prototypes (generated at theta0 = 0)
+    # (Section 4.3).  Operator on rotated prototypes (generated at theta0 = 0)
     # against the operator on matrices generated for each turned particle.
     n = 12
     rng = np.random.default_rng(4)

@@ -1,4 +1,4 @@
-"""GPU parity of the waves sent from the substrate (Section 6.3's plane-wave
+"""GPU parity of the waves sent from the substrate (Section 7.3's plane-wave
 setup, (bplan)) and of the field in the substrate, against the oracle:
 
 * right-hand sides of P and SV waves from the substrate, including angles

@@ -5,7 +5,7 @@
 * host set-up code (closed-form disk S, per-node interface reflection) agrees
   with the oracle;
 * the library's Sommerfeld node rules integrate the Sommerfeld identity and
-  the multipole-to-Sommerfeld lemma (closed forms, Sections 2.1 and 4.4) to
+  the multipole-to-Sommerfeld lemma (closed forms, Sections 3.1 and 5.4) to
   near machine precision, i.e. the quadrature the kernels consume is pinned
   on the CPU.
 """
@@ -128,7 +128,7 @@ def test_node_rule_integrates_sommerfeld_identity(kind):
 @pytest.mark.parametrize("case", [(40, 10, 8.0, 80.0), (16, 10, 4.0, 20.0), (30, 5, 6.0, 100.0),
                                   (40, 15, 8.0, 300.0)])
 def test_node_rule_integrates_lemma_high_order(case):
-    """Section 4.4 Lemma for n = -2p..2p at the horizontal spreads and depth
+    """Section 5.4 Lemma for n = -2p..2p at the horizontal spreads and depth
     sums the cloud produces.  The sum of many large terms has a rounding floor
     of about eps * sum |terms| (the same for any quadrature of this integral),
     so the bound is 1e-12 |exact| + 64 eps sum |terms|."""
@@ -180,4 +180,39 @@ def test_rotated_prototypes_validation_without_gpu():
     nan_th = np.array([0.1, np.nan, 0.3])
     assert lib.ems_set_smatrices_rotated(h, 2, protos.ctypes.data, off.ctypes.data,
                                          ok.ctypes.data, nan_th.ctypes.data) == -6
+    lib.ems_destroy(h)
+
+
+def test_rejected_particles_leave_no_valid_state():
+    """A rejected ems_set_particles (order out of range) must not leave the
+    handle marked as holding particles from an earlier successful call: the
+    S-matrices and the build that follow are refused, not run on a mix of
+    old and new data."""
+    import ctypes
+    lib = E.lib()
+    h = ctypes.c_void_p()
+    assert lib.ems_create(ctypes.byref(h)) == 0
+    m = E.make_media((2, 1, 1), (4, 2, 1.5), 4.0)
+    assert lib.ems_set_media(h, ctypes.byref(m)) == 0
+    xy = np.array([[0.0, -2.0], [3.0, -2.0]])
+    R = np.array([0.4, 0.4])
+    p = np.array([3, 3], dtype=np.int32)
+    assert lib.ems_set_particles(h, 2, xy.ctypes.data, R.ctypes.data, p.ctypes.data) == 0
+    bad = np.array([3, 20], dtype=np.int32)
+    assert lib.ems_set_particles(h, 2, xy.ctypes.data, R.ctypes.data, bad.ctypes.data) == -7
+    # a (4*20+2)^2 block for the second particle is refused: no particles are set
+    S = np.zeros(14 * 14 + 82 * 82, complex)
+    off = np.array([0, 196, 196 + 82 * 82], dtype=np.int64)
+    assert lib.ems_set_smatrices(h, S.ctypes.data, off.ctypes.data) == -5
+    assert lib.ems_build(h, None) == -5
+    # a valid call restores a usable state; a bad S call clears it again
+    assert lib.ems_set_particles(h, 2, xy.ctypes.data, R.ctypes.data, p.ctypes.data) == 0
+    S2 = np.zeros(2 * 14 * 14, complex)
+    off2 = np.array([0, 196, 392], dtype=np.int64)
+    assert lib.ems_set_smatrices(h, S2.ctypes.data, off2.ctypes.data) == 0
+    off_bad = np.array([0, 196, 300], dtype=np.int64)
+    assert lib.ems_set_smatrices(h, S2.ctypes.data, off_bad.ctypes.data) == -1
+    assert lib.ems_build(h, None) == -5
+    rneg = np.array([0.4, -0.4])
+    assert lib.ems_set_particles(h, 2, xy.ctypes.data, rneg.ctypes.data, p.ctypes.data) == -1
     lib.ems_destroy(h)

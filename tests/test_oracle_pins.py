@@ -2,9 +2,9 @@
 
 Each test checks one oracle part against something other than itself:
 closed forms (Graf addition theorem, the Sommerfeld identity and the Lemma of
-Section 4.4, Jacobi-Anger), brute-force boundary conditions evaluated with
+Section 5.4, Jacobi-Anger), brute-force boundary conditions evaluated with
 Cartesian derivative identities, invariants (reciprocity, energy flux of the
-interface, identical media), values the paper prints (Section 6 wavenumbers),
+interface, identical media), values the paper prints (Section 7 wavenumbers),
 an image-source closed form for the reflected part, and spectral convergence
 of the solved field on a particle boundary.  A plausible slip anywhere (a
 dropped term, a sign, a transposed index) fails one of them.
@@ -66,7 +66,7 @@ def real_axis_integral(f, m, T, tol=1e-13):
     return tot
 
 
-# ---- wavenumbers: values printed in Section 6 ------------------------------
+# ---- wavenumbers: values printed in Section 7 ------------------------------
 
 def test_paper_wavenumbers():
     g = json.load(open(os.path.join(HERE, "golden", "paper_wavenumbers.json")))
@@ -119,7 +119,7 @@ def test_disk_smatrix_boundary_condition(bc, a):
 
 
 def test_projection_formula_recovers_outgoing_coefficients():
-    """Section 3.3 remark: (1/2 pi R) M_H^{-1} [int u.e^{il th} r_hat; int u.e^{il th} th_hat]."""
+    """Section 4.3 remark: (1/2 pi R) M_H^{-1} [int u.e^{il th} r_hat; int u.e^{il th} th_hat]."""
     rng = np.random.default_rng(4)
     p = 5
     al = rng.standard_normal(2 * p + 1) + 1j * rng.standard_normal(2 * p + 1)
@@ -236,7 +236,7 @@ def test_sommerfeld_identity_h0():
 
 @pytest.mark.parametrize("n", [-7, -2, 0, 1, 5, 9])
 def test_multipole_to_sommerfeld_lemma(n):
-    """Section 4.4 Lemma with the oracle's (-i zeta)^n form, for y > y_m."""
+    """Section 5.4 Lemma with the oracle's (-i zeta)^n form, for y > y_m."""
     k = M0.ks
     X, Y = 1.1, 1.6
     def f(xi):
@@ -251,7 +251,7 @@ def test_multipole_to_sommerfeld_lemma(n):
 
 @pytest.mark.parametrize("xi", [0.3, -1.7, 3.9, 6.5, -9.0])
 def test_jacobi_anger_local_expansion(xi):
-    """Section 4.3: e^{i xi x + s y} = e^{i xi x_l + s y_l} sum (i zeta)^n J_n e^{i n th}."""
+    """Section 5.3: e^{i xi x + s y} = e^{i xi x_l + s y_l} sum (i zeta)^n J_n e^{i n th}."""
     k = 4.0
     s = complex(interface.branch_s(xi, k))
     z = (xi - s) / k

@@ -1,4 +1,4 @@
-"""Pins of the oracle's point-source incidence (Section 2.3), on the CPU.
+"""Pins of the oracle's point-source incidence (Section 3.2), on the CPU.
 
 * The 4x4 system assembled from the definitions of the three Sommerfeld
   fields equals the paper's printed A_xi (aa) and b_xi at rho = 1, up to the

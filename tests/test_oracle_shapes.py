@@ -1,5 +1,5 @@
 """Pins of the oracle's scattering matrices of non-circular particles
-(Section 3.3; method of fundamental solutions, see oracle/shapes.py), on the
+(Section 4.3; method of fundamental solutions, see oracle/shapes.py), on the
 CPU:
 
 * circles reproduce the closed-form S of the disk (mode-by-mode boundary
@@ -8,7 +8,7 @@ CPU:
   (an incident regular wave is half incoming, half outgoing; the flux of every
   potential mode is the same per |amplitude|^2);
 * the boundary condition holds between the collocation points;
-* a turned particle's S is the basis rotation of the unturned one (Section 3.3,
+* a turned particle's S is the basis rotation of the unturned one (Section 4.3,
   rotated copies);
 * the discretisation has converged at the paper-like 256 points.
 """

@@ -1,4 +1,4 @@
-"""Pins of the oracle's waves sent from the substrate (Section 6.3's plane-wave
+"""Pins of the oracle's waves sent from the substrate (Section 7.3's plane-wave
 setup, (bplan)) and of its transmitted field, checked on the CPU against what
 the physics fixes independently of the oracle's formulas:
 

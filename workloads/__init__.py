@@ -12,7 +12,7 @@ z > 0 measured from the interface; they are mapped with y = -z.  The medium
 holding the particles is called the *host*; the other half-space is the
 *substrate*.
 
-Shape family of the paper's experiments (Section 6): r(t) = a1 + a2 cos(a3 t).
+Shape family of the paper's experiments (Section 7): r(t) = a1 + a2 cos(a3 t).
 Labels used here: 0 circle (radius a), 1 ellipse (semi-axes a and a/2),
 2 five-arm star r(t) = a (1 + 0.3 cos 5t).  The enclosing radius is a for the
 first two and 1.3 a for the star.
