@@ -114,19 +114,26 @@ typedef struct {
 
 typedef struct {
   double tol;        /* relative residual target ||b - A x|| / ||b||          */
-  int32_t restart;   /* Krylov dimension before a restart                      */
+  int32_t restart;   /* Krylov dimension before a restart (<= 0: as many
+                        basis vectors as fit in half of the free device
+                        memory, at most 5000)                                  */
   int32_t maxit;     /* total inner iterations                                 */
   int32_t precision; /* 0: FP64 GMRES; 1: FP32 contractions in the inner
                         solve with FP64 iterative refinement                    */
   double inner_tol;  /* precision 1: relative tolerance of each inner solve    */
+  int32_t precond;   /* 0: none; 1: cluster block-Jacobi right preconditioner
+                        (ems_set_precond), M^{-H} for the adjoint solve         */
 } ems_solver_opts;
 
 typedef struct {
   int32_t iters;       /* inner iterations (all RHS, lock-step: per RHS)      */
   int32_t outer_iters; /* refinement sweeps (precision 1), else 1             */
   int32_t converged;
-  double relres;       /* max over RHS of the final FP64 relative residual    */
-  double seconds;
+  double relres;       /* max over RHS of the final FP64 relative residual,
+                          computed from b - A x (not the GMRES estimate)      */
+  double seconds;      /* wall time of the call, preconditioner set-up included */
+  int32_t restart;     /* Krylov dimension used                               */
+  double precond_seconds; /* set-up time of the preconditioner (0 if none)    */
 } ems_solve_info;
 
 typedef struct {
@@ -299,7 +306,7 @@ int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32
                       ems_stream_t stream);
 
 /* Right-hand side S_m (a0^m, b0^m) of the S-preconditioned system (Section
- * 3.2) for nrhs plane waves, into device memory rhs [nrhs][n_coeff]: the
+ * 4.2) for nrhs plane waves, into device memory rhs [nrhs][n_coeff]: the
  * local expansions of the background field in the host (Section 7.3,
  * (bplan)): incident + interface-reflected waves for waves 0 and 1, the
  * transmitted waves for waves 2 and 3. */
@@ -322,6 +329,44 @@ int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_sol
  * arguments, options and return codes as ems_solve. */
 int ems_solve_adjoint(ems_handle *h, const void *b, void *x, int32_t nrhs,
                       const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream);
+
+/* Cluster block-Jacobi preconditioner of the solves (precond = 1).  The
+ * particles are split into spatial clusters of at most max_unknowns
+ * coefficients (recursive halving of the cloud across its wider extent); on
+ * each cluster c the free-space block of the multiple-scattering system of
+ * Section 4.2, B_c = I - S_c T_cc (identity on the particle blocks, -S_m
+ * T^{ml} between the cluster's particles m != l, T^{ml} the Graf
+ * translation), is inverted on the GPU once per build and stored in complex64
+ * (about 8 max_unknowns bytes per unknown).  GMRES then runs on A M^{-1} with
+ * M = diag(B_c) and returns x = M^{-1} u.  max_unknowns in [1, 512]
+ * (0 = 512, eight particles of order 15; a particle larger than it forms a
+ * cluster of its own); the default is 512.  Takes effect
+ * at the next set-up (a rebuild or the first preconditioned call). */
+int ems_set_precond(ems_handle *h, int32_t max_unknowns);
+
+/* y = M^{-1} x (adjoint = 0) or M^{-H} x (adjoint = 1) with the cluster
+ * block-Jacobi preconditioner above; builds it first when needed (then
+ * synchronous).  x, y device [nrhs][n_coeff] complex128, may not alias.
+ * clusters, max_rows (host, may be NULL) receive the cluster count and the
+ * largest cluster's unknowns; setup_s the set-up time. */
+int ems_precond_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t adjoint,
+                      int32_t *clusters, int32_t *max_rows, double *setup_s,
+                      ems_stream_t stream);
+
+/* Progress report of the solves: fn(iteration, estimated relative residual,
+ * user) is called on the calling thread after every `every`-th inner
+ * iteration of ems_solve / ems_solve_adjoint (fn = NULL switches it off).
+ * The callback must not call into this handle. */
+typedef void (*ems_progress_fn)(int32_t iteration, double relres, void *user);
+int ems_set_progress(ems_handle *h, ems_progress_fn fn, int32_t every, void *user);
+
+/* Residual history of the last ems_solve / ems_solve_adjoint on this handle:
+ * the estimated relative residual after every inner iteration (largest over
+ * the right-hand sides; for precision 1 the inner estimate scaled by the
+ * outer residual at the start of its refinement sweep).  Host out[cap];
+ * *count receives the number of iterations recorded (entries beyond cap are
+ * not written). */
+int ems_solve_history(const ems_handle *h, double *out, int32_t cap, int32_t *count);
 
 /* Scattered displacement at npts points (Section 5, coupled
  * representation).  Host points (y < 0, outside every enclosing disk):

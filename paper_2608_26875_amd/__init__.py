@@ -82,13 +82,15 @@ class PlaneWave(ctypes.Structure):
 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("precond", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("relres", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("precond_seconds", ctypes.c_double)]
 
 
 class Fmm(ctypes.Structure):
@@ -107,6 +109,9 @@ class BuildInfo(ctypes.Structure):
                 ("fmm_levels", ctypes.c_int32), ("fmm_m2l", ctypes.c_int64),
                 ("kp", ctypes.c_double), ("ks", ctypes.c_double), ("kpb", ctypes.c_double),
                 ("ksb", ctypes.c_double), ("somm_kept", ctypes.c_double)]
+
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p)
 
 
 def _load():
@@ -151,6 +156,11 @@ def _load():
         "ems_profile": ([P, I32], I32),
         "ems_set_fmm": ([P, ctypes.POINTER(Fmm)], I32),
         "ems_profile_read": ([P, ctypes.POINTER(KernelTime), I32, ctypes.POINTER(I32)], I32),
+        "ems_set_precond": ([P, I32], I32),
+        "ems_precond_apply": ([P, P, P, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                               ctypes.POINTER(D), P], I32),
+        "ems_solve_history": ([P, ctypes.POINTER(D), I32, ctypes.POINTER(I32)], I32),
+        "ems_set_progress": ([P, PROGRESS_FN, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -171,7 +181,8 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_eval_background_point", "ems_sommerfeld_nodes",
             "ems_sommerfeld_depth_cuts",
             "ems_reflection", "ems_profile",
-            "ems_profile_read", "ems_set_fmm")
+            "ems_profile_read", "ems_set_fmm", "ems_set_precond", "ems_precond_apply",
+            "ems_solve_history", "ems_set_progress")
 
 
 def lib():
@@ -476,7 +487,7 @@ class Operator:
         return dxy, (dl[0], dl[1])
 
     def misfit_gradient(self, waves, pts, u_obs, tol=1e-12, restart=200, maxit=2000,
-                        precision=0):
+                        precision=0, precond=0):
         """J = 1/2 sum |u - u_obs|^2 over the plane waves and receivers, and its
         gradient: forward solve, field, adjoint right-hand side F^H res,
         adjoint solve, parameter vector-Jacobian product.  u_obs: complex128
@@ -484,7 +495,8 @@ class Operator:
         (dJ/dlambda_b, dJ/dmu_b), info)."""
         import torch
         b = self.incident(waves)
-        gam, i1 = self.solve(b, tol=tol, restart=restart, maxit=maxit, precision=precision)
+        gam, i1 = self.solve(b, tol=tol, restart=restart, maxit=maxit, precision=precision,
+                             precond=precond)
         if not i1["converged"]:
             raise NotConvergedError("forward", i1)
         u = self.scattered_field(gam, pts)
@@ -492,7 +504,7 @@ class Operator:
         J = 0.5 * float(torch.sum(torch.abs(res) ** 2))
         g = self.scattered_field_adjoint(res, pts)
         lam, i2 = self.solve(g, tol=tol, restart=restart, maxit=maxit, precision=precision,
-                             adjoint=True)
+                             adjoint=True, precond=precond)
         if not i2["converged"]:
             raise NotConvergedError("adjoint", i2)
         dxy, dl = self.param_vjp(waves, gam, lam, pts, res)
@@ -532,12 +544,15 @@ class Operator:
         return g
 
     def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-5,
-              stream=None, adjoint=False):
-        """GMRES on A (or A^H with adjoint=True); precision 1 = mixed iterative refinement."""
+              stream=None, adjoint=False, precond=0):
+        """GMRES on A (or A^H with adjoint=True); precision 1 = mixed iterative
+        refinement; precond 1 = cluster block-Jacobi right preconditioner;
+        restart 0 = as large as half of the free device memory allows."""
         import torch
         nrhs = self._vec_check(b)
         x = torch.empty_like(b)
-        o = SolverOpts(float(tol), int(restart), int(maxit), int(precision), float(inner_tol))
+        o = SolverOpts(float(tol), int(restart), int(maxit), int(precision), float(inner_tol),
+                       int(precond))
         info = SolveInfo()
         fn = _lib.ems_solve_adjoint if adjoint else _lib.ems_solve
         rc = fn(self.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
@@ -545,6 +560,41 @@ class Operator:
         if rc < 0:
             self._check(rc)
         return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+
+    def set_precond(self, max_unknowns=0):
+        """Cluster size of the block-Jacobi preconditioner (unknowns, <= 512)."""
+        self._check(_lib.ems_set_precond(self.h, int(max_unknowns)))
+
+    def precond_apply(self, x, adjoint=False, stream=None):
+        """(M^{-1} x or M^{-H} x, {clusters, max_rows, setup_s})."""
+        import torch
+        nrhs = self._vec_check(x)
+        y = torch.empty_like(x)
+        nc, mr, su = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+        self._check(_lib.ems_precond_apply(self.h, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()), nrhs,
+                                           1 if adjoint else 0, ctypes.byref(nc), ctypes.byref(mr),
+                                           ctypes.byref(su), _stream_ptr(stream)))
+        return y, {"clusters": nc.value, "max_rows": mr.value, "setup_s": su.value}
+
+    def set_progress(self, fn=None, every=100):
+        """fn(iteration, relres) after every ``every`` inner iterations of a
+        solve (None switches it off).  The ctypes callback is kept alive on
+        the operator."""
+        if fn is None:
+            self._progress_cb = None
+            self._check(_lib.ems_set_progress(self.h, PROGRESS_FN(), 0, None))
+            return
+        self._progress_cb = PROGRESS_FN(lambda it, rr, _u: fn(int(it), float(rr)))
+        self._check(_lib.ems_set_progress(self.h, self._progress_cb, int(every), None))
+
+    def solve_history(self):
+        """Estimated relative residual per iteration of the last solve."""
+        cnt = ctypes.c_int32(0)
+        self._check(_lib.ems_solve_history(self.h, None, 0, ctypes.byref(cnt)))
+        out = (ctypes.c_double * max(1, cnt.value))()
+        self._check(_lib.ems_solve_history(self.h, out, cnt.value, ctypes.byref(cnt)))
+        return np.array(out[:cnt.value])
 
     def profile(self, enable: bool):
         self._check(_lib.ems_profile(self.h, 1 if enable else 0))

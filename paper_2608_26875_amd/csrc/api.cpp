@@ -1,8 +1,9 @@
 // C ABI of the library: handle life cycle, validation, set-up, the operator
 // apply pipeline and the GMRES driver (Saad-Schultz GMRES named in Sections
-// 3.2 and 4.2, restarted, CGS2 Arnoldi on the device, Givens on the host).
+// 4.2 and 5.2, restarted, CGS2 Arnoldi on the device, Givens on the host).
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -272,6 +273,16 @@ void free_device(ems_handle *h) {
   h->fmm_dev.clear();
   h->ws_nrhs = 0;
   h->V_bytes = h->tmp_bytes = h->red_bytes = 0;
+  dfree(h->d_pc_rptr);
+  dfree(h->d_pc_rows);
+  dfree(h->d_pc_nb);
+  dfree(h->d_pc_ioff);
+  dfree(h->d_pc_inv);
+  dfree(h->d_pcz);
+  h->pcz_bytes = 0;
+  h->pc_built = false;
+  h->pc_nc = h->pc_n2 = 0;
+  h->pc_store = 0;
 }
 
 template <typename T>
@@ -446,6 +457,171 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
   if (adjoint) cflags &= ~EMS_PART_S;
   ems::ProfScope ps(h, "combine_s_apply", st, (cflags & EMS_PART_S) ? h->flops_s * nrhs : 0.0);
   HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, st));
+  return EMS_OK;
+}
+
+// Clusters of the block-Jacobi preconditioner: recursive splits of the
+// particle set across the wider extent of its bounding box, the left part
+// taking as many whole clusters of cap unknowns as half of the clusters the
+// set needs, until a set fits in cap unknowns.  order receives the particles
+// cluster by cluster, cptr[c] the start of cluster c in order.
+void kd_clusters(const ems_handle *h, int64_t cap, std::vector<int> &order,
+                 std::vector<int> &cptr) {
+  const int n = h->n;
+  order.resize(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  cptr.assign(1, 0);
+  auto K = [&](int i) { return h->off[i + 1] - h->off[i]; };
+  std::function<void(int, int)> rec = [&](int lo, int hi) {
+    int64_t tot = 0;
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (int k = lo; k < hi; ++k) {
+      const int i = order[k];
+      tot += K(i);
+      x0 = std::min(x0, h->xy[2 * i]);
+      x1 = std::max(x1, h->xy[2 * i]);
+      y0 = std::min(y0, h->xy[2 * i + 1]);
+      y1 = std::max(y1, h->xy[2 * i + 1]);
+    }
+    if (tot <= cap || hi - lo == 1) {
+      cptr.push_back(hi);
+      return;
+    }
+    const int ax = (x1 - x0) >= (y1 - y0) ? 0 : 1;
+    std::sort(order.begin() + lo, order.begin() + hi, [&](int a, int b) {
+      const double va = h->xy[2 * a + ax], vb = h->xy[2 * b + ax];
+      return va < vb || (va == vb && a < b);
+    });
+    const int64_t ncl = (tot + cap - 1) / cap;
+    const int64_t target = cap * ((ncl + 1) / 2);
+    int sp = lo;
+    int64_t acc = 0;
+    while (sp < hi - 1 && acc + K(order[sp]) <= target) acc += K(order[sp++]);
+    if (sp == lo) sp = lo + 1;
+    rec(lo, sp);
+    rec(sp, hi);
+  };
+  rec(0, n);
+}
+
+// Build the cluster block-Jacobi preconditioner (once per build).
+int build_precond(ems_handle *h, hipStream_t st) {
+  if (h->pc_built) return EMS_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int> order, cptr;
+  kd_clusters(h, h->pc_cap, order, cptr);
+  const int nc = (int)cptr.size() - 1;
+  std::vector<int> rptr(nc + 1, 0), rows, nb(nc);
+  std::vector<int64_t> ioff(nc + 1, 0);
+  rows.reserve((size_t)h->ncoef);
+  int bmax = 0;
+  for (int c = 0; c < nc; ++c) {
+    for (int k = cptr[c]; k < cptr[c + 1]; ++k) {
+      const int m = order[k];
+      for (int64_t g = h->off[m]; g < h->off[m + 1]; ++g) rows.push_back((int)g);
+    }
+    rptr[c + 1] = (int)rows.size();
+    nb[c] = rptr[c + 1] - rptr[c];
+    bmax = std::max(bmax, nb[c]);
+    ioff[c + 1] = ioff[c] + (int64_t)nb[c] * nb[c];
+  }
+  const int n2 = (bmax + 15) / 16 * 16;
+  if (n2 > 512) return fail(h, EMS_ERR_ARG, "a particle block exceeds the cluster size limit");
+  int rc;
+  if ((rc = upload(h, h->d_pc_rptr, rptr.data(), rptr.size()))) return rc;
+  if ((rc = upload(h, h->d_pc_rows, rows.data(), rows.size()))) return rc;
+  if ((rc = upload(h, h->d_pc_nb, nb.data(), nb.size()))) return rc;
+  if ((rc = upload(h, h->d_pc_ioff, ioff.data(), ioff.size()))) return rc;
+  dfree(h->d_pc_inv);
+  HIPCHK(h, hipMalloc(&h->d_pc_inv, sizeof(float2) * (size_t)std::max<int64_t>(1, ioff[nc])));
+  // working matrices [B_c | I] in batches
+  const int64_t mstride = (int64_t)n2 * 2 * n2;
+  const size_t mbytes = sizeof(double2) * (size_t)mstride;
+  size_t fr = 0, tot = 0;
+  HIPCHK(h, hipMemGetInfo(&fr, &tot));
+  const size_t budget = std::min<size_t>((size_t)4 << 30, (size_t)(0.3 * (double)fr));
+  const int bcnt = (int)std::max<size_t>(1, std::min<size_t>((size_t)nc, budget / mbytes));
+  double2 *W = nullptr;
+  int *info = nullptr, *dpairs = nullptr;
+  std::vector<int> pairs, hinfo(bcnt);
+  int rcode = EMS_OK;
+  auto cleanup = [&]() {
+    dfree(W);
+    dfree(info);
+    dfree(dpairs);
+  };
+  size_t pairs_cap = 0;
+  if (hipMalloc(&W, mbytes * bcnt) != hipSuccess || hipMalloc(&info, sizeof(int) * bcnt) != hipSuccess) {
+    cleanup();
+    return fail(h, EMS_ERR_OOM, "no device memory for the preconditioner's working matrices");
+  }
+  for (int c0 = 0; c0 < nc && rcode == EMS_OK; c0 += bcnt) {
+    const int cnt = std::min(bcnt, nc - c0);
+    pairs.clear();
+    for (int c = c0; c < c0 + cnt; ++c) {
+      int ro = 0;
+      for (int a = cptr[c]; a < cptr[c + 1]; ++a) {
+        const int m = order[a];
+        int co = 0;
+        for (int b = cptr[c]; b < cptr[c + 1]; ++b) {
+          const int l = order[b];
+          if (l != m) {
+            pairs.push_back(c - c0);
+            pairs.push_back(m);
+            pairs.push_back(l);
+            pairs.push_back(ro);
+            pairs.push_back(co);
+          }
+          co += (int)(h->off[l + 1] - h->off[l]);
+        }
+        ro += (int)(h->off[m + 1] - h->off[m]);
+      }
+    }
+    if (pairs.size() > pairs_cap) {
+      dfree(dpairs);
+      pairs_cap = pairs.size();
+      if (hipMalloc(&dpairs, sizeof(int) * pairs_cap) != hipSuccess) {
+        rcode = fail(h, EMS_ERR_OOM, "no device memory for the cluster pair list");
+        break;
+      }
+    }
+    hipError_t e = hipMemsetAsync(info, 0, sizeof(int) * cnt, st);
+    if (e == hipSuccess && !pairs.empty())
+      e = hipMemcpyAsync(dpairs, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice, st);
+    ems::PcBatch bt;
+    bt.c0 = c0;
+    bt.cnt = cnt;
+    bt.pairs = dpairs;
+    bt.npairs = (int)(pairs.size() / 5);
+    if (e == hipSuccess) e = ems::launch_pc_factor_batch(h, bt, W, n2, mstride, info, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hinfo.data(), info, sizeof(int) * cnt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      rcode = fail(h, EMS_ERR_HIP, std::string("preconditioner set-up: ") + hipGetErrorString(e));
+      break;
+    }
+    for (int i = 0; i < cnt; ++i)
+      if (hinfo[i]) rcode = fail(h, EMS_ERR_NUMERIC, "singular cluster block in the preconditioner");
+  }
+  cleanup();
+  if (rcode != EMS_OK) return rcode;
+  h->pc_nc = nc;
+  h->pc_n2 = n2;
+  h->pc_bmax = bmax;
+  h->pc_store = ioff[nc];
+  h->pc_built = true;
+  h->pc_setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return EMS_OK;
+}
+
+int ensure_pcz(ems_handle *h, int nrhs) {
+  const size_t bytes = sizeof(double2) * 2 * (size_t)nrhs * h->ncoef;
+  if (h->pcz_bytes >= bytes) return EMS_OK;
+  dfree(h->d_pcz);
+  h->pcz_bytes = 0;
+  HIPCHK(h, hipMalloc(&h->d_pcz, bytes));
+  h->pcz_bytes = bytes;
   return EMS_OK;
 }
 
@@ -1328,12 +1504,18 @@ struct Givens {
   std::vector<std::vector<cd>> H;  // columns
 };
 
-// Restarted GMRES on nrhs systems in lock-step; op(x, y) applies the operator
-// to nrhs vectors.  x is updated in place (initial guess taken as given).
-template <typename Op>
-int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, double tol,
-              int restart, int maxit, bool x_zero, hipStream_t st, int &iters, double &relres,
-              std::vector<double> &bnorm_out) {
+// Restarted GMRES on nrhs systems in lock-step.  op(x, y) applies the
+// operator A to nrhs vectors; with prec (use_prec) the Krylov space is built
+// on A M^{-1} (right preconditioning: the residual stays that of A) and the
+// update is x += M^{-1} V y.  Every sweep starts from the true residual
+// b - A x, so the stopping test is always on a computed residual.  x is
+// updated in place (initial guess taken as given; x_zero skips the first
+// product).  The estimated relative residual of every iteration (largest over
+// the systems, times hist_scale) is appended to h->hist.
+template <typename Op, typename Prec>
+int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
+              int nrhs, double tol, int restart, int maxit, bool x_zero, hipStream_t st,
+              int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale) {
   const int64_t n = h->ncoef;
   const size_t vec = (size_t)n;
   restart = std::max(1, std::min(restart, maxit));
@@ -1348,6 +1530,7 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
   }
   int rc = ensure_tmp(h, sizeof(double2) * 2 * nrhs * vec);
   if (rc) return rc;
+  if (use_prec && (rc = ensure_pcz(h, nrhs))) return rc;
   // d_h, d_h2 [restart + 2] each, the norm result (restart + 2 + 8 slots
   // before the partials), then up to restart + 1 reduced vectors of
   // kRedBlocks complex partials each
@@ -1355,6 +1538,7 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
                                         (size_t)(restart + 1) * ems::kRedBlocks));
   if (rc) return rc;
   double2 *W = h->d_tmp;                 // [nrhs][n] operator output
+  double2 *Z = h->d_pcz, *Z2 = h->d_pcz ? h->d_pcz + (size_t)nrhs * vec : nullptr;
   double2 *d_h = reinterpret_cast<double2 *>(h->d_red);  // device coefficients
   double2 *d_h2 = d_h + (restart + 2);
   double *d_nrm = reinterpret_cast<double *>(d_h2 + (restart + 2));
@@ -1369,12 +1553,12 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
     HIPCHK(h, hipStreamSynchronize(st));
   }
   bnorm_out = bnorm;
-  std::vector<bool> done(nrhs, false);
   std::vector<double> rel(nrhs, 0.0);
   iters = 0;
+  relres = 0.0;
   bool first = true;
   while (true) {
-    // residual r0 = b - A x (x = 0 on the first sweep when x_zero)
+    // true residual W = b - A x (x = 0 on the first sweep when x_zero)
     if (first && x_zero) {
       for (int r = 0; r < nrhs; ++r)
         HIPCHK(h, hipMemcpyAsync(W + r * vec, b + r * vec, sizeof(double2) * vec,
@@ -1383,7 +1567,6 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
       rc = op(x, W);
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r) {
-        // W = b - A x
         HIPCHK(h, ems::launch_scale(W + r * vec, n, -1.0, st));
         HIPCHK(h, ems::launch_axpy(W + r * vec, b + r * vec, n, 1.0, st));
       }
@@ -1393,18 +1576,20 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
     std::vector<int> kk(nrhs, 0);
     std::vector<bool> active(nrhs, false);
     bool any = false;
+    relres = 0.0;
     for (int r = 0; r < nrhs; ++r) {
       HIPCHK(h, ems::launch_norm2(W + r * vec, n, d_nrm, scratch, st));
       HIPCHK(h, hipMemcpyAsync(&beta[r], d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(h, hipStreamSynchronize(st));
       rel[r] = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
-      if (bnorm[r] == 0.0 || rel[r] <= tol) {
-        done[r] = true;
-        continue;
-      }
-      done[r] = false;
+      relres = std::max(relres, rel[r]);
+      if (bnorm[r] == 0.0 || rel[r] <= tol) continue;
       active[r] = true;
       any = true;
+    }
+    if (!any || iters >= maxit) break;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!active[r]) continue;
       G[r].g.assign(restart + 1, cd(0.0));
       G[r].g[0] = beta[r];
       G[r].cs.assign(restart, 0.0);
@@ -1412,11 +1597,16 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
       G[r].H.assign(restart, std::vector<cd>(restart + 1, 0.0));
       HIPCHK(h, ems::launch_copy_scaled(W + r * vec, Vk(0, r), n, 1.0 / beta[r], st));
     }
-    if (!any) break;
     int k = 0;
     for (; k < restart && iters < maxit; ++k) {
-      // W = A V_k (all right-hand sides; inactive ones are ignored)
-      rc = op(Vk(k, 0), W);
+      // W = A V_k, or A M^{-1} V_k (all right-hand sides; inactive ones are ignored)
+      if (use_prec) {
+        rc = prec(Vk(k, 0), Z);
+        if (rc) return rc;
+        rc = op(Z, W);
+      } else {
+        rc = op(Vk(k, 0), W);
+      }
       if (rc) return rc;
       ++iters;
       bool all_done = true;
@@ -1463,12 +1653,18 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
         if (rel[r] <= tol || nrm == 0) active[r] = false;
         else all_done = false;
       }
+      double hmax = 0.0;
+      for (int r = 0; r < nrhs; ++r) hmax = std::max(hmax, rel[r]);
+      h->hist.push_back(hmax * hist_scale);
+      if (h->progress && h->progress_every > 0 && (int)h->hist.size() % h->progress_every == 0)
+        h->progress((int32_t)h->hist.size(), hmax * hist_scale, h->progress_user);
       if (all_done) {
         ++k;
         break;
       }
     }
-    // x += V y for every system that took steps in this sweep
+    // x += V y (or M^{-1} V y) for every system that took steps in this sweep
+    if (use_prec) HIPCHK(h, hipMemsetAsync(Z, 0, sizeof(double2) * vec * nrhs, st));
     for (int r = 0; r < nrhs; ++r) {
       const int kr = kk[r];
       if (kr == 0) continue;
@@ -1482,26 +1678,16 @@ int gmres_run(ems_handle *h, Op op, const double2 *b, double2 *x, int nrhs, doub
       std::vector<double2> yd(kr);
       for (int i = 0; i < kr; ++i) yd[i] = make_double2(y[i].real(), y[i].imag());
       HIPCHK(h, hipMemcpyAsync(d_h, yd.data(), sizeof(double2) * kr, hipMemcpyHostToDevice, st));
-      HIPCHK(h, ems::launch_maccum(Vk(0, r), ldv, kr, d_h, x + r * vec, n, st));
+      HIPCHK(h, ems::launch_maccum(Vk(0, r), ldv, kr, d_h, use_prec ? Z + r * vec : x + r * vec,
+                                   n, st));
       HIPCHK(h, hipStreamSynchronize(st));
     }
-    bool all = true;
-    for (int r = 0; r < nrhs; ++r)
-      if (bnorm[r] > 0 && rel[r] > tol) all = false;
-    if (all || iters >= maxit) break;
-  }
-  // true residual
-  rc = op(x, W);
-  if (rc) return rc;
-  relres = 0.0;
-  for (int r = 0; r < nrhs; ++r) {
-    HIPCHK(h, ems::launch_scale(W + r * vec, n, -1.0, st));
-    HIPCHK(h, ems::launch_axpy(W + r * vec, b + r * vec, n, 1.0, st));
-    double nr = 0;
-    HIPCHK(h, ems::launch_norm2(W + r * vec, n, d_nrm, scratch, st));
-    HIPCHK(h, hipMemcpyAsync(&nr, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(h, hipStreamSynchronize(st));
-    if (bnorm[r] > 0) relres = std::max(relres, nr / bnorm[r]);
+    if (use_prec) {
+      rc = prec(Z, Z2);
+      if (rc) return rc;
+      for (int r = 0; r < nrhs; ++r)
+        if (kk[r] > 0) HIPCHK(h, ems::launch_axpy(x + r * vec, Z2 + r * vec, n, 1.0, st));
+    }
   }
   return EMS_OK;
 }
@@ -1554,34 +1740,54 @@ int ensure_ir(ems_handle *h, int nrhs) {
 }
 
 // GMRES on A (adjoint = false) or A^H, FP64 or mixed (FP32 contractions in an
-// inner GMRES on the residual equation, FP64 outer residual and update).
+// inner GMRES on the residual equation, FP64 outer residual and update), with
+// or without the cluster block-Jacobi right preconditioner (for A^H its
+// adjoint: the conjugate transpose of every block, applied to the clusters).
 int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_solver_opts *o,
                ems_solve_info *info, ems_stream_t stream, bool adjoint) {
   if (!h || !b || !x || !o || nrhs <= 0) return fail(h, EMS_ERR_ARG, "bad solve arguments");
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   if (!(o->tol > 0) || o->maxit <= 0) return fail(h, EMS_ERR_ARG, "need tol > 0 and maxit > 0");
   if (o->precision != 0 && o->precision != 1) return fail(h, EMS_ERR_ARG, "precision must be 0 or 1");
+  if (o->precond != 0 && o->precond != 1) return fail(h, EMS_ERR_ARG, "precond must be 0 or 1");
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vec = (size_t)h->ncoef;
   double2 *X = (double2 *)x;
   const double2 *B = (const double2 *)b;
+  int rc;
+  h->hist.clear();
+  const bool use_prec = o->precond == 1;
+  if (use_prec && (rc = build_precond(h, st))) return rc;
   HIPCHK(h, hipMemsetAsync(X, 0, sizeof(double2) * vec * nrhs, st));
-  const int restart = o->restart > 0 ? o->restart : 200;
+  int restart = o->restart;
+  if (restart <= 0) {
+    // as long as the basis fits in half of the free device memory
+    size_t fr = 0, tot = 0;
+    HIPCHK(h, hipMemGetInfo(&fr, &tot));
+    const size_t have = fr / 2 + h->V_bytes;
+    const size_t per = sizeof(double2) * vec * nrhs;
+    restart = (int)std::max<size_t>(20, std::min<size_t>(5000, have / per - 1));
+  }
   int iters = 0, outer = 1;
   double relres = 0;
-  int rc;
   // the operator never aliases GMRES's internal buffers: it reads a basis
-  // vector or the iterate and writes the work vector
+  // vector, a preconditioned vector or the iterate and writes the work vector
   auto op64 = [&](const double2 *in, double2 *out) {
     return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL, adjoint, st);
   };
   auto op32 = [&](const double2 *in, double2 *out) {
     return apply_impl(h, in, out, nrhs, EMS_APPLY_ALL | EMS_MIXED, adjoint, st);
   };
+  auto pc = [&](const double2 *in, double2 *out) {
+    ems::ProfScope ps(h, "precond_apply", st, 8.0 * (double)h->pc_store * nrhs);
+    HIPCHK(h, ems::launch_pc_apply(h, in, out, nrhs, adjoint, st));
+    return EMS_OK;
+  };
   if (o->precision == 0) {
     std::vector<double> bn;
-    rc = gmres_run(h, op64, B, X, nrhs, o->tol, restart, o->maxit, true, st, iters, relres, bn);
+    rc = gmres_run(h, op64, pc, use_prec, B, X, nrhs, o->tol, restart, o->maxit, true, st, iters,
+                   relres, bn, 1.0);
     if (rc) return rc;
   } else {
     if ((rc = ensure_ir(h, nrhs))) return rc;
@@ -1594,15 +1800,22 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
       if ((rc = residual(h, op64, X, B, R, nrhs, st))) return rc;
       if ((rc = norms(h, R, nrhs, rn, st))) return rc;
       relres = 0;
-      for (int r = 0; r < nrhs; ++r)
+      double rmax = 0, bmax = 0;
+      for (int r = 0; r < nrhs; ++r) {
         if (bn[r] > 0) relres = std::max(relres, rn[r] / bn[r]);
+        rmax = std::max(rmax, rn[r]);
+        bmax = std::max(bmax, bn[r]);
+      }
       if (relres <= o->tol || iters >= o->maxit || outer >= 50) break;
       ++outer;
       int it = 0;
       double rr = 0;
       std::vector<double> tmp;
       HIPCHK(h, hipMemsetAsync(D, 0, sizeof(double2) * vec * nrhs, st));
-      rc = gmres_run(h, op32, R, D, nrhs, itol, restart, o->maxit - iters, true, st, it, rr, tmp);
+      // the inner solve needs no more than the factor still missing
+      const double need = std::max(itol, 0.5 * o->tol / std::max(relres, 1e-300));
+      rc = gmres_run(h, op32, pc, use_prec, R, D, nrhs, need, restart, o->maxit - iters, true, st,
+                     it, rr, tmp, relres);
       if (rc) return rc;
       iters += it;
       for (int r = 0; r < nrhs; ++r)
@@ -1619,11 +1832,56 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
     info->relres = relres;
     info->converged = conv ? 1 : 0;
     info->seconds = secs;
+    info->restart = restart;
+    info->precond_seconds = use_prec ? h->pc_setup_s : 0.0;
   }
   return conv ? EMS_OK : EMS_NOT_CONVERGED;
 }
 
 }  // namespace
+
+extern "C" int ems_set_precond(ems_handle *h, int32_t max_unknowns) {
+  if (!h) return EMS_ERR_ARG;
+  if (max_unknowns == 0) max_unknowns = 512;
+  if (max_unknowns < 1 || max_unknowns > 512)
+    return fail(h, EMS_ERR_ARG, "cluster size must be in [1, 512] unknowns");
+  if (h->pc_cap != max_unknowns) {
+    h->pc_cap = max_unknowns;
+    dfree(h->d_pc_inv);
+    h->pc_built = false;
+  }
+  return EMS_OK;
+}
+
+extern "C" int ems_precond_apply(ems_handle *h, const void *x, void *y, int32_t nrhs,
+                                 int32_t adjoint, int32_t *clusters, int32_t *max_rows,
+                                 double *setup_s, ems_stream_t stream) {
+  if (!h || !x || !y || nrhs <= 0 || x == y) return fail(h, EMS_ERR_ARG, "bad preconditioner arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = build_precond(h, st);
+  if (rc) return rc;
+  HIPCHK(h, ems::launch_pc_apply(h, (const double2 *)x, (double2 *)y, nrhs, adjoint != 0, st));
+  if (clusters) *clusters = h->pc_nc;
+  if (max_rows) *max_rows = h->pc_bmax;
+  if (setup_s) *setup_s = h->pc_setup_s;
+  return EMS_OK;
+}
+
+extern "C" int ems_set_progress(ems_handle *h, ems_progress_fn fn, int32_t every, void *user) {
+  if (!h || (fn && every <= 0)) return fail(h, EMS_ERR_ARG, "progress needs every > 0");
+  h->progress = fn;
+  h->progress_every = fn ? every : 0;
+  h->progress_user = user;
+  return EMS_OK;
+}
+
+extern "C" int ems_solve_history(const ems_handle *h, double *out, int32_t cap, int32_t *count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !out)) return EMS_ERR_ARG;
+  *count = (int32_t)h->hist.size();
+  for (int i = 0; i < cap && i < (int)h->hist.size(); ++i) out[i] = h->hist[i];
+  return EMS_OK;
+}
 
 extern "C" int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs,
                          const ems_solver_opts *o, ems_solve_info *info, ems_stream_t stream) {

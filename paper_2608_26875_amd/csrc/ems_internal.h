@@ -261,6 +261,26 @@ struct ems_handle {
   // mixed-precision refinement: residual and correction [nrhs][ncoef]
   double2 *d_irR = nullptr, *d_irD = nullptr;
   size_t ir_bytes = 0;
+
+  // cluster block-Jacobi preconditioner (built by the first solve or
+  // ems_precond_apply after a build): clusters of at most pc_cap unknowns,
+  // rows of cluster c = global coefficient indices d_pc_rows[d_pc_rptr[c] ..
+  // d_pc_rptr[c+1]), inverse blocks complex64 column-major at d_pc_ioff[c]
+  int pc_cap = 512;
+  bool pc_built = false;
+  int pc_nc = 0, pc_n2 = 0, pc_bmax = 0;
+  int *d_pc_rptr = nullptr, *d_pc_rows = nullptr, *d_pc_nb = nullptr;
+  int64_t *d_pc_ioff = nullptr;
+  float2 *d_pc_inv = nullptr;
+  int64_t pc_store = 0;          // complex64 entries of the inverse store
+  double pc_setup_s = 0.0;
+  double2 *d_pcz = nullptr;      // preconditioned vectors [2][nrhs][ncoef]
+  size_t pcz_bytes = 0;
+  // estimated relative residual per iteration of the last solve
+  std::vector<double> hist;
+  ems_progress_fn progress = nullptr;
+  int progress_every = 0;
+  void *progress_user = nullptr;
 };
 
 namespace ems {
@@ -380,5 +400,23 @@ struct MfsBatch {
 hipError_t launch_mfs_smatrices(const MfsBatch &b, int i0, int cnt, double2 *W, int64_t mstride,
                                 double2 *E, int64_t estride, int *info, double2 *S,
                                 hipStream_t st);
+// Batched LU with partial pivoting and back substitution of cnt matrices
+// [A | B] (n2 rows, n2 + nrhs columns, column-major, stride mstride): B is
+// overwritten by A^{-1} B; info[i] = 1 when a pivot of matrix i is zero.
+hipError_t launch_lu_solve_batch(double2 *W, int n2, int64_t mstride, int cnt, int nrhs,
+                                 int *info, hipStream_t st);
+
+// Cluster block-Jacobi preconditioner (precond.hip).  A batch is the clusters
+// c0 .. c0 + cnt - 1; pairs[5 k ..] = {matrix in the batch, m, l, row offset
+// of m, column offset of l} for every ordered pair m != l of its clusters.
+struct PcBatch {
+  int c0 = 0, cnt = 0;
+  const int *pairs = nullptr;
+  int npairs = 0;
+};
+hipError_t launch_pc_factor_batch(const ems_handle *h, const PcBatch &bt, double2 *W, int n2,
+                                  int64_t mstride, int *info, hipStream_t st);
+hipError_t launch_pc_apply(const ems_handle *h, const double2 *x, double2 *y, int nrhs,
+                           bool adjoint, hipStream_t st);
 
 }  // namespace ems

@@ -19,6 +19,7 @@
 // coefficients staged in LDS.
 #include "dev.h"
 #include "ems_internal.h"
+#include "graf_sym.h"
 
 namespace ems {
 
@@ -36,38 +37,6 @@ __device__ __forceinline__ void cfma_any(double2 &a, double2 x, double2 y) { cfm
 __device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(a, x, y); }
 __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
-
-// Toeplitz symbol of one pair and wave number: t[2 PM + nu] = H_nu(k d)
-// e^{-i nu (th - pi)} for |nu| <= 2 PM, (d, th) the polar form of (dx, dy),
-// Hankel functions by forward recurrence from H_0, H_1 (stable because
-// |Y_nu| dominates).
-template <int PM, typename T, typename Cvt>
-__device__ __forceinline__ void graf_symbol(double dx, double dy, double k, T *t, Cvt cvt) {
-  const double d = sqrt(dx * dx + dy * dy);
-  const double th = atan2(dy, dx);
-  const double z = k * d;
-  double sn, cs;
-  sincos(th, &sn, &cs);
-  const double2 e1 = make_double2(-cs, sn);  // e^{-i (th - pi)}
-  double2 hm = make_double2(j0(z), y0(z));
-  double2 h = make_double2(j1(z), y1(z));
-  t[2 * PM] = cvt(hm);
-  double2 ph = e1;
-  t[2 * PM + 1] = cvt(cmul(h, ph));
-  // t_{-nu} = (-1)^nu H_nu conj(e^{-i nu (th - pi)})
-  t[2 * PM - 1] = cvt(cscale(cmul(h, cconj(ph)), -1.0));
-  const double iz = 2.0 / z;
-#pragma unroll
-  for (int nu = 2; nu <= 2 * PM; ++nu) {
-    const double2 hn = csub(cscale(h, (nu - 1) * iz), hm);
-    hm = h;
-    h = hn;
-    ph = cmul(ph, e1);
-    t[2 * PM + nu] = cvt(cmul(h, ph));
-    const double sg = (nu & 1) ? -1.0 : 1.0;
-    t[2 * PM - nu] = cvt(cscale(cmul(h, cconj(ph)), sg));
-  }
-}
 
 template <int PM, bool MIXED, int RB, bool STORED>
 __global__ __launch_bounds__(128) void graf_direct_kernel(

@@ -1,5 +1,5 @@
-// S-matrix apply and the final combination of the operator (Section 4.2 and
-// 4.2: y_m = x_m - S_m (T_free x + T_refl x)_m), the plane-wave right-hand
+// S-matrix apply and the final combination of the operator (Sections 4.2 and
+// 5.2: y_m = x_m - S_m (T_free x + T_refl x)_m), the plane-wave right-hand
 // side (Section 7.3), and the vector kernels of the GMRES driver.
 //
 // The S store is packed per particle column-major (S^T row-major), so the

@@ -406,7 +406,7 @@ int reflection(cd xi, const Media &md, cd R[4]) {
 }
 
 // The four continuity conditions (u_x, u_y, t_xy, t_yy at y = 0, Section
-// 2.2) for potentials at one xi.  Unknowns: host downgoing P, S (e^{+s y})
+// 3.2) for potentials at one xi.  Unknowns: host downgoing P, S (e^{+s y})
 // and substrate upgoing P, S (e^{-s_b y}); M = [P_h(+s_p), S_h(+s_s),
 // -P_b(-s_pb), -S_b(-s_sb)], X = M^{-1} B for the two columns of B.
 static int interface_solve(cd xi, const cd s4[4], const Media &md, const cd B[4][2],

@@ -285,14 +285,16 @@ __global__ __launch_bounds__(128) void mfs_rhs_kernel(ShapeArgs g, int i0, int N
 }
 
 // Blocked LU with partial pivoting (pivot = largest |Re| + |Im|, ties to the
-// lower row index) of [A | B], one workgroup of 512 lanes per particle, lane
+// lower row index) of [A | B], one workgroup of 512 lanes per matrix, lane
 // r = row r.  The L factor's columns left of the panel are never read again
 // (B already carries L^{-1} P), so row swaps are applied to the columns right
-// of the panel only.  info[m] is set when a pivot is exactly zero.
+// of the panel only.  info[m] is set when a pivot is exactly zero.  B has
+// fixed_rhs columns, or 2 (2 p + 1) (the particle's incident basis) when
+// fixed_rhs is 0.
 __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ W, int n2,
                                                          int64_t mstride,
                                                          const int *__restrict__ p, int i0,
-                                                         int *__restrict__ info) {
+                                                         int *__restrict__ info, int fixed_rhs) {
   __shared__ double2 urow[kNB], krow[kNB];
   __shared__ double2 L11[kNB][kNB];
   __shared__ double2 Us[kCC][kNB];
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
   __shared__ int redi[kLuLanes / 64];
   const int mloc = blockIdx.x;
   double2 *A = W + (int64_t)mloc * mstride;
-  const int ncol = n2 + 2 * (2 * p[i0 + mloc] + 1);
+  const int ncol = n2 + (fixed_rhs > 0 ? fixed_rhs : 2 * (2 * p[i0 + mloc] + 1));
   const int r = threadIdx.x, lane = r & 63, wv = r >> 6;
   for (int k0 = 0; k0 < n2; k0 += kNB) {
     double2 pr[kNB];
@@ -479,12 +481,12 @@ __global__ __launch_bounds__(kLuLanes) void mfs_lu_kernel(double2 *__restrict__ 
 __global__ __launch_bounds__(kLuLanes) void mfs_backsolve_kernel(double2 *__restrict__ W, int n2,
                                                                 int64_t mstride,
                                                                 const int *__restrict__ p,
-                                                                int i0) {
+                                                                int i0, int fixed_rhs) {
   __shared__ double2 Ub[kBB][kBB];
   __shared__ double2 yb[kBB][kRC];
   const int mloc = blockIdx.x;
   double2 *A = W + (int64_t)mloc * mstride;
-  const int nr = 2 * (2 * p[i0 + mloc] + 1);
+  const int nr = fixed_rhs > 0 ? fixed_rhs : 2 * (2 * p[i0 + mloc] + 1);
   const int r = threadIdx.x;
   for (int c0 = 0; c0 < nr; c0 += kRC) {
     const int nc = min(kRC, nr - c0);
@@ -586,6 +588,16 @@ __global__ __launch_bounds__(256) void mfs_project_kernel(const double2 *__restr
 
 }  // namespace
 
+hipError_t launch_lu_solve_batch(double2 *W, int n2, int64_t mstride, int cnt, int nrhs,
+                                 int *info, hipStream_t st) {
+  if (n2 > kLuLanes || n2 % kNB != 0 || n2 % kBB != 0 || nrhs <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mfs_lu_kernel, dim3(cnt), dim3(kLuLanes), 0, st, W, n2, mstride, nullptr, 0,
+                     info, nrhs);
+  hipLaunchKernelGGL(mfs_backsolve_kernel, dim3(cnt), dim3(kLuLanes), 0, st, W, n2, mstride,
+                     nullptr, 0, nrhs);
+  return hipGetLastError();
+}
+
 hipError_t launch_mfs_smatrices(const MfsBatch &b, int i0, int cnt, double2 *W, int64_t mstride,
                                 double2 *E, int64_t estride, int *info, double2 *S,
                                 hipStream_t st) {
@@ -600,9 +612,9 @@ hipError_t launch_mfs_smatrices(const MfsBatch &b, int i0, int cnt, double2 *W, 
   hipLaunchKernelGGL(mfs_proj_table_kernel, dim3((N + 127) / 128, cnt), dim3(128), 0, st, g, i0,
                      N, estride, kp, ks, E);
   hipLaunchKernelGGL(mfs_lu_kernel, dim3(cnt), dim3(kLuLanes), 0, st, W, n2, mstride, b.p, i0,
-                     info);
+                     info, 0);
   hipLaunchKernelGGL(mfs_backsolve_kernel, dim3(cnt), dim3(kLuLanes), 0, st, W, n2, mstride, b.p,
-                     i0);
+                     i0, 0);
   const int nrmax = 2 * (2 * kMaxP + 1);
   hipLaunchKernelGGL(mfs_project_kernel, dim3((nrmax * nrmax + 255) / 256, cnt), dim3(256), 0, st,
                      W, E, N, mstride, estride, b.p, b.Soff, i0, S);
