@@ -120,7 +120,8 @@ typedef struct {
   int32_t maxit;     /* total inner iterations                                 */
   int32_t precision; /* 0: FP64 GMRES; 1: FP32 contractions in the inner
                         solve with FP64 iterative refinement                    */
-  double inner_tol;  /* precision 1: relative tolerance of each inner solve    */
+  double inner_tol;  /* precision 1: relative tolerance of each inner solve
+                        (<= 0: 1e-4, above the floor the FP32 products leave) */
   int32_t precond;   /* 0: none; 1: cluster block-Jacobi right preconditioner
                         (ems_set_precond), M^{-H} for the adjoint solve         */
 } ems_solver_opts;
@@ -134,6 +135,7 @@ typedef struct {
   double seconds;      /* wall time of the call, preconditioner set-up included */
   int32_t restart;     /* Krylov dimension used                               */
   double precond_seconds; /* set-up time of the preconditioner (0 if none)    */
+  int32_t reorth;      /* Arnoldi steps that needed a second Gram-Schmidt pass */
 } ems_solve_info;
 
 typedef struct {
@@ -148,6 +150,14 @@ typedef struct {
   double kp, ks, kpb, ksb;
   double somm_kept;     /* fraction of the Sommerfeld contraction work kept by
                            the depth truncation (1 without the tables)        */
+  int32_t mixed_near_fp64; /* 1: the mixed form keeps the direct / near-field
+                              Graf sums in FP64 because their Hankel symbols
+                              |H_nu(kp d)|, |nu| <= 2 p_max, at the closest
+                              pair could exceed 1e30 (FP32 range)             */
+  int32_t mixed_somm_fp64; /* 1: the mixed form runs the tabulated Sommerfeld
+                              contractions in FP64 (no complex64 tables: they
+                              did not fit, or the node powers (-i zeta)^n,
+                              |n| <= p_max, exceed 1e30)                       */
 } ems_build_info;
 
 /* Parts of the operator selected by ems_apply's flags. */
@@ -317,8 +327,12 @@ int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void 
  * systems advanced in lock-step.  b, x device memory [nrhs][n_coeff].
  * precision 0: every apply in FP64.  precision 1 (mixed): iterative
  * refinement, i.e. an FP64 outer residual b - A x and update x += d, with d
- * from an inner GMRES to inner_tol (default 1e-5) whose applies run the
- * contractions in FP32 (EMS_MIXED); tol is met on the FP64 residual.
+ * from an inner GMRES to inner_tol (default 1e-4) whose applies run the
+ * contractions in FP32 (EMS_MIXED); an inner solve also ends when its
+ * estimate gains less than 10 % over 200 iterations (the FP32 products put a
+ * floor under what it can reach); tol is met on the FP64 residual.
+ * precond 1 runs every GMRES (outer and inner) on A M^{-1} with the cluster
+ * block-Jacobi preconditioner (ems_set_precond), built on first use.
  * Returns EMS_NOT_CONVERGED when maxit (total inner iterations) is reached,
  * EMS_ERR_ARG for tol <= 0, maxit <= 0 or another precision.  Synchronous. */
 int ems_solve(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_solver_opts *o,

@@ -90,7 +90,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("relres", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("restart", ctypes.c_int32),
-                ("precond_seconds", ctypes.c_double)]
+                ("precond_seconds", ctypes.c_double), ("reorth", ctypes.c_int32)]
 
 
 class Fmm(ctypes.Structure):
@@ -108,7 +108,8 @@ class BuildInfo(ctypes.Structure):
                 ("q", ctypes.c_int32), ("t_max", ctypes.c_double), ("n_pairs", ctypes.c_int64),
                 ("fmm_levels", ctypes.c_int32), ("fmm_m2l", ctypes.c_int64),
                 ("kp", ctypes.c_double), ("ks", ctypes.c_double), ("kpb", ctypes.c_double),
-                ("ksb", ctypes.c_double), ("somm_kept", ctypes.c_double)]
+                ("ksb", ctypes.c_double), ("somm_kept", ctypes.c_double),
+                ("mixed_near_fp64", ctypes.c_int32), ("mixed_somm_fp64", ctypes.c_int32)]
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p)
@@ -360,6 +361,19 @@ class Operator:
                                                    theta0.ctypes.data))
         self.built = False
 
+    def set_smatrices_packed(self, flat):
+        """S-matrices from one packed array (row-major (4p+2)^2 per particle,
+        the output of shape_smatrices; host or device)."""
+        flat = flat.cpu().numpy() if hasattr(flat, "cpu") else np.asarray(flat)
+        flat = np.ascontiguousarray(flat, dtype=np.complex128)
+        sizes = (4 * self.p.astype(np.int64) + 2) ** 2
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        if flat.size != off[-1]:
+            raise ValueError("packed S does not match the particles' orders")
+        self._S_keep = flat
+        self._check(_lib.ems_set_smatrices(self.h, flat.ctypes.data, off.ctypes.data))
+        self.built = False
+
     def set_smatrices(self, blocks):
         sizes = [b.size for b in blocks]
         off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -543,7 +557,7 @@ class Operator:
                                                     _stream_ptr(stream)))
         return g
 
-    def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=1e-5,
+    def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=0.0,
               stream=None, adjoint=False, precond=0):
         """GMRES on A (or A^H with adjoint=True); precision 1 = mixed iterative
         refinement; precond 1 = cluster block-Jacobi right preconditioner;

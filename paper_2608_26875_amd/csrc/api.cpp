@@ -391,6 +391,8 @@ int check_geometry(ems_handle *h) {
 int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags, bool adjoint,
                hipStream_t st) {
   const bool mixed = (flags & EMS_MIXED) != 0;
+  // FP32 near field unless its Hankel symbols could overflow FP32 (build)
+  const bool mixed_near = mixed && !h->near_fp64;
   const int parts = flags & 15;
   if ((parts & EMS_PART_IDENTITY) && !(parts & EMS_PART_S))
     return fail(h, EMS_ERR_ARG, "EMS_PART_IDENTITY needs EMS_PART_S");
@@ -407,11 +409,11 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
   if (parts & EMS_PART_FREE) {
     if (!h->fmm_on) {
       ems::ProfScope ps(h, "graf_direct", st, h->flops_graf * nrhs);
-      HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed, st));
+      HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, adjoint, mixed_near, st));
     } else if (!adjoint) {
       {
         ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
-        HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, false, mixed, st));
+        HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, false, mixed_near, st));
       }
       HIPCHK(h, ems::launch_fmm(h, src, h->d_free, nrhs, st));
     } else {
@@ -428,7 +430,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
       HIPCHK(h, ems::launch_conj_flip(h, src, h->d_adj1, nrhs, st));
       {
         ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
-        HIPCHK(h, ems::launch_graf_direct(h, h->d_adj1, h->d_adj2, nrhs, false, mixed, st));
+        HIPCHK(h, ems::launch_graf_direct(h, h->d_adj1, h->d_adj2, nrhs, false, mixed_near, st));
       }
       HIPCHK(h, ems::launch_fmm(h, h->d_adj1, h->d_adj2, nrhs, st));
       HIPCHK(h, ems::launch_conj_flip(h, h->d_adj2, h->d_free, nrhs, st));
@@ -1051,6 +1053,7 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   std::vector<double2> xi(q), w(q), sp(q), ss(q), spb(q), ssb(q), R(4 * (size_t)q),
       Tu(4 * (size_t)q), dR(8 * (size_t)q), Vp((size_t)q * ld), Vs((size_t)q * ld);
   const cd I(0.0, 1.0);
+  double vmax = 0.0;
   for (int j = 0; j < q; ++j) {
     const cd x = nt.xi[j];
     cd s4[4];
@@ -1086,7 +1089,11 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
       Vp[(size_t)j * ld + pmb - n] = make_double2(bp.real(), bp.imag());
       Vs[(size_t)j * ld + pmb - n] = make_double2(bs.real(), bs.imag());
     }
+    vmax = std::max({vmax, std::abs(ap), std::abs(as), std::abs(bp), std::abs(bs)});
   }
+  // the FP32 contractions of the mixed form carry these powers in FP32: beyond
+  // 1e30 (low frequency, high order, long tails) they run in FP64 instead
+  h->somm_fp64 = !(vmax < 1e30);
   // packed S store: per particle column-major
   std::vector<double2> St(h->S_host.size());
   for (int m = 0; m < h->n; ++m) {
@@ -1124,6 +1131,37 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
       for (int t = h->fmm.nbr_ptr[m]; t < h->fmm.nbr_ptr[m + 1]; ++t)
         f += 16.0 * (2.0 * h->p[m] + 1.0) * (2.0 * h->p[h->fmm.nbr_idx[t]] + 1.0);
     h->flops_graf = f;
+  }
+  {
+    // The mixed form runs the direct / near-field Graf sums in FP32.  Their
+    // symbols H_nu(k d), |nu| <= 2 pmax, grow like (nu - 1)! (2 / k d)^nu for
+    // small k d; where that passes 1e30 over the pairs the kernel visits (kp d
+    // smallest), FP32 would overflow and the near field stays FP64.
+    double dmin = 1e300;
+    auto dist = [&](int a, int b) {
+      return std::hypot(h->xy[2 * a] - h->xy[2 * b], h->xy[2 * a + 1] - h->xy[2 * b + 1]);
+    };
+    if (h->fmm_on) {
+      for (int m = 0; m < h->n; ++m)
+        for (int t = h->fmm.nbr_ptr[m]; t < h->fmm.nbr_ptr[m + 1]; ++t)
+          dmin = std::min(dmin, dist(m, h->fmm.nbr_idx[t]));
+    } else {
+      for (int m = 0; m < h->n; ++m)
+        for (int l = m + 1; l < h->n; ++l) dmin = std::min(dmin, dist(m, l));
+    }
+    h->near_fp64 = false;
+    if (h->n > 1) {
+      const double x = h->md.kp * dmin;
+      double ym = std::cyl_neumann(0.0, x), y1 = std::cyl_neumann(1.0, x);
+      double ymax = std::max(std::fabs(ym), std::fabs(y1));
+      for (int nu = 1; nu < 2 * h->pmax && ymax < 1e30; ++nu) {
+        const double yn = 2.0 * nu / x * y1 - ym;
+        ym = y1;
+        y1 = yn;
+        ymax = std::max(ymax, std::fabs(yn));
+      }
+      h->near_fp64 = !(ymax < 1e30);
+    }
   }
   if (h->device < 0) return fail(h, EMS_ERR_HIP, "no HIP device (host set-up completed)");
   if ((rc = upload(h, h->d_xy, h->xy.data(), h->xy.size()))) return rc;
@@ -1258,7 +1296,7 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
         dfree(h->d_Edis);
       } else {
         // complex64 copies for the mixed form when they fit as well
-        if (1.5 * gb <= h->etab_budget_gb && 1.5 * gb * 1e9 < 0.6 * (double)fre &&
+        if (!h->somm_fp64 && 1.5 * gb <= h->etab_budget_gb && 1.5 * gb * 1e9 < 0.6 * (double)fre &&
             (hipMalloc(&h->d_Eagg32, sizeof(float2) * half) != hipSuccess ||
              hipMalloc(&h->d_Edis32, sizeof(float2) * half) != hipSuccess)) {
           (void)hipGetLastError();
@@ -1313,6 +1351,8 @@ int ems_get_info(const ems_handle *h, ems_build_info *out) {
   out->kpb = h->md.kpb;
   out->ksb = h->md.ksb;
   out->somm_kept = h->d_Eagg ? h->depth_kept : 1.0;
+  out->mixed_near_fp64 = h->near_fp64 ? 1 : 0;
+  out->mixed_somm_fp64 = (h->d_Eagg && !h->d_Eagg32) ? 1 : 0;
   return EMS_OK;
 }
 
@@ -1512,10 +1552,14 @@ struct Givens {
 // updated in place (initial guess taken as given; x_zero skips the first
 // product).  The estimated relative residual of every iteration (largest over
 // the systems, times hist_scale) is appended to h->hist.
+// stall > 0 (inner solves of the mixed refinement, whose FP32 products put a
+// floor under the reachable residual): a sweep also ends when its estimate
+// fell by less than 10 % over the last `stall` iterations.
 template <typename Op, typename Prec>
 int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
               int nrhs, double tol, int restart, int maxit, bool x_zero, hipStream_t st,
-              int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale) {
+              int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale,
+              int stall = 0) {
   const int64_t n = h->ncoef;
   const size_t vec = (size_t)n;
   restart = std::max(1, std::min(restart, maxit));
@@ -1598,6 +1642,8 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
       HIPCHK(h, ems::launch_copy_scaled(W + r * vec, Vk(0, r), n, 1.0 / beta[r], st));
     }
     int k = 0;
+    std::vector<double> sweep_hist;
+    bool stalled = false;
     for (; k < restart && iters < maxit; ++k) {
       // W = A V_k, or A M^{-1} V_k (all right-hand sides; inactive ones are ignored)
       if (use_prec) {
@@ -1613,18 +1659,28 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
       for (int r = 0; r < nrhs; ++r) {
         if (!active[r]) continue;
         double2 *w = W + r * vec;
-        // CGS2
+        // classical Gram-Schmidt, repeated once when the first pass cancels
+        // more than 30 % of ||w|| ("twice is enough": a second pass then
+        // restores orthogonality to working precision)
+        double nrm0 = 0, nrm = 0;
+        HIPCHK(h, ems::launch_norm2(w, n, d_nrm + 1, scratch, st));
         HIPCHK(h, ems::launch_mdot(Vk(0, r), ldv, k + 1, w, n, d_h, scratch, st));
         HIPCHK(h, ems::launch_mupdate(Vk(0, r), ldv, k + 1, d_h, w, n, st));
-        HIPCHK(h, ems::launch_mdot(Vk(0, r), ldv, k + 1, w, n, d_h2, scratch, st));
-        HIPCHK(h, ems::launch_mupdate(Vk(0, r), ldv, k + 1, d_h2, w, n, st));
         HIPCHK(h, ems::launch_norm2(w, n, d_nrm, scratch, st));
-        std::vector<double2> h1(k + 1), h2(k + 1);
-        double nrm = 0;
+        std::vector<double2> h1(k + 1), h2(k + 1, make_double2(0.0, 0.0));
         HIPCHK(h, hipMemcpyAsync(h1.data(), d_h, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, st));
-        HIPCHK(h, hipMemcpyAsync(h2.data(), d_h2, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipMemcpyAsync(&nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(&nrm0, d_nrm + 1, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipStreamSynchronize(st));
+        if (!(nrm > 0.7 * nrm0)) {
+          ++h->reorth;
+          HIPCHK(h, ems::launch_mdot(Vk(0, r), ldv, k + 1, w, n, d_h2, scratch, st));
+          HIPCHK(h, ems::launch_mupdate(Vk(0, r), ldv, k + 1, d_h2, w, n, st));
+          HIPCHK(h, ems::launch_norm2(w, n, d_nrm, scratch, st));
+          HIPCHK(h, hipMemcpyAsync(h2.data(), d_h2, sizeof(double2) * (k + 1), hipMemcpyDeviceToHost, st));
+          HIPCHK(h, hipMemcpyAsync(&nrm, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(h, hipStreamSynchronize(st));
+        }
         std::vector<cd> col(k + 2);
         for (int i = 0; i <= k; ++i) col[i] = cd(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
         col[k + 1] = nrm;
@@ -1658,7 +1714,11 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
       h->hist.push_back(hmax * hist_scale);
       if (h->progress && h->progress_every > 0 && (int)h->hist.size() % h->progress_every == 0)
         h->progress((int32_t)h->hist.size(), hmax * hist_scale, h->progress_user);
-      if (all_done) {
+      sweep_hist.push_back(hmax);
+      if (stall > 0 && (int)sweep_hist.size() > stall &&
+          hmax > 0.9 * sweep_hist[sweep_hist.size() - 1 - stall])
+        stalled = true;
+      if (all_done || stalled) {
         ++k;
         break;
       }
@@ -1687,6 +1747,22 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
       if (rc) return rc;
       for (int r = 0; r < nrhs; ++r)
         if (kk[r] > 0) HIPCHK(h, ems::launch_axpy(x + r * vec, Z2 + r * vec, n, 1.0, st));
+    }
+    if (stalled) {
+      // report the residual of the stalled sweep's iterate
+      rc = op(x, W);
+      if (rc) return rc;
+      relres = 0.0;
+      for (int r = 0; r < nrhs; ++r) {
+        HIPCHK(h, ems::launch_scale(W + r * vec, n, -1.0, st));
+        HIPCHK(h, ems::launch_axpy(W + r * vec, b + r * vec, n, 1.0, st));
+        double nr = 0.0;
+        HIPCHK(h, ems::launch_norm2(W + r * vec, n, d_nrm, scratch, st));
+        HIPCHK(h, hipMemcpyAsync(&nr, d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        if (bnorm[r] > 0) relres = std::max(relres, nr / bnorm[r]);
+      }
+      break;
     }
   }
   return EMS_OK;
@@ -1757,6 +1833,7 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
   const double2 *B = (const double2 *)b;
   int rc;
   h->hist.clear();
+  h->reorth = 0;
   const bool use_prec = o->precond == 1;
   if (use_prec && (rc = build_precond(h, st))) return rc;
   HIPCHK(h, hipMemsetAsync(X, 0, sizeof(double2) * vec * nrhs, st));
@@ -1792,7 +1869,7 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
   } else {
     if ((rc = ensure_ir(h, nrhs))) return rc;
     double2 *R = h->d_irR, *D = h->d_irD;
-    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-5;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
     std::vector<double> bn, rn;
     if ((rc = norms(h, B, nrhs, bn, st))) return rc;
     outer = 0;
@@ -1815,7 +1892,7 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
       // the inner solve needs no more than the factor still missing
       const double need = std::max(itol, 0.5 * o->tol / std::max(relres, 1e-300));
       rc = gmres_run(h, op32, pc, use_prec, R, D, nrhs, need, restart, o->maxit - iters, true, st,
-                     it, rr, tmp, relres);
+                     it, rr, tmp, relres, 200);
       if (rc) return rc;
       iters += it;
       for (int r = 0; r < nrhs; ++r)
@@ -1833,6 +1910,7 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
     info->converged = conv ? 1 : 0;
     info->seconds = secs;
     info->restart = restart;
+    info->reorth = h->reorth;
     info->precond_seconds = use_prec ? h->pc_setup_s : 0.0;
   }
   return conv ? EMS_OK : EMS_NOT_CONVERGED;

@@ -212,6 +212,8 @@ struct ems_handle {
   double2 *d_dis = nullptr;      // [nrhs][dis_chunks][ncoef] partial local coefficients
   double2 *d_free = nullptr;     // [nrhs][ncoef]
   int64_t n_pairs = 0;
+  bool near_fp64 = false;        // mixed form keeps the near field in FP64 (FP32 range)
+  bool somm_fp64 = false;        // mixed form keeps the Sommerfeld contractions in FP64
   // algorithmic flops per right-hand side (complex multiply-add = 8)
   double flops_graf = 0.0;   // direct Graf sum over the pairs the kernel visits
   double flops_s = 0.0;      // S multiply, 8 sum (4 p_m + 2)^2
@@ -278,6 +280,7 @@ struct ems_handle {
   size_t pcz_bytes = 0;
   // estimated relative residual per iteration of the last solve
   std::vector<double> hist;
+  int reorth = 0;                // second Gram-Schmidt passes in the last solve
   ems_progress_fn progress = nullptr;
   int progress_every = 0;
   void *progress_user = nullptr;

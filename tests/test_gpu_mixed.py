@@ -103,3 +103,28 @@ def test_mixed_fmm_close_to_fp64():
             e = rel(z32, z64)
             print("mixed fmm", adjoint, flags, e, flush=True)
             assert 1e-10 < e <= TOL_MIXED, (adjoint, flags, e)
+
+
+def test_mixed_near_field_stays_fp64_where_fp32_would_overflow():
+    """Order 16 at a low frequency (kp d of the closest pair below 1): the
+    Graf symbols H_nu(kp d), |nu| <= 32, pass FP32's range, so the build keeps
+    the mixed form's direct Graf sum in FP64 (its free part is the FP64 one,
+    bit for bit); the Sommerfeld node powers (-i zeta)^16 pass it as well
+    (|zeta| ~ 2 t_max / kp ~ 1e2), so the contractions stay FP64 too: the
+    mixed apply stays finite and within the mixed tolerance of FP64.  At the
+    benchmark frequency the FP32 paths are kept."""
+    w = W.small_cloud(12, seed=17, p=16, omega=1.0, width=14.0, depth=(1.0, 6.0))
+    op = product_operator(w)
+    info = op.build()
+    assert info["mixed_near_fp64"] == 1 and info["mixed_somm_fp64"] == 1
+    x = to_gpu(W.random_coeffs(w.n_coeff, 41, nrhs=1))
+    f64 = to_np(op.apply(x, flags=E.EMS_PART_FREE))
+    f32 = to_np(op.apply(x, flags=E.EMS_PART_FREE | E.EMS_MIXED))
+    assert np.array_equal(f32, f64)
+    z64 = to_np(op.apply(x, flags=Z))
+    z32 = to_np(op.apply(x, flags=Z | E.EMS_MIXED))
+    assert np.all(np.isfinite(z32)) and rel(z32, z64) <= TOL_MIXED
+    w2 = W.small_cloud(12, seed=17, p=6, omega=8.0, width=14.0, depth=(1.0, 6.0))
+    op2 = product_operator(w2)
+    i2 = op2.build()
+    assert i2["mixed_near_fp64"] == 0 and i2["mixed_somm_fp64"] == 0
