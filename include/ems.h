@@ -311,6 +311,25 @@ int ems_apply(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags
 int ems_apply_graph(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
                     int32_t adjoint, ems_stream_t stream);
 
+/* Operator apply for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same operator as ems_apply (forward only; flags as there, EMS_MIXED
+ * included; x, y as there), with its per-call workspace (Sommerfeld aggregate
+ * and disaggregate partial sums, reflected amplitudes, free-space output, FMM
+ * expansions) in one static device array of 256 MiB per GPU instead of
+ * handle-owned allocations; nothing is allocated or freed.  The split-K
+ * chunk counts of the Sommerfeld contractions are halved until the workspace
+ * fits; when it does not fit with one chunk each, EMS_ERR_ARG (use fewer
+ * right-hand sides; one right-hand side of the 20000-particle cloud needs
+ * about 60 MB).  The array is shared by every handle and call on that GPU and
+ * keeps the last call's contents; each call clears the part it uses first.
+ * Calls that overlap on one GPU (two streams, two threads) race on it and
+ * must be serialized by the caller.  EMS_ERR_STATE while kernel profiling
+ * (ems_profile) is on.  Results equal ems_apply's up to the order in which
+ * partial sums are added. */
+int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
+                      ems_stream_t stream);
+
 /* Conjugate-transpose apply (same flags; y = x - T^H S^H x for ALL). */
 int ems_apply_adjoint(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
                       ems_stream_t stream);

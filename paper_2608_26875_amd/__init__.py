@@ -162,6 +162,7 @@ def _load():
                                ctypes.POINTER(D), P], I32),
         "ems_solve_history": ([P, ctypes.POINTER(D), I32, ctypes.POINTER(I32)], I32),
         "ems_set_progress": ([P, PROGRESS_FN, I32, P], I32),
+        "ems_apply_noalloc": ([P, P, P, I32, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -183,7 +184,7 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_sommerfeld_depth_cuts",
             "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm", "ems_set_precond", "ems_precond_apply",
-            "ems_solve_history", "ems_set_progress")
+            "ems_solve_history", "ems_set_progress", "ems_apply_noalloc")
 
 
 def lib():
@@ -425,6 +426,16 @@ class Operator:
         f = _lib.ems_apply_adjoint if adjoint else _lib.ems_apply
         self._check(f(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), nrhs,
                       int(flags), _stream_ptr(stream)))
+        return y
+
+    def apply_noalloc(self, x, y, flags=EMS_APPLY_ALL, stream=None):
+        """Forward apply whose workspace is the library's static device array
+        (no allocation); y must be preallocated like x."""
+        nrhs = self._vec_check(x)
+        self._vec_check(y)
+        self._check(_lib.ems_apply_noalloc(self.h, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()), nrhs, int(flags),
+                                           _stream_ptr(stream)))
         return y
 
     def incident(self, waves, stream=None):

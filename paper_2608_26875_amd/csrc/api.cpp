@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 
 #include "ems_internal.h"
@@ -2301,6 +2302,122 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return EMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply without allocation: the per-call workspace of ems_apply
+// (Sommerfeld aggregate partials and reflected amplitudes, disaggregate
+// partials, the free-space output, FMM expansions and task-group partials)
+// lives in one static device array per GPU instead of handle-owned
+// allocations.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) double2 scratch[kScratchBytes / sizeof(double2)];
+
+std::mutex g_scratch_mu;
+std::map<int, double2 *> g_scratch_ptr;  // device -> address of that device's array
+
+__global__ void scratch_fill_zero(double2 *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+// Address of the current device's array, looked up once per device.
+int scratch_address(ems_handle *h, double2 **out) {
+  int dev = 0;
+  HIPCHK(h, hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(h, EMS_ERR_HIP,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(dev, reinterpret_cast<double2 *>(p)).first;
+  }
+  *out = it->second;
+  return EMS_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t nrhs,
+                                 int32_t flags, ems_stream_t stream) {
+  if (!h || !x || !y || nrhs <= 0 || x == y) return fail(h, EMS_ERR_ARG, "bad apply arguments");
+  if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
+  if (h->prof)
+    return fail(h, EMS_ERR_STATE, "kernel profiling creates events: switch it off for this call");
+  double2 *base = nullptr;
+  int rc = scratch_address(h, &base);
+  if (rc) return rc;
+  // workspace layout: the chunk counts of ems_apply, halved until it fits
+  const size_t nc = (size_t)h->ncoef, c16 = sizeof(double2);
+  const int node_tiles = (h->q + 255) / 256, part_tiles = (h->n + 255) / 256;
+  int agg = std::max(1, std::min(std::max(1, h->n / 8),
+                                 (4096 + 2 * nrhs * node_tiles - 1) / (2 * nrhs * node_tiles)));
+  int dis = std::max(1, std::min(std::max(1, h->q / 32),
+                                 (4096 + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
+  auto need = [&](int a, int d, size_t *o) {
+    size_t t = 0;
+    o[0] = t; t += align256(c16 * nrhs * 2 * (size_t)a * h->q);   // aggregate partials
+    o[1] = t; t += align256(c16 * nrhs * 2 * (size_t)h->q);       // reflected amplitudes
+    o[2] = t; t += align256(c16 * nrhs * (size_t)d * nc);         // disaggregate partials
+    o[3] = t; t += align256(c16 * nrhs * nc);                     // free-space output
+    o[4] = o[5] = o[6] = t;
+    if (h->fmm_on) {
+      o[4] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
+      o[5] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
+      o[6] = t; t += align256(c16 * nrhs * (size_t)h->fmm.max_slots * ems::kFmmRows);
+    }
+    return t;
+  };
+  size_t o[7];
+  size_t total = need(agg, dis, o);
+  while (total > kScratchBytes && (dis > 1 || agg > 1)) {
+    if (dis > 1) dis = (dis + 1) / 2;
+    else agg = (agg + 1) / 2;
+    total = need(agg, dis, o);
+  }
+  if (total > kScratchBytes)
+    return fail(h, EMS_ERR_ARG,
+                "apply workspace of " + std::to_string(total) + " bytes exceeds the " +
+                    std::to_string(kScratchBytes) + "-byte static scratch (fewer right-hand sides)");
+  hipStream_t st = (hipStream_t)stream;
+  // whatever an earlier call left there: the partial sums start from zero
+  hipLaunchKernelGGL(scratch_fill_zero, dim3(1024), dim3(256), 0, st, base,
+                     (int64_t)(total / c16));
+  HIPCHK(h, hipGetLastError());
+  char *b = reinterpret_cast<char *>(base);
+  double2 *sv[7] = {h->d_agg, h->d_refl, h->d_dis, h->d_free, h->d_mult, h->d_loc, h->d_fmm_part};
+  const int s_agg = h->agg_chunks, s_dis = h->dis_chunks, s_ws = h->ws_nrhs;
+  h->d_agg = reinterpret_cast<double2 *>(b + o[0]);
+  h->d_refl = reinterpret_cast<double2 *>(b + o[1]);
+  h->d_dis = reinterpret_cast<double2 *>(b + o[2]);
+  h->d_free = reinterpret_cast<double2 *>(b + o[3]);
+  h->d_mult = h->fmm_on ? reinterpret_cast<double2 *>(b + o[4]) : nullptr;
+  h->d_loc = h->fmm_on ? reinterpret_cast<double2 *>(b + o[5]) : nullptr;
+  h->d_fmm_part = (h->fmm_on && h->fmm.max_slots > 0) ? reinterpret_cast<double2 *>(b + o[6])
+                                                      : nullptr;
+  h->agg_chunks = agg;
+  h->dis_chunks = dis;
+  h->ws_nrhs = nrhs;  // the workspace is in place: the apply sizes nothing
+  rc = apply_impl(h, (const double2 *)x, (double2 *)y, nrhs, flags, false, st);
+  h->d_agg = sv[0];
+  h->d_refl = sv[1];
+  h->d_dis = sv[2];
+  h->d_free = sv[3];
+  h->d_mult = sv[4];
+  h->d_loc = sv[5];
+  h->d_fmm_part = sv[6];
+  h->agg_chunks = s_agg;
+  h->dis_chunks = s_dis;
+  h->ws_nrhs = s_ws;
+  return rc;
 }
 
 extern "C" int ems_apply_graph(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t flags,
