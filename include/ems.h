@@ -121,7 +121,7 @@ typedef struct {
   int32_t precision; /* 0: FP64 GMRES; 1: FP32 contractions in the inner
                         solve with FP64 iterative refinement                    */
   double inner_tol;  /* precision 1: relative tolerance of each inner solve
-                        (<= 0: 1e-4, above the floor the FP32 products leave) */
+                        (<= 0: 1e-3, above the floor the FP32 products leave) */
   int32_t precond;   /* 0: none; 1: cluster block-Jacobi right preconditioner
                         (ems_set_precond), M^{-H} for the adjoint solve         */
 } ems_solver_opts;
@@ -346,7 +346,7 @@ int ems_incident(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, void 
  * systems advanced in lock-step.  b, x device memory [nrhs][n_coeff].
  * precision 0: every apply in FP64.  precision 1 (mixed): iterative
  * refinement, i.e. an FP64 outer residual b - A x and update x += d, with d
- * from an inner GMRES to inner_tol (default 1e-4) whose applies run the
+ * from an inner GMRES to inner_tol (default 1e-3) whose applies run the
  * contractions in FP32 (EMS_MIXED); an inner solve also ends when its
  * estimate gains less than 10 % over 200 iterations (the FP32 products put a
  * floor under what it can reach); tol is met on the FP64 residual.

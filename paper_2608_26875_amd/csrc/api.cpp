@@ -272,6 +272,25 @@ void free_device(ems_handle *h) {
     dfree(D.out_base);
   }
   h->fmm_dev.clear();
+  {
+    ems::M2lDev &G = h->m2l_dev;
+    dfree(G.g_P);
+    dfree(G.g_G);
+    dfree(G.g_nb);
+    dfree(G.g_off);
+    dfree(G.g_poff);
+    dfree(G.tile_ptr);
+    dfree(G.tile_box);
+    dfree(G.ent_sym);
+    dfree(G.ent_src);
+    dfree(G.it_g);
+    dfree(G.it_rt);
+    dfree(G.it_tile);
+    dfree(G.it_e0);
+    dfree(G.it_e1);
+    dfree(G.it_slot);
+  }
+  dfree(h->d_m2l_part);
   h->ws_nrhs = 0;
   h->V_bytes = h->tmp_bytes = h->red_bytes = 0;
   dfree(h->d_pc_rptr);
@@ -331,6 +350,9 @@ int ensure_ws(ems_handle *h, int nrhs) {
     if (h->fmm.max_slots > 0)
       HIPCHK(h, hipMalloc(&h->d_fmm_part,
                           sizeof(double2) * (size_t)nrhs * h->fmm.max_slots * ems::kFmmRows));
+    dfree(h->d_m2l_part);
+    if (h->fmm.m2l.part_len > 0)
+      HIPCHK(h, hipMalloc(&h->d_m2l_part, sizeof(double2) * (size_t)nrhs * h->fmm.m2l.part_len));
   }
   h->ws_nrhs = nrhs;
   return EMS_OK;
@@ -416,7 +438,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
         ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
         HIPCHK(h, ems::launch_graf_direct(h, src, h->d_free, nrhs, false, mixed_near, st));
       }
-      HIPCHK(h, ems::launch_fmm(h, src, h->d_free, nrhs, st));
+      HIPCHK(h, ems::launch_fmm(h, src, h->d_free, nrhs, mixed, st));
     } else {
       // reciprocity: T^H v = P conj(T conj(P v))
       const size_t bytes = sizeof(double2) * (size_t)nrhs * h->ncoef;
@@ -433,7 +455,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
         ems::ProfScope ps(h, "graf_near", st, h->flops_graf * nrhs);
         HIPCHK(h, ems::launch_graf_direct(h, h->d_adj1, h->d_adj2, nrhs, false, mixed_near, st));
       }
-      HIPCHK(h, ems::launch_fmm(h, h->d_adj1, h->d_adj2, nrhs, st));
+      HIPCHK(h, ems::launch_fmm(h, h->d_adj1, h->d_adj2, nrhs, mixed, st));
       HIPCHK(h, ems::launch_conj_flip(h, h->d_adj2, h->d_free, nrhs, st));
     }
   }
@@ -1244,19 +1266,45 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
       }
     }
     h->fmm_dev.assign(F.launches.size(), ems::FmmDev());
+    {
+      const ems::M2lPlan &Q = F.m2l;
+      ems::M2lDev &D = h->m2l_dev;
+      if ((rc = upload(h, D.g_P, Q.g_P.data(), Q.g_P.size()))) return rc;
+      if ((rc = upload(h, D.g_G, Q.g_G.data(), Q.g_G.size()))) return rc;
+      if ((rc = upload(h, D.g_nb, Q.g_nb.data(), Q.g_nb.size()))) return rc;
+      if ((rc = upload(h, D.g_off, Q.g_off.data(), Q.g_off.size()))) return rc;
+      if ((rc = upload(h, D.g_poff, Q.g_poff.data(), Q.g_poff.size()))) return rc;
+      if ((rc = upload(h, D.tile_ptr, Q.tile_ptr.data(), Q.tile_ptr.size()))) return rc;
+      if ((rc = upload(h, D.tile_box, Q.tile_box.data(), Q.tile_box.size()))) return rc;
+      if ((rc = upload(h, D.ent_sym, Q.ent_sym.data(), Q.ent_sym.size()))) return rc;
+      if ((rc = upload(h, D.ent_src, Q.ent_src.data(), Q.ent_src.size()))) return rc;
+      if ((rc = upload(h, D.it_g, Q.it_g.data(), Q.it_g.size()))) return rc;
+      if ((rc = upload(h, D.it_rt, Q.it_rt.data(), Q.it_rt.size()))) return rc;
+      if ((rc = upload(h, D.it_tile, Q.it_tile.data(), Q.it_tile.size()))) return rc;
+      if ((rc = upload(h, D.it_e0, Q.it_e0.data(), Q.it_e0.size()))) return rc;
+      if ((rc = upload(h, D.it_e1, Q.it_e1.data(), Q.it_e1.size()))) return rc;
+      if ((rc = upload(h, D.it_slot, Q.it_slot.data(), Q.it_slot.size()))) return rc;
+    }
     static const char *names[] = {"fmm_p2m", "fmm_m2m", "fmm_l2p"};
-    // M2L (+L2L) launches named by tree level, top level first
-    static const char *m2l_names[] = {"fmm_m2l_l2l_0", "fmm_m2l_l2l_1", "fmm_m2l_l2l_2",
-                                      "fmm_m2l_l2l_3", "fmm_m2l_l2l_4", "fmm_m2l_l2l_5",
-                                      "fmm_m2l_l2l_6", "fmm_m2l_l2l_7", "fmm_m2l_l2l_8",
-                                      "fmm_m2l_l2l_9", "fmm_m2l_l2l_10", "fmm_m2l_l2l_11",
-                                      "fmm_m2l_l2l_12"};
+    // M2L (matrix cores) and L2L launches named by tree level, top level 0
+    static const char *m2l_names[] = {"fmm_m2l_0", "fmm_m2l_1", "fmm_m2l_2", "fmm_m2l_3",
+                                      "fmm_m2l_4", "fmm_m2l_5", "fmm_m2l_6", "fmm_m2l_7",
+                                      "fmm_m2l_8", "fmm_m2l_9", "fmm_m2l_10", "fmm_m2l_11",
+                                      "fmm_m2l_12"};
+    static const char *l2l_names[] = {"fmm_l2l_0", "fmm_l2l_1", "fmm_l2l_2", "fmm_l2l_3",
+                                      "fmm_l2l_4", "fmm_l2l_5", "fmm_l2l_6", "fmm_l2l_7",
+                                      "fmm_l2l_8", "fmm_l2l_9", "fmm_l2l_10", "fmm_l2l_11",
+                                      "fmm_l2l_12"};
     int m2l_level = 0;
     for (size_t i = 0; i < F.launches.size(); ++i) {
       ems::FmmLaunch &L = F.launches[i];
-      if (L.in_kind == 0) L.name = names[0];
+      if (L.gemm_level >= 0) {
+        m2l_level = L.gemm_level;
+        L.name = m2l_names[std::min(m2l_level, 12)];
+      } else if (L.in_kind == 0) L.name = names[0];
       else if (L.out_kind == 1) L.name = names[1];
-      else if (L.out_kind == 2) L.name = m2l_names[std::min(m2l_level++, 12)];
+      else if (L.out_kind == 2 && !L.accumulate) L.name = m2l_names[0];  // top level, tasks
+      else if (L.out_kind == 2) L.name = l2l_names[std::min(m2l_level, 12)];
       else L.name = names[2];
       ems::FmmDev &D = h->fmm_dev[i];
       if ((rc = upload(h, D.ptr, L.ptr.data(), L.ptr.size()))) return rc;
@@ -1870,7 +1918,7 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
   } else {
     if ((rc = ensure_ir(h, nrhs))) return rc;
     double2 *R = h->d_irR, *D = h->d_irD;
-    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-3;
     std::vector<double> bn, rn;
     if ((rc = norms(h, B, nrhs, bn, st))) return rc;
     outer = 0;
@@ -2368,15 +2416,16 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
     o[1] = t; t += align256(c16 * nrhs * 2 * (size_t)h->q);       // reflected amplitudes
     o[2] = t; t += align256(c16 * nrhs * (size_t)d * nc);         // disaggregate partials
     o[3] = t; t += align256(c16 * nrhs * nc);                     // free-space output
-    o[4] = o[5] = o[6] = t;
+    o[4] = o[5] = o[6] = o[7] = t;
     if (h->fmm_on) {
       o[4] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
       o[5] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
       o[6] = t; t += align256(c16 * nrhs * (size_t)h->fmm.max_slots * ems::kFmmRows);
+      o[7] = t; t += align256(c16 * nrhs * (size_t)h->fmm.m2l.part_len);
     }
     return t;
   };
-  size_t o[7];
+  size_t o[8];
   size_t total = need(agg, dis, o);
   while (total > kScratchBytes && (dis > 1 || agg > 1)) {
     if (dis > 1) dis = (dis + 1) / 2;
@@ -2393,7 +2442,8 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
                      (int64_t)(total / c16));
   HIPCHK(h, hipGetLastError());
   char *b = reinterpret_cast<char *>(base);
-  double2 *sv[7] = {h->d_agg, h->d_refl, h->d_dis, h->d_free, h->d_mult, h->d_loc, h->d_fmm_part};
+  double2 *sv[8] = {h->d_agg,  h->d_refl, h->d_dis,      h->d_free,
+                    h->d_mult, h->d_loc,  h->d_fmm_part, h->d_m2l_part};
   const int s_agg = h->agg_chunks, s_dis = h->dis_chunks, s_ws = h->ws_nrhs;
   h->d_agg = reinterpret_cast<double2 *>(b + o[0]);
   h->d_refl = reinterpret_cast<double2 *>(b + o[1]);
@@ -2403,6 +2453,8 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
   h->d_loc = h->fmm_on ? reinterpret_cast<double2 *>(b + o[5]) : nullptr;
   h->d_fmm_part = (h->fmm_on && h->fmm.max_slots > 0) ? reinterpret_cast<double2 *>(b + o[6])
                                                       : nullptr;
+  h->d_m2l_part = (h->fmm_on && h->fmm.m2l.part_len > 0) ? reinterpret_cast<double2 *>(b + o[7])
+                                                         : nullptr;
   h->agg_chunks = agg;
   h->dis_chunks = dis;
   h->ws_nrhs = nrhs;  // the workspace is in place: the apply sizes nothing
@@ -2414,6 +2466,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
   h->d_mult = sv[4];
   h->d_loc = sv[5];
   h->d_fmm_part = sv[6];
+  h->d_m2l_part = sv[7];
   h->agg_chunks = s_agg;
   h->dis_chunks = s_dis;
   h->ws_nrhs = s_ws;

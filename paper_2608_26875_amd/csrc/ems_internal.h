@@ -116,6 +116,7 @@ struct FmmLevel {
 constexpr int kFmmRows = 192;
 struct FmmLaunch {
   const char *name = "fmm";
+  int gemm_level = -1;  // >= 0: the matrix-core M2L of that level (both waves), no tasks
   int in_kind = 0, out_kind = 0, accumulate = 0, nout = 0, max_in_P = 0, max_out_P = 0;
   double flops = 0.0;  // 8 (2 P_out + 1)(2 P_in + 1) summed over the tasks, per right-hand side
   std::vector<int> ptr, in_P, sym_L, sgn, out_P, item_out, item_row0;
@@ -123,6 +124,43 @@ struct FmmLaunch {
   int nslot = 0;                                  // partial slots of kFmmRows complex
   std::vector<int> red_out, red_row0, red_slot0, red_g;
   std::vector<int64_t> in_base, sym_base, out_base;
+};
+
+// M2L of every tree level and wave as matrix products on the matrix cores.
+// Product g (one level li, one wave w, order P, N = 2P + 1 rows):
+//   L_b[k] = sum_o sum_j s^o_{j-k} M_{src(b,o)}[j],
+// the Toeplitz matrix of offset o (symbol s^o, shared by every box pair at
+// that offset) times the gathered source multipoles.  The level's boxes,
+// grouped by their position in the parent (the four positions have
+// different interaction lists; the top level is one group), form column
+// tiles of kM2lCols target boxes; a tile's entries are the offsets any of its
+// boxes uses, each with the pool index of s^o_0 and one source box per
+// column (-1: none).  A work item (one wavefront) is 16 rows of one tile over
+// a contiguous group of its entries; with G > 1 groups per tile the items
+// write partial slots that a reduction adds in a fixed order.
+constexpr int kM2lCols = 16;
+struct M2lPlan {
+  // per product g
+  std::vector<int> g_li, g_w, g_P, g_G, g_nb;
+  std::vector<int64_t> g_off, g_poff;   // expansions of (li, w); partial slots (complex)
+  std::vector<double> g_flops;          // 8 (2P+1)^2 per (target, source) pair, per RHS
+  std::vector<double> g_symmax;         // largest |s| of the product's symbols
+  std::vector<int> g_item0;             // items of g: [g_item0[g], g_item0[g+1])
+  // tiles and entries (ids over all products)
+  std::vector<int> tile_ptr, tile_box;  // [ntiles+1], [ntiles * kM2lCols]
+  std::vector<int64_t> ent_sym;         // [entries] pool index of s_0
+  std::vector<int> ent_src;             // [entries * kM2lCols]
+  // work items
+  std::vector<int> it_g, it_rt, it_tile, it_e0, it_e1, it_slot;
+  int64_t part_len = 0;                 // complex elements of the partial slots per RHS
+};
+struct M2lDev {
+  int *g_P = nullptr, *g_G = nullptr, *g_nb = nullptr;
+  int64_t *g_off = nullptr, *g_poff = nullptr;
+  int *tile_ptr = nullptr, *tile_box = nullptr, *ent_src = nullptr;
+  int64_t *ent_sym = nullptr;
+  int *it_g = nullptr, *it_rt = nullptr, *it_tile = nullptr, *it_e0 = nullptr, *it_e1 = nullptr,
+      *it_slot = nullptr;
 };
 
 struct FmmDev {
@@ -142,6 +180,7 @@ struct FmmPlan {
   std::vector<int> nbr_ptr, nbr_idx;
   std::vector<int64_t> part_sym;
   std::vector<FmmLaunch> launches;
+  M2lPlan m2l;
   std::vector<cd> pool;
   int64_t n_m2l = 0;
 };
@@ -225,6 +264,8 @@ struct ems_handle {
   bool fmm_on = false;
   ems::FmmPlan fmm;
   std::vector<ems::FmmDev> fmm_dev;
+  ems::M2lDev m2l_dev;
+  double2 *d_m2l_part = nullptr;  // [nrhs][m2l.part_len] M2L partial slots
   double2 *d_pool = nullptr, *d_mult = nullptr, *d_loc = nullptr;
   double2 *d_fmm_part = nullptr;  // [nrhs][max_slots][kFmmRows] task-group partials
   double2 *d_nsym = nullptr;      // near-pair symbols [pair][2][4 PMb + 1] (optional)
@@ -317,7 +358,8 @@ hipError_t launch_graf_direct(const ems_handle *h, const double2 *x, double2 *ou
                               bool adjoint, bool mixed, hipStream_t st);
 int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err);
 hipError_t launch_near_symbols(ems_handle *h, const int *pair_tgt, hipStream_t st);
-hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs,
+// mixed: the M2L runs on FP32 matrix cores where its symbols fit FP32
+hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs, bool mixed,
                       hipStream_t st);
 hipError_t launch_conj_flip(const ems_handle *h, const double2 *in, double2 *out, int nrhs,
                             hipStream_t st);

@@ -287,57 +287,187 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
       }
     }
   }
-  // M2L (+ L2L from the parent) per level, top down (in = mult / loc, out = loc)
+  // M2L per level, top down, as matrix products on the matrix cores (one
+  // launch marker per level covering both waves), then L2L from the parent
+  // local as a task launch that accumulates onto it (in = loc, out = loc).
   for (int li = 0; li < nl; ++li) {
-    const int id = new_launch(1, 2, 0);
-    FmmLaunch &L = F.launches[id];
     const int nb = (int)F.levels[li].bx.size();
+    // source boxes of every target: all non-adjacent boxes on the top level,
+    // the interaction list (children of the parent's neighbours that are not
+    // neighbours) below it
+    std::vector<std::vector<int>> srcs(nb);
+    for (int b = 0; b < nb; ++b) {
+      const int bx = F.levels[li].bx[b], by = F.levels[li].by[b];
+      if (li == 0) {
+        for (int s = 0; s < nb; ++s)
+          if (std::max(std::abs(F.levels[li].bx[s] - bx), std::abs(F.levels[li].by[s] - by)) > 1)
+            srcs[b].push_back(s);
+      } else {
+        const int pbx = bx >> 1, pby = by >> 1;
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int ex = 0; ex < 2; ++ex)
+              for (int ey = 0; ey < 2; ++ey) {
+                const int sx = 2 * (pbx + dx) + ex, sy = 2 * (pby + dy) + ey;
+                if (std::max(std::abs(sx - bx), std::abs(sy - by)) <= 1) continue;
+                auto it = index[li].find({sx, sy});
+                if (it != index[li].end()) srcs[b].push_back(it->second);
+              }
+      }
+      F.n_m2l += 2 * (int64_t)srcs[b].size();
+    }
+    // column tiles: boxes grouped by position in the parent (one group on
+    // the top level), row-major order inside a group
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    auto cls = [&](int b) {
+      return li == 0 ? 0 : (F.levels[li].bx[b] & 1) + 2 * (F.levels[li].by[b] & 1);
+    };
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      const int ca = cls(a), cb = cls(b);
+      if (ca != cb) return ca < cb;
+      if (F.levels[li].by[a] != F.levels[li].by[b]) return F.levels[li].by[a] < F.levels[li].by[b];
+      return F.levels[li].bx[a] < F.levels[li].bx[b];
+    });
+    std::vector<std::vector<int>> tiles;
+    for (int k = 0; k < nb;) {
+      std::vector<int> t;
+      const int c0 = cls(order[k]);
+      while (k < nb && (int)t.size() < kM2lCols && cls(order[k]) == c0) t.push_back(order[k++]);
+      tiles.push_back(t);
+    }
+    if (li == 0) {
+      // top level: every non-adjacent pair, nearly every pair its own offset,
+      // so column tiles would be sparse; the Toeplitz task kernel runs it
+      const int id = new_launch(1, 2, 0);
+      FmmLaunch &L = F.launches[id];
+      for (int w = 0; w < 2; ++w) {
+        const double k = w == 0 ? h->md.kp : h->md.ks;
+        const int P = F.levels[li].P[w];
+        std::map<std::pair<int, int>, int64_t> sym_of;
+        for (int b = 0; b < nb; ++b) {
+          double cx, cy;
+          center(li, b, cx, cy);
+          for (int s : srcs[b]) {
+            const std::pair<int, int> key(F.levels[li].bx[s] - F.levels[li].bx[b],
+                                          F.levels[li].by[s] - F.levels[li].by[b]);
+            auto it = sym_of.find(key);
+            int64_t sy;
+            if (it == sym_of.end()) {
+              double sx_, sy_;
+              center(li, s, sx_, sy_);
+              sy = push_hsym(pool, 2 * P, k, std::hypot(cx - sx_, cy - sy_), std::atan2(cy - sy_, cx - sx_));
+              sym_of[key] = sy;
+            } else {
+              sy = it->second;
+            }
+            add_task(L, F.levels[li].off[w] + (int64_t)s * (2 * P + 1), P, sy, 2 * P, 1);
+          }
+          end_output(L, F.levels[li].off[w] + (int64_t)b * (2 * P + 1), P);
+        }
+      }
+      continue;
+    }
+    F.launches.emplace_back();
+    F.launches.back().gemm_level = li;
+    F.launches.back().ptr.push_back(0);
+    M2lPlan &Q = F.m2l;
     for (int w = 0; w < 2; ++w) {
       const double k = w == 0 ? h->md.kp : h->md.ks;
-      const int P = F.levels[li].P[w];
+      const int P = F.levels[li].P[w], N = 2 * P + 1;
+      const int g = (int)Q.g_P.size();
+      Q.g_li.push_back(li);
+      Q.g_w.push_back(w);
+      Q.g_P.push_back(P);
+      Q.g_nb.push_back(nb);
+      Q.g_off.push_back(F.levels[li].off[w]);
+      Q.g_item0.push_back((int)Q.it_g.size());
+      double flops = 0.0, symmax = 0.0;
       std::map<std::pair<int, int>, int64_t> sym_of;
-      std::map<int, int64_t> l2l_of;
-      for (int b = 0; b < nb; ++b) {
-        const int bx = F.levels[li].bx[b], by = F.levels[li].by[b];
-        double cx, cy;
+      auto sym_at = [&](int b, int s) {
+        const std::pair<int, int> key(F.levels[li].bx[s] - F.levels[li].bx[b],
+                                      F.levels[li].by[s] - F.levels[li].by[b]);
+        auto it = sym_of.find(key);
+        if (it != sym_of.end()) return it->second;
+        double cx, cy, sx_, sy_;
         center(li, b, cx, cy);
-        std::vector<int> srcs;
-        if (li == 0) {
-          for (int s = 0; s < nb; ++s)
-            if (std::max(std::abs(F.levels[li].bx[s] - bx), std::abs(F.levels[li].by[s] - by)) > 1)
-              srcs.push_back(s);
-        } else {
-          const int pbx = bx >> 1, pby = by >> 1;
-          for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-              for (int ex = 0; ex < 2; ++ex)
-                for (int ey = 0; ey < 2; ++ey) {
-                  const int sx = 2 * (pbx + dx) + ex, sy = 2 * (pby + dy) + ey;
-                  if (std::max(std::abs(sx - bx), std::abs(sy - by)) <= 1) continue;
-                  auto it = index[li].find({sx, sy});
-                  if (it != index[li].end()) srcs.push_back(it->second);
-                }
-        }
-        for (int s : srcs) {
-          const std::pair<int, int> key(F.levels[li].bx[s] - bx, F.levels[li].by[s] - by);
-          auto it = sym_of.find(key);
-          int64_t sy;
-          if (it == sym_of.end()) {
-            double sx_, sy_;
-            center(li, s, sx_, sy_);
-            sy = push_hsym(pool, 2 * P, k, std::hypot(cx - sx_, cy - sy_), std::atan2(cy - sy_, cx - sx_));
-            sym_of[key] = sy;
-          } else {
-            sy = it->second;
+        center(li, s, sx_, sy_);
+        const int64_t base = push_hsym(pool, 2 * P, k, std::hypot(cx - sx_, cy - sy_),
+                                       std::atan2(cy - sy_, cx - sx_));
+        for (int nu = 0; nu <= 4 * P; ++nu) symmax = std::max(symmax, std::abs(pool[base + nu]));
+        sym_of[key] = base + 2 * P;  // index of s_0
+        return base + 2 * P;
+      };
+      // tiles of this product with their entries
+      std::vector<int> t0s, t1s;  // entry range per tile
+      const int tile_base = (int)Q.tile_ptr.size() == 0 ? 0 : (int)Q.tile_ptr.size() - 1;
+      if (Q.tile_ptr.empty()) Q.tile_ptr.push_back(0);
+      int max_ent = 1;
+      for (const auto &t : tiles) {
+        std::map<std::pair<int, int>, std::vector<int>> ents;
+        for (int c = 0; c < (int)t.size(); ++c) {
+          const int b = t[c];
+          for (int s : srcs[b]) {
+            const std::pair<int, int> key(F.levels[li].bx[s] - F.levels[li].bx[b],
+                                          F.levels[li].by[s] - F.levels[li].by[b]);
+            auto &v = ents[key];
+            if (v.empty()) v.assign(kM2lCols, -1);
+            v[c] = s;
+            flops += 8.0 * N * N;
           }
-          add_task(L, F.levels[li].off[w] + (int64_t)s * (2 * P + 1), P, sy, 2 * P, 1);
-          F.n_m2l += 1;
         }
-        if (li > 0) {
+        for (auto &kv : ents) {
+          int first = -1;
+          for (int c = 0; c < kM2lCols && first < 0; ++c)
+            if (kv.second[c] >= 0) first = c;
+          Q.ent_sym.push_back(sym_at(t[first], kv.second[first]));
+          Q.ent_src.insert(Q.ent_src.end(), kv.second.begin(), kv.second.end());
+        }
+        Q.tile_ptr.push_back((int)Q.ent_sym.size());
+        for (int c = 0; c < kM2lCols; ++c) Q.tile_box.push_back(c < (int)t.size() ? t[c] : -1);
+        max_ent = std::max(max_ent, (int)ents.size());
+      }
+      // entry groups: about two wavefronts per SIMD (1024 SIMDs); more groups
+      // would cost partial slots (G nb N complex per product and RHS)
+      const int nrt = (N + 15) / 16, nt = (int)tiles.size();
+      const int G = std::max(1, std::min(max_ent, (2048 + nrt * nt - 1) / std::max(1, nrt * nt)));
+      Q.g_G.push_back(G);
+      Q.g_poff.push_back(G > 1 ? Q.part_len : 0);
+      if (G > 1) Q.part_len += (int64_t)G * nb * N;
+      for (int ti = 0; ti < nt; ++ti) {
+        const int tid = tile_base + ti;
+        const int e0 = Q.tile_ptr[tid], ne = Q.tile_ptr[tid + 1] - e0;
+        for (int gr = 0; gr < G; ++gr) {
+          const int a0 = e0 + (int)((int64_t)ne * gr / G), a1 = e0 + (int)((int64_t)ne * (gr + 1) / G);
+          for (int rt = 0; rt < nrt; ++rt) {
+            Q.it_g.push_back(g);
+            Q.it_rt.push_back(rt);
+            Q.it_tile.push_back(tid);
+            Q.it_e0.push_back(a0);
+            Q.it_e1.push_back(a1);
+            Q.it_slot.push_back(G > 1 ? gr : -1);
+          }
+        }
+      }
+      Q.g_flops.push_back(flops);
+      Q.g_symmax.push_back(symmax);
+      F.launches.back().flops += flops;
+    }
+    if (li > 0) {
+      const int id = new_launch(1, 2, 1);
+      FmmLaunch &L = F.launches[id];
+      for (int w = 0; w < 2; ++w) {
+        const double k = w == 0 ? h->md.kp : h->md.ks;
+        const int P = F.levels[li].P[w];
+        const int Pp = F.levels[li - 1].P[w];
+        std::map<int, int64_t> l2l_of;
+        for (int b = 0; b < nb; ++b) {
+          const int bx = F.levels[li].bx[b], by = F.levels[li].by[b];
+          double cx, cy;
+          center(li, b, cx, cy);
           // L2L from the parent local (in = loc): marked by sgn = 2
           auto it = index[li - 1].find({bx >> 1, by >> 1});
           const int pb = it->second;
-          const int Pp = F.levels[li - 1].P[w];
           const int pos = (bx & 1) + 2 * (by & 1);
           auto jt = l2l_of.find(pos);
           int64_t s;
@@ -350,8 +480,8 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
             s = jt->second;
           }
           add_task(L, F.levels[li - 1].off[w] + (int64_t)pb * (2 * Pp + 1), Pp, s, Pp + P, 2);
+          end_output(L, F.levels[li].off[w] + (int64_t)b * (2 * P + 1), P);
         }
-        end_output(L, F.levels[li].off[w] + (int64_t)b * (2 * P + 1), P);
       }
     }
   }
@@ -406,6 +536,7 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
     F.max_slots = std::max(F.max_slots, L.nslot);
     for (int t = 0; t < (int)L.in_P.size(); ++t) L.max_in_P = std::max(L.max_in_P, L.in_P[t]);
     for (int o = 0; o < L.nout; ++o) L.max_out_P = std::max(L.max_out_P, L.out_P[o]);
+    if (L.gemm_level >= 0) continue;  // flops from the M2L plan
     L.flops = 0.0;
     for (int o = 0; o < L.nout; ++o)
       for (int t = L.ptr[o]; t < L.ptr[o + 1]; ++t)
@@ -456,6 +587,57 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
       err = "fmm plan: near list out of range";
       return EMS_ERR_NUMERIC;
     }
+  // the matrix-core M2L: boxes, sources, symbols and items inside their arrays
+  {
+    M2lPlan &Q = F.m2l;
+    const int ng = (int)Q.g_P.size();
+    Q.g_item0.push_back((int)Q.it_g.size());
+    const int ntile = Q.tile_ptr.empty() ? 0 : (int)Q.tile_ptr.size() - 1;
+    const int nent = (int)Q.ent_sym.size();
+    if ((int64_t)Q.tile_box.size() != (int64_t)ntile * kM2lCols ||
+        (int64_t)Q.ent_src.size() != (int64_t)nent * kM2lCols) {
+      err = "fmm plan: M2L tile layout";
+      return EMS_ERR_NUMERIC;
+    }
+    for (int g = 0; g < ng; ++g) {
+      const int P = Q.g_P[g], N = 2 * P + 1, nbl = Q.g_nb[g];
+      if (Q.g_off[g] < 0 || Q.g_off[g] + (int64_t)nbl * N > F.exp_len ||
+          (Q.g_G[g] > 1 && Q.g_poff[g] + (int64_t)Q.g_G[g] * nbl * N > Q.part_len)) {
+        err = "fmm plan: M2L product layout";
+        return EMS_ERR_NUMERIC;
+      }
+      for (int it = Q.g_item0[g]; it < Q.g_item0[g + 1]; ++it) {
+        const int tl = Q.it_tile[it];
+        if (Q.it_g[it] != g || tl < 0 || tl >= ntile || Q.it_rt[it] < 0 ||
+            16 * Q.it_rt[it] >= N || Q.it_e0[it] < Q.tile_ptr[tl] ||
+            Q.it_e1[it] > Q.tile_ptr[tl + 1] || Q.it_e0[it] > Q.it_e1[it] ||
+            Q.it_slot[it] >= Q.g_G[g] || (Q.g_G[g] > 1 && Q.it_slot[it] < 0)) {
+          err = "fmm plan: M2L item out of range";
+          return EMS_ERR_NUMERIC;
+        }
+        for (int c = 0; c < kM2lCols; ++c) {
+          const int v = Q.tile_box[(int64_t)tl * kM2lCols + c];
+          if (v < -1 || v >= nbl) {
+            err = "fmm plan: M2L target out of range";
+            return EMS_ERR_NUMERIC;
+          }
+        }
+        for (int e = Q.it_e0[it]; e < Q.it_e1[it]; ++e) {
+          if (Q.ent_sym[e] - 2 * P < 0 || Q.ent_sym[e] + 2 * P >= npool) {
+            err = "fmm plan: M2L symbol out of range";
+            return EMS_ERR_NUMERIC;
+          }
+          for (int c = 0; c < kM2lCols; ++c) {
+            const int v = Q.ent_src[(int64_t)e * kM2lCols + c];
+            if (v < -1 || v >= nbl) {
+              err = "fmm plan: M2L source out of range";
+              return EMS_ERR_NUMERIC;
+            }
+          }
+        }
+      }
+    }
+  }
   return EMS_OK;
 }
 

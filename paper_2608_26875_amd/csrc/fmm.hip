@@ -7,6 +7,8 @@
 // and from the input vector read with scalar loads (see below).  Right-hand
 // sides are taken 8 at a time, the symbol window of a task staged once for
 // all of them.
+#include <algorithm>
+
 #include "dev.h"
 #include "ems_internal.h"
 
@@ -121,6 +123,152 @@ __global__ __launch_bounds__(64) void toep_task_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// M2L on the matrix cores (plan: M2lPlan in fmm.cpp).  One wavefront per work
+// item: rows 16 rt .. 16 rt + 15 of product g, the kM2lCols = 16 target boxes
+// of one tile, over a group of the tile's offsets:
+//   acc[k][b] += sum_j s^o_{j-k} M_{src(b,o)}[j]
+// as 16x16x4 MFMAs (A = the Toeplitz symbol, B = the gathered source
+// multipoles, a complex product four real MFMAs).  Lane (i16, kq) supplies A
+// entry (row i16, K index kq) and B entry (K index kq, box i16); both are
+// read straight from the symbol pool and the multipole array (L1/L2
+// resident), four K steps at a time, the next four loaded before the current
+// ones are multiplied.  No LDS and no barriers: waves run independently and
+// the hardware overlaps their loads.  T = double (FP64 MFMA) or float (FP32
+// MFMA on rounded operands, FP32 accumulation) for the mixed form.
+typedef double m2l_d4 __attribute__((ext_vector_type(4)));
+typedef float m2l_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct M2lM;
+template <> struct M2lM<double> {
+  using Acc = m2l_d4;
+  __device__ static Acc mf(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int kq, int v) { return kq + 4 * v; }
+};
+template <> struct M2lM<float> {
+  using Acc = m2l_f4;
+  __device__ static Acc mf(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int kq, int v) { return 4 * kq + v; }
+};
+
+constexpr int kM2lKB = 4;  // K steps of 4 loaded together
+
+template <typename T>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(
+    int i0, int i1, const int *__restrict__ it_g, const int *__restrict__ it_rt,
+    const int *__restrict__ it_tile, const int *__restrict__ it_e0,
+    const int *__restrict__ it_e1, const int *__restrict__ it_slot,
+    const int *__restrict__ g_P, const int *__restrict__ g_nb, const int64_t *__restrict__ g_off,
+    const int64_t *__restrict__ g_poff, const int *__restrict__ tile_box,
+    const int64_t *__restrict__ ent_sym, const int *__restrict__ ent_src,
+    const double2 *__restrict__ pool, const double2 *__restrict__ mult, double2 *__restrict__ loc,
+    int64_t stride, double2 *__restrict__ part, int64_t pstride) {
+  using Acc = typename M2lM<T>::Acc;
+  const int it = i0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (it >= i1) return;  // whole wavefront; the kernel has no barrier
+  const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
+  const int g = it_g[it], P = g_P[g], N = 2 * P + 1;
+  const int row0 = 16 * it_rt[it], tile = it_tile[it];
+  const int r = blockIdx.y;
+  const double2 *M = mult + (int64_t)r * stride + g_off[g];
+  Acc ar = Acc{0, 0, 0, 0}, ai = Acc{0, 0, 0, 0};
+  const int krow = row0 + i16;  // A row of this lane
+  for (int e = it_e0[it]; e < it_e1[it]; ++e) {
+    const double2 *sym = pool + ent_sym[e];
+    const int sb = ent_src[(int64_t)e * kM2lCols + i16];
+    const double2 *Mb = M + (int64_t)(sb < 0 ? 0 : sb) * N;
+    auto load = [&](int j0, double2 (&a)[kM2lKB], double2 (&b)[kM2lKB]) {
+#pragma unroll
+      for (int u = 0; u < kM2lKB; ++u) {
+        const int jj = j0 + 4 * u + kq;
+        const int nu = min(max(jj - krow, -2 * P), 2 * P);
+        a[u] = sym[nu];
+        b[u] = (sb >= 0 && jj < N) ? Mb[jj] : make_double2(0.0, 0.0);
+      }
+    };
+    double2 ca[kM2lKB], cb[kM2lKB], na[kM2lKB], nb[kM2lKB];
+    load(0, ca, cb);
+    for (int j0 = 0; j0 < N; j0 += 4 * kM2lKB) {
+      if (j0 + 4 * kM2lKB < N) load(j0 + 4 * kM2lKB, na, nb);
+#pragma unroll
+      for (int u = 0; u < kM2lKB; ++u) {
+        const T are = (T)ca[u].x, aim = (T)ca[u].y, bre = (T)cb[u].x, bim = (T)cb[u].y;
+        ar = M2lM<T>::mf(are, bre, ar);
+        ai = M2lM<T>::mf(are, bim, ai);
+        ar = M2lM<T>::mf(aim, -bim, ar);
+        ai = M2lM<T>::mf(aim, bre, ai);
+      }
+#pragma unroll
+      for (int u = 0; u < kM2lKB; ++u) {
+        ca[u] = na[u];
+        cb[u] = nb[u];
+      }
+    }
+  }
+  // accumulator element v: row M2lM::row(kq, v), box column i16
+  const int b = tile_box[(int64_t)tile * kM2lCols + i16];
+  if (b < 0) return;
+  const int slot = it_slot[it];
+  double2 *dst = slot < 0 ? loc + (int64_t)r * stride + g_off[g] + (int64_t)b * N
+                          : part + (int64_t)r * pstride + g_poff[g] +
+                                ((int64_t)slot * g_nb[g] + b) * N;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = row0 + M2lM<T>::row(kq, v);
+    if (k < N) dst[k] = make_double2((double)ar[v], (double)ai[v]);
+  }
+}
+
+// L_b = sum of the G partial slots of product g, in slot order.
+__global__ __launch_bounds__(256) void m2l_reduce_kernel(int G, int nb, int N, int64_t off,
+                                                         int64_t poff, const double2 *__restrict__ part,
+                                                         int64_t pstride, double2 *__restrict__ loc,
+                                                         int64_t stride) {
+  const int64_t tot = (int64_t)nb * N;
+  const int r = blockIdx.y;
+  const double2 *pp = part + (int64_t)r * pstride + poff;
+  double2 *L = loc + (int64_t)r * stride + off;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (int64_t)gridDim.x * 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int g = 0; g < G; ++g) s = cadd(s, pp[(int64_t)g * tot + i]);
+    L[i] = s;
+  }
+}
+
+// M2L of tree level li for both waves; mixed: FP32 matrix cores for the
+// products whose symbols stay inside FP32's range (largest |s| below 1e30).
+hipError_t launch_m2l_mfma(const ems_handle *h, int li, int nrhs, bool mixed, hipStream_t st) {
+  const FmmPlan &F = h->fmm;
+  const M2lPlan &Q = F.m2l;
+  const M2lDev &D = h->m2l_dev;
+  for (size_t g = 0; g < Q.g_P.size(); ++g) {
+    if (Q.g_li[g] != li) continue;
+    const int i0 = Q.g_item0[g], i1 = Q.g_item0[g + 1];
+    if (i1 <= i0) continue;
+    const dim3 grid((unsigned)((i1 - i0 + 3) / 4), nrhs);
+    const bool f32 = mixed && Q.g_symmax[g] < 1e30;
+#define EMS_M2L_LAUNCH(T)                                                                      \
+  hipLaunchKernelGGL((m2l_mfma_kernel<T>), grid, dim3(256), 0, st, i0, i1, D.it_g, D.it_rt,    \
+                     D.it_tile, D.it_e0, D.it_e1, D.it_slot, D.g_P, D.g_nb, D.g_off, D.g_poff, \
+                     D.tile_box, D.ent_sym, D.ent_src, h->d_pool, h->d_mult, h->d_loc,        \
+                     F.exp_len, h->d_m2l_part, Q.part_len)
+    if (f32) EMS_M2L_LAUNCH(float);
+    else EMS_M2L_LAUNCH(double);
+#undef EMS_M2L_LAUNCH
+    if (Q.g_G[g] > 1) {
+      const int N = 2 * Q.g_P[g] + 1;
+      const int64_t tot = (int64_t)Q.g_nb[g] * N;
+      hipLaunchKernelGGL(m2l_reduce_kernel, dim3((unsigned)std::min<int64_t>(2048, (tot + 255) / 256), nrhs),
+                         dim3(256), 0, st, Q.g_G[g], Q.g_nb[g], N, Q.g_off[g], Q.g_poff[g],
+                         h->d_m2l_part, Q.part_len, h->d_loc, F.exp_len);
+    }
+  }
+  return hipGetLastError();
+}
+
 // Sum of the task-group partials of one (output, chunk), in group order.
 __global__ __launch_bounds__(kFmmRows) void fmm_reduce_kernel(
     const int *__restrict__ red_out, const int *__restrict__ red_row0,
@@ -140,12 +288,18 @@ __global__ __launch_bounds__(kFmmRows) void fmm_reduce_kernel(
   else *d = s;
 }
 
-hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs,
+hipError_t launch_fmm(const ems_handle *h, const double2 *x, double2 *fre, int nrhs, bool mixed,
                       hipStream_t st) {
   const FmmPlan &F = h->fmm;
   for (size_t li = 0; li < F.launches.size(); ++li) {
     const FmmLaunch &L = F.launches[li];
     const FmmDev &D = h->fmm_dev[li];
+    if (L.gemm_level >= 0) {
+      ProfScope ps(const_cast<ems_handle *>(h), L.name, st, L.flops * nrhs);
+      const hipError_t e = launch_m2l_mfma(h, L.gemm_level, nrhs, mixed, st);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const double2 *in = L.in_kind == 0 ? x : (L.in_kind == 1 ? h->d_mult : h->d_loc);
     const int64_t in_stride = L.in_kind == 0 ? h->ncoef : F.exp_len;
     double2 *out = L.out_kind == 1 ? h->d_mult : (L.out_kind == 2 ? h->d_loc : fre);

@@ -88,9 +88,10 @@ def test_adjoint_solve_against_dense_oracle(precision):
 
 def test_mixed_fmm_close_to_fp64():
     """2000 particles (FMM on): the mixed form runs the near-field Graf sums
-    in FP32 and keeps the FMM translations in FP64 (their Hankel symbols reach
-    1e39 at the finest M2L level, beyond FP32's range); its free part, forward
-    and adjoint, stays within the mixed tolerance of FP64."""
+    in FP32 and the M2L products of the levels below the top on FP32 matrix
+    cores wherever their Hankel symbols stay below 1e30 (the compressional
+    wave's finest level reaches beyond FP32's range and keeps FP64); its free
+    part, forward and adjoint, stays within the mixed tolerance of FP64."""
     w = W.c1_cloud()
     op = product_operator(w)
     info = op.build()
