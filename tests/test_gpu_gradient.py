@@ -83,3 +83,27 @@ def test_autograd_misfit_against_oracle():
     assert abs(float(J) - J0) <= 1e-10 * J0
     assert np.abs(xy.grad.numpy() - 2.0 * gxy0).max() <= 2e-8 * scale
     assert np.abs(lame.grad.numpy() - 2.0 * gl0).max() <= 2e-8 * scale
+
+
+def test_gradient_with_fmm_against_oracle():
+    """The gradient with the FMM forced on (quadtree of several levels, so the
+    matrix-core M2L, the near lists and the internal order-(p+1) operator all
+    take the FMM path) against the oracle's gradient of the same case, stored
+    by tests/golden/make_goldens.py (grad9)."""
+    import os
+
+    from tests.golden.make_goldens import grad_case
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "grad9_oracle.npz"))
+    w, pts, waves, u_obs = grad_case()
+    op = product_operator(w)
+    op.set_fmm(mode=2, leaf=1, top_boxes=4)
+    info = op.build()
+    assert info["fmm_levels"] >= 2
+    J, gxy, gl, sinfo = op.misfit_gradient(waves, pts, u_obs, tol=1e-12)
+    J0, gxy0, gl0 = float(g["J"]), g["gxy"], g["glame"]
+    print("fmm gradient", info["fmm_levels"], J, J0, np.abs(gxy - gxy0).max(), gl, gl0, flush=True)
+    assert abs(J - J0) <= 1e-10 * J0
+    scale = max(np.abs(gxy0).max(), np.abs(gl0).max())
+    assert np.abs(gxy - gxy0).max() <= 1e-8 * scale
+    assert np.abs(np.asarray(gl) - gl0).max() <= 1e-8 * scale
