@@ -25,8 +25,14 @@ What it computes (paper frame: particles in y < 0, interface y = 0):
 * ``field``        scattered displacement at receivers (Section 5, coupled
                    representation).
 
-Parity unpinned: nothing in this package; each part is pinned by the tests in
-``tests/test_oracle_*.py`` (closed forms, invariants, brute force).
+* ``shapes``       scattering matrices of ellipses, stars and the paper's pear
+                   and starfish by fundamental solutions (Section 4.3).
+
+Each part is pinned by the tests in ``tests/test_oracle_*.py`` (closed forms,
+invariants, brute force), except one: parity unpinned for the non-circular
+S-matrices of ``shapes`` (no closed form; pinned only by the disk limit,
+unitarity, the boundary condition between collocation points, rotation and
+convergence in the point count).
 """
 from . import media, smatrix, graf, interface, sommerfeld, incident, operator, gmres, field  # noqa: F401
 from .media import Media, wavenumbers  # noqa: F401

@@ -24,6 +24,14 @@ Shapes (paper frame, about the centre, turned by theta0): 0 circle of radius a;
 1 ellipse with semi-axes a and a/2; 2 five-arm star r(t) = a (1 + 0.3 cos 5t);
 and the paper's own family r(t) = a1 + a2 cos(a3 t) (Section 7) with
 a2 = a1/4: 3 pear (a3 = 3), 4 starfish (a3 = 5), a = a1.
+
+Parity unpinned for the non-circular shapes: no closed form exists and the
+GPU generator uses the same discretisation, so agreement with it shows two
+implementations of one method agreeing.  What pins this module is the
+closed-form disk (kind 0 against the mode-by-mode boundary conditions), and
+for the other shapes only invariants: I + 2S unitary (lossless particles), the
+boundary condition between the collocation points, the basis rotation of a
+turned shape, and agreement between 256 and 320 collocation points.
 """
 from __future__ import annotations
 
