@@ -149,15 +149,17 @@ typedef struct {
   int64_t fmm_m2l;      /* multipole-to-local translations per apply          */
   double kp, ks, kpb, ksb;
   double somm_kept;     /* fraction of the Sommerfeld contraction work kept by
-                           the depth truncation (1 without the tables)        */
+                           the depth truncation (1 when the vector-ALU
+                           kernels run)                                       */
   int32_t mixed_near_fp64; /* 1: the mixed form keeps the direct / near-field
                               Graf sums in FP64 because their Hankel symbols
                               |H_nu(kp d)|, |nu| <= 2 p_max, at the closest
                               pair could exceed 1e30 (FP32 range)             */
-  int32_t mixed_somm_fp64; /* 1: the mixed form runs the tabulated Sommerfeld
-                              contractions in FP64 (no complex64 tables: they
-                              did not fit, or the node powers (-i zeta)^n,
-                              |n| <= p_max, exceed 1e30)                       */
+  int32_t mixed_somm_fp64; /* 1: the mixed form runs the matrix-core
+                              Sommerfeld contractions in FP64 (the node powers
+                              (-i zeta)^n, |n| <= p_max, exceed 1e30, or
+                              neither complex64 tables nor the register form
+                              are available)                                   */
 } ems_build_info;
 
 /* Parts of the operator selected by ems_apply's flags. */
@@ -282,6 +284,21 @@ typedef struct {
 } ems_fmm;
 
 int ems_set_fmm(ems_handle *h, const ems_fmm *f);
+
+/* How the Sommerfeld contractions obtain the geometric exponentials
+ * E(j, m) = exp(s_w(xi_j) y_m -+ i xi_j x_m) of the aggregate (Section 5.4)
+ * and the disaggregate (Section 5.3).  tabulate 1 (the default): ems_build
+ * tabulates them, 16 B per (node, particle, wave type) for each contraction,
+ * plus complex64 copies for the mixed form and the conjugated tables of the
+ * adjoint, each set only when it fits in a 96 GB budget and 60 % of free
+ * memory.  Every form without tables (tabulate 0: all of them) has the
+ * matrix-core kernels form each exponential in registers from four
+ * coefficients per node and the particle's position (256 B per node and 16 B
+ * per particle; about a quarter slower than reading the tables at 20000
+ * particles, order 15).  Clouds whose phases reach 1e9 rad keep the tables or,
+ * without them, the vector-ALU kernels.  Takes effect at the next ems_build;
+ * EMS_ERR_ARG for another value. */
+int ems_set_exponentials(ems_handle *h, int32_t tabulate);
 
 /* Validate, build the node table and the per-node 2x2 reflection R(xi_j)
  * (the 4x4 interface system of Section 3.2 solved per node), pack the S

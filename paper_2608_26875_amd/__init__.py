@@ -163,6 +163,7 @@ def _load():
         "ems_solve_history": ([P, ctypes.POINTER(D), I32, ctypes.POINTER(I32)], I32),
         "ems_set_progress": ([P, PROGRESS_FN, I32, P], I32),
         "ems_apply_noalloc": ([P, P, P, I32, I32, P], I32),
+        "ems_set_exponentials": ([P, I32], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -184,7 +185,8 @@ EXPORTED = ("ems_create", "ems_destroy", "ems_last_error", "ems_set_media", "ems
             "ems_sommerfeld_depth_cuts",
             "ems_reflection", "ems_profile",
             "ems_profile_read", "ems_set_fmm", "ems_set_precond", "ems_precond_apply",
-            "ems_solve_history", "ems_set_progress", "ems_apply_noalloc")
+            "ems_solve_history", "ems_set_progress", "ems_apply_noalloc",
+            "ems_set_exponentials")
 
 
 def lib():
@@ -585,6 +587,12 @@ class Operator:
         if rc < 0:
             self._check(rc)
         return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+
+    def set_exponentials(self, tabulate=True):
+        """Sommerfeld exponentials tabulated at set-up where they fit
+        (tabulate=True, the default) or formed in registers by the
+        matrix-core kernels (tabulate=False); takes effect at the next build."""
+        self._check(_lib.ems_set_exponentials(self.h, 1 if tabulate else 0))
 
     def set_precond(self, max_unknowns=0):
         """Cluster size of the block-Jacobi preconditioner (unknowns, <= 512)."""

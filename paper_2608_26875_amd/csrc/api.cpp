@@ -220,6 +220,8 @@ void free_device(ems_handle *h) {
   dfree(h->d_Edis32);
   dfree(h->d_EaggA);
   dfree(h->d_EdisA);
+  dfree(h->d_gco);
+  dfree(h->d_xys);
   dfree(h->d_sperm);
   dfree(h->d_kcut);
   dfree(h->d_jr);
@@ -463,7 +465,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
     // one complex multiply-add per (node, coefficient) in each contraction,
     // over the (node, particle) pairs the depth truncation keeps when the
     // tabulated kernels run
-    const bool tab = adjoint ? h->d_EaggA != nullptr : h->d_Eagg != nullptr;
+    const bool tab = ems::somm_mfma_ready(h, adjoint);
     const double fc = 8.0 * (double)h->q * (double)h->ncoef * nrhs * (tab ? h->depth_kept : 1.0);
     {
       ems::ProfScope ps(h, "somm_aggregate", st, fc);
@@ -1330,8 +1332,44 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
   h->p_uniform = true;
   for (int i = 0; i < h->n; ++i)
     if (h->p[i] != h->pmax) h->p_uniform = false;
-  // tabulated exponentials when they fit the budget and free memory
+  // Depth order of the particles and the ranges of the truncated
+  // contractions, the exponentials' node coefficients (register form), and,
+  // unless switched off, the tabulated exponentials of each form that fits
+  // the budget and free memory.  A form without tables forms its
+  // exponentials in registers; without either, the vector-ALU kernels run.
   {
+    ems::DepthCuts dc;
+    h->depth_min = 1e300;
+    for (int i = 0; i < h->n; ++i) h->depth_min = std::min(h->depth_min, -h->xy[2 * i + 1]);
+    ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, h->depth_min, dc);
+    // coefficient-weighted kept fraction: the work of either contraction
+    std::vector<double> pre(h->n + 1, 0.0);
+    for (int i = 0; i < h->n; ++i) pre[i + 1] = pre[i] + 2.0 * h->p[dc.perm[i]] + 1.0;
+    double kept = 0.0;
+    for (size_t k = 0; k < dc.kcut.size(); ++k) kept += pre[dc.kcut[k]];
+    h->depth_kept = kept / ((double)h->q * (double)h->ncoef);
+    if ((rc = upload(h, h->d_sperm, dc.perm.data(), dc.perm.size()))) return rc;
+    if ((rc = upload(h, h->d_kcut, dc.kcut.data(), dc.kcut.size()))) return rc;
+    if ((rc = upload(h, h->d_jr, dc.jr.data(), dc.jr.size()))) return rc;
+  }
+  // the register form reduces the phase s_i y + xi_r x by Cody-Waite for
+  // |phase| < 2^30 (|s| <= |xi| + k); clouds beyond it keep the tables
+  double phase = 0.0;
+  {
+    double xm = 0.0, ym = 0.0, xim = 0.0;
+    for (int i = 0; i < h->n; ++i) {
+      xm = std::max(xm, std::fabs(h->xy[2 * i]));
+      ym = std::max(ym, std::fabs(h->xy[2 * i + 1]));
+    }
+    for (const auto &z : h->nodes.xi) xim = std::max(xim, std::abs(z));
+    phase = (xim + std::max(h->md.kp, h->md.ks)) * ym + xim * xm;
+  }
+  if (phase < 1.0e9) {
+    HIPCHK(h, hipMalloc(&h->d_gco, sizeof(double4) * 8 * (size_t)h->q));
+    HIPCHK(h, hipMalloc(&h->d_xys, sizeof(double2) * (size_t)h->n));
+    HIPCHK(h, ems::launch_gen_coef(h, 0));
+  }
+  if (h->somm_tab) {
     const double gb = 4.0 * (double)h->q * (double)h->n * sizeof(double2) / 1e9;
     size_t fre = 0, tot = 0;
     (void)hipMemGetInfo(&fre, &tot);
@@ -1360,21 +1398,7 @@ int ems_build(ems_handle *h, ems_stream_t stream) {
           dfree(h->d_EaggA);
           dfree(h->d_EdisA);
         }
-        // table rows (aggregate) and columns (disaggregate) in depth order,
-        // with the ranges of the depth truncation
-        ems::DepthCuts dc;
-        h->depth_min = 1e300;
-        for (int i = 0; i < h->n; ++i) h->depth_min = std::min(h->depth_min, -h->xy[2 * i + 1]);
-        ems::depth_cuts(h->nodes, h->md, h->xy, h->pmax, h->somm.depth_cut, h->depth_min, dc);
-        // coefficient-weighted kept fraction: the work of either contraction
-        std::vector<double> pre(h->n + 1, 0.0);
-        for (int i = 0; i < h->n; ++i) pre[i + 1] = pre[i] + 2.0 * h->p[dc.perm[i]] + 1.0;
-        double kept = 0.0;
-        for (size_t k = 0; k < dc.kcut.size(); ++k) kept += pre[dc.kcut[k]];
-        h->depth_kept = kept / ((double)h->q * (double)h->ncoef);
-        if ((rc = upload(h, h->d_sperm, dc.perm.data(), dc.perm.size()))) return rc;
-        if ((rc = upload(h, h->d_kcut, dc.kcut.data(), dc.kcut.size()))) return rc;
-        if ((rc = upload(h, h->d_jr, dc.jr.data(), dc.jr.size()))) return rc;
+        // table rows (aggregate) and columns (disaggregate) in depth order
         HIPCHK(h, ems::launch_etables(h, 0));
       }
     }
@@ -1399,9 +1423,9 @@ int ems_get_info(const ems_handle *h, ems_build_info *out) {
   out->ks = h->md.ks;
   out->kpb = h->md.kpb;
   out->ksb = h->md.ksb;
-  out->somm_kept = h->d_Eagg ? h->depth_kept : 1.0;
+  out->somm_kept = ems::somm_mfma_ready(h, false) ? h->depth_kept : 1.0;
   out->mixed_near_fp64 = h->near_fp64 ? 1 : 0;
-  out->mixed_somm_fp64 = (h->d_Eagg && !h->d_Eagg32) ? 1 : 0;
+  out->mixed_somm_fp64 = (ems::somm_mfma_ready(h, false) && !ems::somm_mfma_fp32(h)) ? 1 : 0;
   return EMS_OK;
 }
 
@@ -1967,6 +1991,13 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
 
 }  // namespace
 
+extern "C" int ems_set_exponentials(ems_handle *h, int32_t tabulate) {
+  if (!h) return EMS_ERR_ARG;
+  if (tabulate != 0 && tabulate != 1) return fail(h, EMS_ERR_ARG, "tabulate must be 0 or 1");
+  h->somm_tab = tabulate == 1;
+  return EMS_OK;
+}
+
 extern "C" int ems_set_precond(ems_handle *h, int32_t max_unknowns) {
   if (!h) return EMS_ERR_ARG;
   if (max_unknowns == 0) max_unknowns = 512;
@@ -2299,7 +2330,7 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
   if (!h->built) return fail(h, EMS_ERR_STATE, "ems_build first");
   if (chosen)
     for (int k = 0; k < 8; ++k) chosen[k] = 0;
-  if (!h->d_Eagg || !h->d_Edis) return EMS_OK;  // no tables: the vector-ALU kernels run
+  if (!ems::somm_mfma_ready(h, false)) return EMS_OK;  // the vector-ALU kernels run
   hipStream_t st = (hipStream_t)stream;
   int rc = ensure_ws(h, nrhs);
   if (rc) return rc;
@@ -2314,7 +2345,7 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
   const int batched = nrhs > 1 ? 1 : 0;
   for (int kernel = 0; kernel < 2; ++kernel)
     for (int prec = 0; prec < 2; ++prec) {
-      if (prec == 1 && (!h->d_Eagg32 || !h->d_Edis32)) continue;
+      if (prec == 1 && !ems::somm_mfma_fp32(h)) continue;
       float best = 1e30f;
       int bi = -1;
       for (int idx = 0; idx < 4; ++idx) {

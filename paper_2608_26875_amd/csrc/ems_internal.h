@@ -234,6 +234,12 @@ struct ems_handle {
   // depth order of the table rows / columns and the per-node and per-particle
   // ranges of the truncated contractions (with the tables)
   int *d_sperm = nullptr, *d_kcut = nullptr, *d_jr = nullptr;
+  // register form of the exponentials (every form whose tables were not
+  // built): node coefficients [variant][wave][q], particle positions in depth
+  // order
+  double4 *d_gco = nullptr;
+  double2 *d_xys = nullptr;
+  bool somm_tab = true;  // tabulate the exponentials at set-up where they fit
   double depth_kept = 1.0, depth_min = 0.0;
   // the same for receivers shallower than every particle (field evaluation)
   int *d_kcut_f = nullptr, *d_jr_f = nullptr;
@@ -378,6 +384,11 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb);
 hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipStream_t st,
                                bool transmit = false);
 hipError_t launch_etables(ems_handle *h, hipStream_t st);
+hipError_t launch_gen_coef(ems_handle *h, hipStream_t st);
+// the matrix-core Sommerfeld kernels can run (register form, or tables built)
+bool somm_mfma_ready(const ems_handle *h, bool adjoint);
+// ... and have an FP32 form for the mixed apply
+bool somm_mfma_fp32(const ems_handle *h);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut = nullptr);
 // y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags.

@@ -26,6 +26,7 @@
 // Partial sums over particle chunks (aggregate) and node chunks
 // (disaggregate) are written separately and reduced in a fixed order, so
 // results are reproducible run to run.
+#include <algorithm>
 #include <type_traits>
 
 #include "dev.h"
@@ -216,8 +217,14 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
 //   I_j     = sum_k V[j][k] A[j][k],
 // Disaggregate: for one wave type and one chunk of nodes,
 //   a^l_{k-PM} = sum_j E(j, l) (RW_j V[j][k])  (particles x modes, contracted over j).
-// Both are skinny complex products whose long operand (the exponential
-// table, 16 B per (node, particle)) streams from HBM exactly once.  A wave
+// Both are skinny complex products.  Their long operand, the exponential
+// E(j, m), is either read from a table built at set-up (16 B per (node,
+// particle), streamed from HBM once per contraction) or, with GEN, formed in
+// registers from the particle's position and four per-node coefficients,
+//   E = exp((g.x y + g.y x) + i (g.z y + g.w x)),
+// (one exp and one sincos per entry on the vector ALU, beside the MFMAs:
+// no table, no HBM stream).  The four sign patterns of g give the forward
+// and adjoint factors of both contractions (gen_coef_kernel).  A wave
 // owns 16*NT rows x 16*NU modes; each step contracts 4 indices (lane group
 // kq = lane / 16 supplies index base + kq) with 16x16x4 MFMAs, a complex
 // product being four real ones (re*re - im*im, re*im + im*re).  The operands
@@ -268,16 +275,122 @@ __device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NC],
   }
 }
 
+// e^a (cos b, sin b) without the library's large-argument branches, which
+// cost registers the matrix-core loops need.  Cody-Waite reduction with
+// two-part constants and fused multiply-adds, a = k ln2 + r (|r| <= ln2/2)
+// and b = n pi/2 + t (|t| <= pi/4), then Taylor polynomials of the reduced
+// arguments: FP64 to degree 13 (e^r, truncation < 5e-18), 15 (sin, < 4e-17)
+// and 16 (cos, < 3e-18); the FP32 form (for the complex64 operands of the
+// mixed apply) reduces in FP64 and evaluates degree 7, 9 and 10 in FP32
+// (truncation < 6e-9).  Valid for |b| < 2^30, which the build checks
+// (ems_build keeps the tables or the vector-ALU kernels beyond it); e^a
+// flushes to zero below a = -745 (FP64) and -104 (FP32).
+constexpr double kLog2e = 1.4426950408889634;       // 1 / ln 2
+constexpr double kLn2Hi = 0.6931471805599453;       // ln 2 rounded
+constexpr double kLn2Lo = 2.3190468138462996e-17;   // ln 2 - kLn2Hi
+constexpr double kTwoOverPi = 0.6366197723675814;   // 2 / pi
+constexpr double kPio2Hi = 1.5707963267948966;      // pi / 2 rounded
+constexpr double kPio2Lo = 6.123233995736766e-17;   // pi / 2 - kPio2Hi
+
+__device__ __forceinline__ void cexp_reg(double a, double b, double &er, double &ei) {
+  const double k = fmin(fmax(__builtin_rint(a * kLog2e), -1100.0), 1100.0);
+  double r = fma(-k, kLn2Hi, a);
+  r = fma(-k, kLn2Lo, r);
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  const double e = a < -745.2 ? 0.0 : ldexp(p, (int)k);
+  const double n = __builtin_rint(b * kTwoOverPi);
+  double t = fma(-n, kPio2Hi, b);
+  t = fma(-n, kPio2Lo, t);
+  const double z = t * t;
+  double sp = -1.0 / 1307674368000.0;
+  sp = fma(sp, z, 1.0 / 6227020800.0);
+  sp = fma(sp, z, -1.0 / 39916800.0);
+  sp = fma(sp, z, 1.0 / 362880.0);
+  sp = fma(sp, z, -1.0 / 5040.0);
+  sp = fma(sp, z, 1.0 / 120.0);
+  sp = fma(sp, z, -1.0 / 6.0);
+  const double sn = fma(sp * z, t, t);
+  double cp = 1.0 / 20922789888000.0;
+  cp = fma(cp, z, -1.0 / 87178291200.0);
+  cp = fma(cp, z, 1.0 / 479001600.0);
+  cp = fma(cp, z, -1.0 / 3628800.0);
+  cp = fma(cp, z, 1.0 / 40320.0);
+  cp = fma(cp, z, -1.0 / 720.0);
+  cp = fma(cp, z, 1.0 / 24.0);
+  cp = fma(cp, z, -0.5);
+  const double cs = fma(cp, z, 1.0);
+  // quadrant n mod 4: (cos, sin) of b = (cs, sn), (-sn, cs), (-cs, -sn), (sn, -cs)
+  const int qd = (int)n & 3;
+  const double c0 = (qd & 1) ? sn : cs, s0 = (qd & 1) ? cs : sn;
+  er = e * (((qd + 1) & 2) ? -c0 : c0);
+  ei = e * ((qd & 2) ? -s0 : s0);
+}
+
+__device__ __forceinline__ void cexp_reg(double a, double b, float &er, float &ei) {
+  const double k = fmin(fmax(__builtin_rint(a * kLog2e), -200.0), 200.0);
+  double r = fma(-k, kLn2Hi, a);
+  r = fma(-k, kLn2Lo, r);
+  const float rf = (float)r;
+  float p = 1.0f / 5040.0f;
+  p = fmaf(p, rf, 1.0f / 720.0f);
+  p = fmaf(p, rf, 1.0f / 120.0f);
+  p = fmaf(p, rf, 1.0f / 24.0f);
+  p = fmaf(p, rf, 1.0f / 6.0f);
+  p = fmaf(p, rf, 0.5f);
+  p = fmaf(p, rf, 1.0f);
+  p = fmaf(p, rf, 1.0f);
+  const float e = a < -104.0 ? 0.0f : ldexpf(p, (int)k);
+  const double n = __builtin_rint(b * kTwoOverPi);
+  double t = fma(-n, kPio2Hi, b);
+  t = fma(-n, kPio2Lo, t);
+  const float tf = (float)t, z = tf * tf;
+  float sp = 1.0f / 362880.0f;
+  sp = fmaf(sp, z, -1.0f / 5040.0f);
+  sp = fmaf(sp, z, 1.0f / 120.0f);
+  sp = fmaf(sp, z, -1.0f / 6.0f);
+  const float sn = fmaf(sp * z, tf, tf);
+  float cp = -1.0f / 3628800.0f;
+  cp = fmaf(cp, z, 1.0f / 40320.0f);
+  cp = fmaf(cp, z, -1.0f / 720.0f);
+  cp = fmaf(cp, z, 1.0f / 24.0f);
+  cp = fmaf(cp, z, -0.5f);
+  const float cs = fmaf(cp, z, 1.0f);
+  const int qd = (int)n & 3;
+  const float c0 = (qd & 1) ? sn : cs, s0 = (qd & 1) ? cs : sn;
+  er = e * (((qd + 1) & 2) ? -c0 : c0);
+  ei = e * ((qd & 2) ? -s0 : s0);
+}
+
+// E = exp((g.x y + g.y x) + i (g.z y + g.w x)) at position ps = (x, y).
+template <typename T>
+__device__ __forceinline__ void gen_exp(const double4 &g, const double2 &ps, T &er, T &ei) {
+  cexp_reg(fma(g.x, ps.y, g.y * ps.x), fma(g.z, ps.y, g.w * ps.x), er, ei);
+}
+
 // Column tiles: NU tiles of 16 modes for each of RB right-hand sides (tile
 // c = k NU + u is right-hand side r0 + k, modes 16 u .. 16 u + 15).  nm =
 // 2 PM + 1 of the power tables (PM their padded order), nrhs bounds r0 + k.
-template <typename T, int NU, int NT, int RB, bool UNI>
+template <typename T, int NU, int NT, int RB, bool UNI, bool GEN>
 __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ x, int64_t ldx, const double2 *__restrict__ Vp_t,
     const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
     const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
-    const int *__restrict__ kcut) {
+    const int *__restrict__ kcut, const double4 *__restrict__ gco,
+    const double2 *__restrict__ xys) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
   constexpr int NC = NU * RB;
@@ -294,6 +407,12 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   int jl[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) jl[t] = min(jb + 16 * t + i16, q - 1);
+  // GEN: the coefficients of the lane's nodes stay in registers
+  double4 gc[NT];
+  if constexpr (GEN) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) gc[t] = gco[(int64_t)wave * q + jl[t]];
+  }
   // table rows run through the particles by depth; the wave's nodes keep the
   // first kc of them (the largest count over its nodes)
   int kc = 0;
@@ -305,12 +424,18 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   // Two operand slots, each refilled right after it is consumed: the loads
   // of a step are issued two steps ahead of its products.  The particle index
   // of a table row is loaded one refill earlier still (a dependent load).
+  // (GEN: the slot holds the particle position in en[0] instead)
   C enA[NT], enB[NT];
+  double2 psA, psB;
   double2 xnA[NC], xnB[NC];
-  auto fetch = [&](C (&en)[NT], double2 (&xn)[NC], int m, int mo) {
+  auto fetch = [&](C (&en)[NT], double2 &ps, double2 (&xn)[NC], int m, int mo) {
     const int mc = min(m + kq, m1 - 1);
+    if constexpr (GEN) {
+      ps = xys[mc];
+    } else {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
+      for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
+    }
     // uniform orders: the coefficient address needs no offset lookup
     const int pm = UNI ? PM : p[mo];
     const int64_t base = (UNI ? (int64_t)mo * 2 * nm : off[mo]) + wave * (2 * pm + 1) + pm;
@@ -325,13 +450,17 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       }
     }
   };
-  auto take = [&](const C (&en)[NT], const double2 (&xn)[NC], int m, T (&er)[NT], T (&ei)[NT],
-                  T (&br)[NC], T (&bi)[NC]) {
+  auto take = [&](const C (&en)[NT], const double2 &ps, const double2 (&xn)[NC], int m,
+                  T (&er)[NT], T (&ei)[NT], T (&br)[NC], T (&bi)[NC]) {
     const bool ok = m + kq < m1;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      er[t] = en[t].x;
-      ei[t] = en[t].y;
+      if constexpr (GEN) {
+        gen_exp<T>(gc[t], ps, er[t], ei[t]);
+      } else {
+        er[t] = en[t].x;
+        ei[t] = en[t].y;
+      }
     }
 #pragma unroll
     for (int u = 0; u < NC; ++u) {
@@ -342,24 +471,24 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   auto row = [&](int m) { return sperm[min(m + kq, m1 - 1)]; };
   int moA = 0, moB = 0;
   if (m0 < m1) {
-    fetch(enA, xnA, m0, row(m0));
-    fetch(enB, xnB, m0 + 4, row(m0 + 4));
+    fetch(enA, psA, xnA, m0, row(m0));
+    fetch(enB, psB, xnB, m0 + 4, row(m0 + 4));
     moA = row(m0 + 8);
     moB = row(m0 + 12);
   }
   for (int m = m0; m < m1; m += 8) {
     {
       T er[NT], ei[NT], br[NC], bi[NC];
-      take(enA, xnA, m, er, ei, br, bi);
-      fetch(enA, xnA, m + 8, moA);
+      take(enA, psA, xnA, m, er, ei, br, bi);
+      fetch(enA, psA, xnA, m + 8, moA);
       moA = row(m + 16);
       mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
     }
     if (m + 4 >= m1) break;  // uniform over the wave
     {
       T er[NT], ei[NT], br[NC], bi[NC];
-      take(enB, xnB, m + 4, er, ei, br, bi);
-      fetch(enB, xnB, m + 12, moB);
+      take(enB, psB, xnB, m + 4, er, ei, br, bi);
+      fetch(enB, psB, xnB, m + 12, moB);
       moB = row(m + 20);
       mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
     }
@@ -398,13 +527,14 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
   }
 }
 
-template <typename T, int NU, int NT, int RB>
+template <typename T, int NU, int NT, int RB, bool GEN>
 __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
-    const int2 *__restrict__ jr) {
+    const int2 *__restrict__ jr, const double4 *__restrict__ gco,
+    const double2 *__restrict__ xys) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
   constexpr int NC = NU * RB;
@@ -422,6 +552,12 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   int lc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) lc[t] = min(lb + 16 * t + i16, n - 1);
+  // GEN: the positions of the lane's particles stay in registers
+  double2 pl[NT];
+  if constexpr (GEN) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pl[t] = xys[lc[t]];
+  }
   // table columns run through the particles by depth; the wave's particles
   // need the hull of their node ranges (empty ranges add nothing)
   int lo = q, hi = 0;
@@ -440,11 +576,16 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   }
   const int j0 = max(c * per_chunk, lo), j1 = min(min(q, c * per_chunk + per_chunk), hi);
   C en[NT];
+  double4 gj;  // GEN: the coefficients of the step's node
   double2 vn[NU], gn[RB];
   auto fetch = [&](int j) {
     const int jc = min(j + kq, j1 - 1);
+    if constexpr (GEN) {
+      gj = gco[(int64_t)wave * q + jc];
+    } else {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)jc * n + lc[t]];
+      for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)jc * n + lc[t]];
+    }
 #pragma unroll
     for (int k = 0; k < RB; ++k)
       gn[k] = g[(int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc];
@@ -457,8 +598,12 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     T er[NT], ei[NT], br[NC], bi[NC];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      er[t] = en[t].x;
-      ei[t] = en[t].y;
+      if constexpr (GEN) {
+        gen_exp<T>(gj, pl[t], er[t], ei[t]);
+      } else {
+        er[t] = en[t].x;
+        ei[t] = en[t].y;
+      }
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k)
@@ -521,52 +666,90 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
   return 0;
 }
 
+// Operands of one matrix-core launch: the table (nullptr: the exponentials
+// are formed in registers from the node coefficients), the node coefficients
+// of the register form, the power tables.
+template <typename T>
+struct SommOps {
+  const typename Mfma<T>::C *E;
+  const double4 *gco;
+  const double2 *Vp, *Vs;
+};
+
 template <typename T, int NU, int NT, int RB, bool UNI>
-static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per,
-                   const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
+static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per, const SommOps<T> &o,
                    hipStream_t st, const int *cut) {
-  hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI>),
-                     dim3((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB)),
-                     dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, x, h->ncoef, Vp, Vs, h->d_agg, h->agg_chunks, per, E, h->d_sperm,
-                     cut);
+  const dim3 grid((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB));
+  const int nm = 2 * pm_bucket(h->pmax) + 1;
+  if (o.E)
+    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI, false>), grid, dim3(256), 0,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, x, h->ncoef, o.Vp, o.Vs,
+                       h->d_agg, h->agg_chunks, per, o.E, h->d_sperm, cut, o.gco, h->d_xys);
+  else
+    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI, true>), grid, dim3(256), 0,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, x, h->ncoef, o.Vp, o.Vs,
+                       h->d_agg, h->agg_chunks, per, o.E, h->d_sperm, cut, o.gco, h->d_xys);
 }
 template <typename T, int NU, bool UNI>
 static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
-                     const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
-                     hipStream_t st, const int *cut) {
+                     const SommOps<T> &o, hipStream_t st, const int *cut) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
-    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
-    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
-    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, o, st, cut); break;
+    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, o, st, cut); break;
+    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, o, st, cut); break;
+    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, o, st, cut); break;
   }
 }
 template <typename T, int NU, int NT, int RB>
-static void dis_go(const ems_handle *h, int nrhs, int per, const typename Mfma<T>::C *E,
-                   const double2 *Vp, const double2 *Vs, hipStream_t st, const int *cut) {
-  hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB>),
-                     dim3((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB)),
-                     dim3(256), 0, st, h->n, h->q, 2 * pm_bucket(h->pmax) + 1, nrhs, h->d_p,
-                     h->d_off, Vp, Vs, h->d_refl, h->d_dis, h->ncoef, h->dis_chunks, per, E,
-                     h->d_sperm, (const int2 *)cut);
+static void dis_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, hipStream_t st,
+                   const int *cut) {
+  const dim3 grid((h->n + 64 * NT - 1) / (64 * NT), h->dis_chunks, 2 * ((nrhs + RB - 1) / RB));
+  const int nm = 2 * pm_bucket(h->pmax) + 1;
+  if (o.E)
+    hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, o.Vp, o.Vs, h->d_refl,
+                       h->d_dis, h->ncoef, h->dis_chunks, per, o.E, h->d_sperm,
+                       (const int2 *)cut, o.gco, h->d_xys);
+  else
+    hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, o.Vp, o.Vs, h->d_refl,
+                       h->d_dis, h->ncoef, h->dis_chunks, per, o.E, h->d_sperm,
+                       (const int2 *)cut, o.gco, h->d_xys);
 }
 template <typename T, int NU>
-static void dis_cand(const ems_handle *h, int idx, int nrhs, int per,
-                     const typename Mfma<T>::C *E, const double2 *Vp, const double2 *Vs,
+static void dis_cand(const ems_handle *h, int idx, int nrhs, int per, const SommOps<T> &o,
                      hipStream_t st, const int *cut) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
-    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
-    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
-    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, E, Vp, Vs, st, cut); break;
+    case 0: dis_go<T, NU, kCand[1][P][0][0], kCand[1][P][0][1]>(h, nrhs, per, o, st, cut); break;
+    case 1: dis_go<T, NU, kCand[1][P][1][0], kCand[1][P][1][1]>(h, nrhs, per, o, st, cut); break;
+    case 2: dis_go<T, NU, kCand[1][P][2][0], kCand[1][P][2][1]>(h, nrhs, per, o, st, cut); break;
+    default: dis_go<T, NU, kCand[1][P][3][0], kCand[1][P][3][1]>(h, nrhs, per, o, st, cut); break;
   }
 }
 
-// Matrix-core aggregate with the candidate idx (prec 0 FP64 tables, 1 FP32;
-// adj: the adjoint's conjugated tables, FP64).
+// Node coefficients of the register form: variant v (0 forward aggregate,
+// 1 adjoint aggregate, 2 forward disaggregate, 3 adjoint disaggregate),
+// wave type w, laid out [v][w][q].
+static const double4 *gen_coef(const ems_handle *h, int v) {
+  return h->d_gco ? h->d_gco + (size_t)v * 2 * h->q : nullptr;
+}
+
+// Each form reads its tables when they were built and forms the
+// exponentials in registers otherwise.
+bool somm_mfma_ready(const ems_handle *h, bool adjoint) {
+  if (h->d_gco) return true;
+  return adjoint ? (h->d_EaggA && h->d_EdisA) : (h->d_Eagg && h->d_Edis);
+}
+
+bool somm_mfma_fp32(const ems_handle *h) {
+  if (h->somm_fp64) return false;
+  return h->d_gco || (h->d_Eagg32 && h->d_Edis32);
+}
+
+// Matrix-core aggregate with the candidate idx (prec 0 FP64, 1 FP32; adj:
+// the adjoint's conjugated factors, FP64).
 hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int nrhs, int prec,
                                       int idx, hipStream_t st, bool adj, const int *cut) {
   if (!cut) cut = h->d_kcut;
@@ -574,18 +757,19 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
   const bool uni = h->p_uniform && pm_bucket(h->pmax) == h->pmax;
   if (adj) prec = 0;
-  const double2 *E64 = adj ? h->d_EaggA : h->d_Eagg;
+  if (!somm_mfma_ready(h, adj) || (prec == 1 && !somm_mfma_fp32(h))) return hipErrorInvalidValue;
+  const double4 *gco = gen_coef(h, adj ? 1 : 0);
   const double2 *Vp = adj ? h->d_VpA_agg : h->d_Vp, *Vs = adj ? h->d_VsA_agg : h->d_Vs;
-  if (prec == 1 && !h->d_Eagg32) return hipErrorInvalidValue;
-  if (prec == 0 && !E64) return hipErrorInvalidValue;
+  const SommOps<double> o64{adj ? h->d_EaggA : h->d_Eagg, gco, Vp, Vs};
+  const SommOps<float> o32{h->d_Eagg32, gco, Vp, Vs};
 #define EMS_AGGM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
     if (prec == 1) {                                                                         \
-      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st, cut);      \
-      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, h->d_Eagg32, Vp, Vs, st, cut);         \
+      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, o32, st, cut);               \
+      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, o32, st, cut);                  \
     } else {                                                                                 \
-      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, E64, Vp, Vs, st, cut);             \
-      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, E64, Vp, Vs, st, cut);                \
+      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, o64, st, cut);              \
+      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, o64, st, cut);                 \
     }                                                                                        \
     return hipGetLastError();                                                                \
   }
@@ -601,14 +785,15 @@ hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
   if (adj) prec = 0;
-  const double2 *E64 = adj ? h->d_EdisA : h->d_Edis;
+  if (!somm_mfma_ready(h, adj) || (prec == 1 && !somm_mfma_fp32(h))) return hipErrorInvalidValue;
+  const double4 *gco = gen_coef(h, adj ? 3 : 2);
   const double2 *Vp = adj ? h->d_VpA_dis : h->d_Vp, *Vs = adj ? h->d_VsA_dis : h->d_Vs;
-  if (prec == 1 && !h->d_Edis32) return hipErrorInvalidValue;
-  if (prec == 0 && !E64) return hipErrorInvalidValue;
+  const SommOps<double> o64{adj ? h->d_EdisA : h->d_Edis, gco, Vp, Vs};
+  const SommOps<float> o32{h->d_Edis32, gco, Vp, Vs};
 #define EMS_DISM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
-    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, h->d_Edis32, Vp, Vs, st, cut);          \
-    else dis_cand<double, NUV>(h, idx, nrhs, per, E64, Vp, Vs, st, cut);                           \
+    if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, o32, st, cut);                   \
+    else dis_cand<double, NUV>(h, idx, nrhs, per, o64, st, cut);                            \
     return hipGetLastError();                                                                \
   }
   EMS_DISM_NU(1)
@@ -631,12 +816,10 @@ hipError_t launch_somm_aggregate(const ems_handle *h, const double2 *x, int nrhs
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   const int pb = pm_bucket(h->pmax);
   const bool uni = h->p_uniform && pb == h->pmax;
-  if (!adjoint && h->d_Eagg != nullptr) {
-    const int prec = (mixed && h->d_Eagg32) ? 1 : 0;
-    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st, false, cut);
+  if (somm_mfma_ready(h, adjoint)) {
+    const int prec = (!adjoint && mixed && somm_mfma_fp32(h)) ? 1 : 0;
+    return launch_somm_aggregate_mfma(h, x, nrhs, prec, pick(h, 0, prec, nrhs), st, adjoint, cut);
   }
-  if (adjoint && h->d_EaggA != nullptr)
-    return launch_somm_aggregate_mfma(h, x, nrhs, 0, pick(h, 0, 0, nrhs), st, true, cut);
   dim3 grid((h->q + 255) / 256, h->agg_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pb) {
@@ -676,12 +859,10 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut) {
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
-  if (!adjoint && h->d_Edis != nullptr) {
-    const int prec = (mixed && h->d_Edis32) ? 1 : 0;
-    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, false, cut);
+  if (somm_mfma_ready(h, adjoint)) {
+    const int prec = (!adjoint && mixed && somm_mfma_fp32(h)) ? 1 : 0;
+    return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, adjoint, cut);
   }
-  if (adjoint && h->d_EdisA != nullptr)
-    return launch_somm_disaggregate_mfma(h, nrhs, 0, pick(h, 1, 0, nrhs), st, true, cut);
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
   const int mode = adjoint ? 2 : 1;
   switch (pm_bucket(h->pmax)) {
@@ -743,6 +924,41 @@ __global__ void etab_dis_kernel(int n, int q, const double *__restrict__ xy,
   if (E32) E32[at] = make_float2((float)e.x, (float)e.y);
   // adjoint disaggregate table: conj(e^{s y_l - i xi x_l}) in this layout
   if (EA) EA[at] = cconj(cexp(make_double2(s.x * yl + xi.y * xl, s.y * yl - xi.x * xl)));
+}
+
+// Node coefficients g of E = exp((g.x y + g.y x) + i (g.z y + g.w x)) for
+// the register form, [variant][wave][q] (variants as in gen_coef), and the
+// particle positions in depth order.  With s = s_w(j), xi = xi_j:
+//   forward aggregate    s y - i xi x                 g = ( s_r,  xi_i,  s_i, -xi_r)
+//   adjoint aggregate    conj(i xi x + s y)           g = ( s_r, -xi_i, -s_i, -xi_r)
+//   forward disaggregate i xi x + s y                 g = ( s_r, -xi_i,  s_i,  xi_r)
+//   adjoint disaggregate conj(s y - i xi x)           g = ( s_r,  xi_i, -s_i,  xi_r)
+// (the same four factors as the tables etab_agg_kernel / etab_dis_kernel).
+__global__ void gen_coef_kernel(int n, int q, const double *__restrict__ xy,
+                                const int *__restrict__ sperm, const double2 *__restrict__ xi_t,
+                                const double2 *__restrict__ sp_t, const double2 *__restrict__ ss_t,
+                                double4 *__restrict__ gco, double2 *__restrict__ xys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int o = sperm[i];
+    xys[i] = make_double2(xy[2 * o], xy[2 * o + 1]);
+  }
+  if (i >= 2 * q) return;
+  const int w = i / q, j = i - w * q;
+  const double2 xi = xi_t[j];
+  const double2 s = w ? ss_t[j] : sp_t[j];
+  const size_t V = (size_t)2 * q;
+  gco[i] = make_double4(s.x, xi.y, s.y, -xi.x);
+  gco[V + i] = make_double4(s.x, -xi.y, -s.y, -xi.x);
+  gco[2 * V + i] = make_double4(s.x, -xi.y, s.y, xi.x);
+  gco[3 * V + i] = make_double4(s.x, xi.y, -s.y, xi.x);
+}
+
+hipError_t launch_gen_coef(ems_handle *h, hipStream_t st) {
+  const int m = std::max(h->n, 2 * h->q);
+  hipLaunchKernelGGL(gen_coef_kernel, dim3((m + 255) / 256), dim3(256), 0, st, h->n, h->q, h->d_xy,
+                     h->d_sperm, h->d_xi, h->d_sp, h->d_ss, h->d_gco, h->d_xys);
+  return hipGetLastError();
 }
 
 hipError_t launch_etables(ems_handle *h, hipStream_t st) {
