@@ -222,6 +222,7 @@ void free_device(ems_handle *h) {
   dfree(h->d_EdisA);
   dfree(h->d_gco);
   dfree(h->d_xys);
+  dfree(h->d_xpad);
   dfree(h->d_sperm);
   dfree(h->d_kcut);
   dfree(h->d_jr);
@@ -323,6 +324,12 @@ bool finite_all(const double *v, size_t n) {
 }
 
 // Workspace for nrhs right-hand sides.
+// Elements of the matrix-core aggregate's padded coefficient copy.
+size_t xpad_len(const ems_handle *h, int nrhs) {
+  const int nw = 16 * ((2 * ems::pm_bucket(h->pmax) + 1 + 15) / 16);
+  return (size_t)nrhs * 2 * h->n * nw;
+}
+
 int ensure_ws(ems_handle *h, int nrhs) {
   if (h->ws_nrhs >= nrhs) return EMS_OK;
   ++h->ws_epoch;
@@ -341,6 +348,9 @@ int ensure_ws(ems_handle *h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_refl, sizeof(double2) * (size_t)nrhs * 2 * h->q));
   HIPCHK(h, hipMalloc(&h->d_dis, sizeof(double2) * (size_t)nrhs * h->dis_chunks * nc));
   HIPCHK(h, hipMalloc(&h->d_free, sizeof(double2) * (size_t)nrhs * nc));
+  dfree(h->d_xpad);
+  if (ems::somm_mfma_ready(h, false) || ems::somm_mfma_ready(h, true))
+    HIPCHK(h, hipMalloc(&h->d_xpad, sizeof(double2) * xpad_len(h, nrhs)));
   dfree(h->d_mult);
   dfree(h->d_loc);
   dfree(h->d_fmm_part);
@@ -2447,6 +2457,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
     o[1] = t; t += align256(c16 * nrhs * 2 * (size_t)h->q);       // reflected amplitudes
     o[2] = t; t += align256(c16 * nrhs * (size_t)d * nc);         // disaggregate partials
     o[3] = t; t += align256(c16 * nrhs * nc);                     // free-space output
+    o[8] = t; t += align256(c16 * (h->d_xpad ? xpad_len(h, nrhs) : 0));  // padded coefficients
     o[4] = o[5] = o[6] = o[7] = t;
     if (h->fmm_on) {
       o[4] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
@@ -2456,7 +2467,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
     }
     return t;
   };
-  size_t o[8];
+  size_t o[9];
   size_t total = need(agg, dis, o);
   while (total > kScratchBytes && (dis > 1 || agg > 1)) {
     if (dis > 1) dis = (dis + 1) / 2;
@@ -2473,13 +2484,14 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
                      (int64_t)(total / c16));
   HIPCHK(h, hipGetLastError());
   char *b = reinterpret_cast<char *>(base);
-  double2 *sv[8] = {h->d_agg,  h->d_refl, h->d_dis,      h->d_free,
-                    h->d_mult, h->d_loc,  h->d_fmm_part, h->d_m2l_part};
+  double2 *sv[9] = {h->d_agg,  h->d_refl, h->d_dis,      h->d_free,
+                    h->d_mult, h->d_loc,  h->d_fmm_part, h->d_m2l_part, h->d_xpad};
   const int s_agg = h->agg_chunks, s_dis = h->dis_chunks, s_ws = h->ws_nrhs;
   h->d_agg = reinterpret_cast<double2 *>(b + o[0]);
   h->d_refl = reinterpret_cast<double2 *>(b + o[1]);
   h->d_dis = reinterpret_cast<double2 *>(b + o[2]);
   h->d_free = reinterpret_cast<double2 *>(b + o[3]);
+  h->d_xpad = sv[8] ? reinterpret_cast<double2 *>(b + o[8]) : nullptr;
   h->d_mult = h->fmm_on ? reinterpret_cast<double2 *>(b + o[4]) : nullptr;
   h->d_loc = h->fmm_on ? reinterpret_cast<double2 *>(b + o[5]) : nullptr;
   h->d_fmm_part = (h->fmm_on && h->fmm.max_slots > 0) ? reinterpret_cast<double2 *>(b + o[6])
@@ -2498,6 +2510,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
   h->d_loc = sv[5];
   h->d_fmm_part = sv[6];
   h->d_m2l_part = sv[7];
+  h->d_xpad = sv[8];
   h->agg_chunks = s_agg;
   h->dis_chunks = s_dis;
   h->ws_nrhs = s_ws;

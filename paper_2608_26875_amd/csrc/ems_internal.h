@@ -256,6 +256,7 @@ struct ems_handle {
   double2 *d_refl = nullptr;     // [nrhs][2][q] reflected amplitudes (weights folded in)
   double2 *d_dis = nullptr;      // [nrhs][dis_chunks][ncoef] partial local coefficients
   double2 *d_free = nullptr;     // [nrhs][ncoef]
+  double2 *d_xpad = nullptr;     // [nrhs][2][n][16 NU] aggregate operand (matrix-core form)
   int64_t n_pairs = 0;
   bool near_fp64 = false;        // mixed form keeps the near field in FP64 (FP32 range)
   bool somm_fp64 = false;        // mixed form keeps the Sommerfeld contractions in FP64

@@ -227,8 +227,8 @@ __global__ __launch_bounds__(256) void somm_disaggregate_kernel(
 // and adjoint factors of both contractions (gen_coef_kernel).  A wave
 // owns 16*NT rows x 16*NU modes; each step contracts 4 indices (lane group
 // kq = lane / 16 supplies index base + kq) with 16x16x4 MFMAs, a complex
-// product being four real ones (re*re - im*im, re*im + im*re).  The operands
-// of the next step are fetched before the products of the current one.
+// product being three or four real ones (mfma_cstep).  The operands of a
+// step are fetched a few steps before its products (SommForm).
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
@@ -250,29 +250,84 @@ template <> struct Mfma<float> {
   __device__ static int row(int kq, int v) { return 4 * kq + v; }
 };
 
-template <typename T, int NT, int NC>
-__device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&ar)[NT][NC],
-                                           typename Mfma<T>::Acc (&ai)[NT][NC],
+// Per kernel and precision: the complex product form (three or four real
+// MFMAs per complex tile) and the operand slots in flight per wave.  Measured
+// at 20000 particles, order 15, against four MFMAs with two slots (aggregate)
+// and one (disaggregate): the 3M form takes the FP64 aggregate from 2.83 to
+// 2.63 ms and, with four slots, the FP32 aggregate and disaggregate down 7 %
+// and 13 %; in the FP64 disaggregate it costs occupancy (2.51 against 3.13 ms),
+// and more FP64 slots did not pay.
+template <typename T> struct SommForm {
+  static constexpr bool kFp32 = std::is_same<T, float>::value;
+  static constexpr bool k3MAgg = true, k3MDis = kFp32;
+  static constexpr int kSlotsAgg = kFp32 ? 4 : 2, kSlotsDis = kFp32 ? 4 : 1;
+};
+
+// One step of the complex product.  The 3M form (three real MFMAs):
+//   K1 += (Ar + Ai) Br,  K2 += Ar (Bi - Br),  K3 += Ai (Br + Bi),
+// with Re = K1 - K3 and Im = K1 + K2 formed once after the loop (the operand
+// sums cost three vector adds per lane and step; each accumulator is updated
+// once per step, so dependent MFMAs sit 3 NT NC issues apart).  The 4M form
+// accumulates Re and Im in k1, k2 directly (k3 unused): first the products
+// of every accumulator, then the second ones, so a dependent pair of MFMAs
+// sits 2 NT NC issues apart.
+template <typename T, int NT, int NC, bool G3>
+__device__ __forceinline__ void mfma_cstep(typename Mfma<T>::Acc (&k1)[NT][NC],
+                                           typename Mfma<T>::Acc (&k2)[NT][NC],
+                                           typename Mfma<T>::Acc (&k3)[NT][NC],
                                            const T (&er)[NT], const T (&ei)[NT], const T (&br)[NC],
                                            const T (&bi)[NC]) {
-  // first the products of every accumulator, then the second ones: a
-  // dependent pair of MFMAs sits 2 NT NC issues apart
+  if constexpr (!G3) {
+#pragma unroll
+    for (int u = 0; u < NC; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        k1[t][u] = Mfma<T>::op(er[t], br[u], k1[t][u]);
+        k2[t][u] = Mfma<T>::op(er[t], bi[u], k2[t][u]);
+      }
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const T nb = -bi[u];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        k1[t][u] = Mfma<T>::op(ei[t], nb, k1[t][u]);
+        k2[t][u] = Mfma<T>::op(ei[t], br[u], k2[t][u]);
+      }
+    }
+    return;
+  }
+  T es[NT], bd[NC], bs[NC];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) es[t] = er[t] + ei[t];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    bd[u] = bi[u] - br[u];
+    bs[u] = br[u] + bi[u];
+  }
 #pragma unroll
   for (int u = 0; u < NC; ++u)
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      ar[t][u] = Mfma<T>::op(er[t], br[u], ar[t][u]);
-      ai[t][u] = Mfma<T>::op(er[t], bi[u], ai[t][u]);
+      k1[t][u] = Mfma<T>::op(es[t], br[u], k1[t][u]);
+      k2[t][u] = Mfma<T>::op(er[t], bd[u], k2[t][u]);
+      k3[t][u] = Mfma<T>::op(ei[t], bs[u], k3[t][u]);
     }
+}
+
+// Real and imaginary parts of the 3M accumulators, in place: (K1, K2, K3)
+// becomes (Re, Im, -); nothing to do in the 4M form.
+template <typename T, int NT, int NC, bool G3>
+__device__ __forceinline__ void mfma_cfinish(typename Mfma<T>::Acc (&k1)[NT][NC],
+                                             typename Mfma<T>::Acc (&k2)[NT][NC],
+                                             const typename Mfma<T>::Acc (&k3)[NT][NC]) {
+  if constexpr (!G3) return;
 #pragma unroll
-  for (int u = 0; u < NC; ++u) {
-    const T nb = -bi[u];
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      ar[t][u] = Mfma<T>::op(ei[t], nb, ar[t][u]);
-      ai[t][u] = Mfma<T>::op(ei[t], br[u], ai[t][u]);
+    for (int u = 0; u < NC; ++u) {
+      k2[t][u] = k1[t][u] + k2[t][u];
+      k1[t][u] = k1[t][u] - k3[t][u];
     }
-  }
 }
 
 // e^a (cos b, sin b) without the library's large-argument branches, which
@@ -383,27 +438,27 @@ __device__ __forceinline__ void gen_exp(const double4 &g, const double2 &ps, T &
 // Column tiles: NU tiles of 16 modes for each of RB right-hand sides (tile
 // c = k NU + u is right-hand side r0 + k, modes 16 u .. 16 u + 15).  nm =
 // 2 PM + 1 of the power tables (PM their padded order), nrhs bounds r0 + k.
-template <typename T, int NU, int NT, int RB, bool UNI, bool GEN>
+// xp: the coefficients in depth order, modes -PM .. 16 NU - 1 - PM
+// (somm_xpad_kernel), [nrhs][wave][n][16 NU].
+template <typename T, int NU, int NT, int RB, bool GEN>
 __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
-    int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
-    const double2 *__restrict__ x, int64_t ldx, const double2 *__restrict__ Vp_t,
-    const double2 *__restrict__ Vs_t, double2 *__restrict__ agg, int chunks, int per_chunk,
-    const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
-    const int *__restrict__ kcut, const double4 *__restrict__ gco,
-    const double2 *__restrict__ xys) {
+    int n, int q, int nm, int nrhs, const double2 *__restrict__ xp,
+    const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
+    double2 *__restrict__ agg, int chunks, int per_chunk,
+    const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ kcut,
+    const double4 *__restrict__ gco, const double2 *__restrict__ xys) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
   constexpr int NC = NU * RB;
-  const int PM = nm >> 1;
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int jb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
   const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
   const C *Ew = Etab + (int64_t)wave * n * q;
-  Acc ar[NT][NC], ai[NT][NC];
+  Acc ar[NT][NC], ai[NT][NC], a3[NT][NC];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = a3[t][u] = Acc{0, 0, 0, 0};
   int jl[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) jl[t] = min(jb + 16 * t + i16, q - 1);
@@ -421,78 +476,59 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) kc = max(kc, __shfl_xor(kc, o));
   const int m0 = c * per_chunk, m1 = min(min(n, m0 + per_chunk), kc);
-  // Two operand slots, each refilled right after it is consumed: the loads
-  // of a step are issued two steps ahead of its products.  The particle index
-  // of a table row is loaded one refill earlier still (a dependent load).
-  // (GEN: the slot holds the particle position in en[0] instead)
-  C enA[NT], enB[NT];
-  double2 psA, psB;
-  double2 xnA[NC], xnB[NC];
-  auto fetch = [&](C (&en)[NT], double2 &ps, double2 (&xn)[NC], int m, int mo) {
+  // A ring of S operand slots, each refilled right after it is consumed:
+  // the loads of a step are issued S steps ahead of its products (GEN: a
+  // slot holds the particle position instead of table entries).
+  constexpr int S = SommForm<T>::kSlotsAgg;
+  constexpr int NW = 16 * NU;
+  C en[S][NT];
+  double2 ps[S];
+  double2 xn[S][NC];
+  auto fetch = [&](int sl, int m) {
     const int mc = min(m + kq, m1 - 1);
     if constexpr (GEN) {
-      ps = xys[mc];
+      ps[sl] = xys[mc];
     } else {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)mc * q + jl[t]];
+      for (int t = 0; t < NT; ++t) en[sl][t] = Ew[(int64_t)mc * q + jl[t]];
     }
-    // uniform orders: the coefficient address needs no offset lookup
-    const int pm = UNI ? PM : p[mo];
-    const int64_t base = (UNI ? (int64_t)mo * 2 * nm : off[mo]) + wave * (2 * pm + 1) + pm;
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      const int r = min(r0 + k, nrhs - 1);
+      const double2 *xr = xp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * n + mc) * NW + i16;
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int nn = 16 * u + i16 - PM;
-        xn[k * NU + u] = (nn >= -pm && nn <= pm) ? x[(int64_t)r * ldx + base + nn]
-                                                 : make_double2(0.0, 0.0);
-      }
+      for (int u = 0; u < NU; ++u) xn[sl][k * NU + u] = xr[16 * u];
     }
   };
-  auto take = [&](const C (&en)[NT], const double2 &ps, const double2 (&xn)[NC], int m,
-                  T (&er)[NT], T (&ei)[NT], T (&br)[NC], T (&bi)[NC]) {
-    const bool ok = m + kq < m1;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if constexpr (GEN) {
-        gen_exp<T>(gc[t], ps, er[t], ei[t]);
-      } else {
-        er[t] = en[t].x;
-        ei[t] = en[t].y;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      br[u] = ok ? (T)xn[u].x : T(0);
-      bi[u] = ok ? (T)xn[u].y : T(0);
-    }
-  };
-  auto row = [&](int m) { return sperm[min(m + kq, m1 - 1)]; };
-  int moA = 0, moB = 0;
   if (m0 < m1) {
-    fetch(enA, psA, xnA, m0, row(m0));
-    fetch(enB, psB, xnB, m0 + 4, row(m0 + 4));
-    moA = row(m0 + 8);
-    moB = row(m0 + 12);
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) fetch(sl, m0 + 4 * sl);
   }
-  for (int m = m0; m < m1; m += 8) {
-    {
+  for (int m = m0; m < m1; m += 4 * S) {
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      const int ms = m + 4 * sl;
+      if (sl > 0 && ms >= m1) break;  // uniform over the wave
+      const bool ok = ms + kq < m1;
       T er[NT], ei[NT], br[NC], bi[NC];
-      take(enA, psA, xnA, m, er, ei, br, bi);
-      fetch(enA, psA, xnA, m + 8, moA);
-      moA = row(m + 16);
-      mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
-    }
-    if (m + 4 >= m1) break;  // uniform over the wave
-    {
-      T er[NT], ei[NT], br[NC], bi[NC];
-      take(enB, psB, xnB, m + 4, er, ei, br, bi);
-      fetch(enB, psB, xnB, m + 12, moB);
-      moB = row(m + 20);
-      mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if constexpr (GEN) {
+          gen_exp<T>(gc[t], ps[sl], er[t], ei[t]);
+        } else {
+          er[t] = en[sl][t].x;
+          ei[t] = en[sl][t].y;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        br[u] = ok ? (T)xn[sl][u].x : T(0);
+        bi[u] = ok ? (T)xn[sl][u].y : T(0);
+      }
+      fetch(sl, ms + 4 * S);
+      mfma_cstep<T, NT, NC, SommForm<T>::k3MAgg>(ar, ai, a3, er, ei, br, bi);
     }
   }
+  mfma_cfinish<T, NT, NC, SommForm<T>::k3MAgg>(ar, ai, a3);
   // I_j = sum_k V[j][k] A[j][k]; the 16 lanes of a group hold the 16 columns
   const double2 *Vt = wave ? Vs_t : Vp_t;
 #pragma unroll
@@ -544,11 +580,11 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
   const double2 *Vt = wave ? Vs_t : Vp_t;
   const C *Ew = Etab + (int64_t)wave * q * n;
-  Acc ar[NT][NC], ai[NT][NC];
+  Acc ar[NT][NC], ai[NT][NC], a3[NT][NC];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = Acc{0, 0, 0, 0};
+    for (int u = 0; u < NC; ++u) ar[t][u] = ai[t][u] = a3[t][u] = Acc{0, 0, 0, 0};
   int lc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) lc[t] = min(lb + 16 * t + i16, n - 1);
@@ -575,48 +611,60 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     hi = max(hi, __shfl_xor(hi, o));
   }
   const int j0 = max(c * per_chunk, lo), j1 = min(min(q, c * per_chunk + per_chunk), hi);
-  C en[NT];
-  double4 gj;  // GEN: the coefficients of the step's node
-  double2 vn[NU], gn[RB];
-  auto fetch = [&](int j) {
+  // ring of S operand slots, loads issued S steps ahead
+  constexpr int S = SommForm<T>::kSlotsDis;
+  C en[S][NT];
+  double4 gj[S];  // GEN: the coefficients of the step's node
+  double2 vn[S][NU], gn[S][RB];
+  auto fetch = [&](int sl, int j) {
     const int jc = min(j + kq, j1 - 1);
     if constexpr (GEN) {
-      gj = gco[(int64_t)wave * q + jc];
+      gj[sl] = gco[(int64_t)wave * q + jc];
     } else {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) en[t] = Ew[(int64_t)jc * n + lc[t]];
+      for (int t = 0; t < NT; ++t) en[sl][t] = Ew[(int64_t)jc * n + lc[t]];
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k)
-      gn[k] = g[(int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc];
+      gn[sl][k] = g[(int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) vn[u] = Vt[(int64_t)jc * nm + min(16 * u + i16, nm - 1)];
+    for (int u = 0; u < NU; ++u)
+      vn[sl][u] = Vt[(int64_t)jc * nm + min(16 * u + i16, nm - 1)];
   };
-  if (j0 < j1) fetch(j0);
-  for (int j = j0; j < j1; j += 4) {
-    const bool ok = j + kq < j1;
-    T er[NT], ei[NT], br[NC], bi[NC];
+  if (j0 < j1) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if constexpr (GEN) {
-        gen_exp<T>(gj, pl[t], er[t], ei[t]);
-      } else {
-        er[t] = en[t].x;
-        ei[t] = en[t].y;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < RB; ++k)
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const bool use = ok && 16 * u + i16 < nm;
-        const double2 G = cmul(gn[k], vn[u]);
-        br[k * NU + u] = use ? (T)G.x : T(0);
-        bi[k * NU + u] = use ? (T)G.y : T(0);
-      }
-    fetch(j + 4);
-    mfma_cstep<T, NT, NC>(ar, ai, er, ei, br, bi);
+    for (int sl = 0; sl < S; ++sl) fetch(sl, j0 + 4 * sl);
   }
+  for (int j = j0; j < j1; j += 4 * S) {
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+      const int js = j + 4 * sl;
+      if (sl > 0 && js >= j1) break;  // uniform over the wave
+      const bool ok = js + kq < j1;
+      T er[NT], ei[NT], br[NC], bi[NC];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if constexpr (GEN) {
+          gen_exp<T>(gj[sl], pl[t], er[t], ei[t]);
+        } else {
+          er[t] = en[sl][t].x;
+          ei[t] = en[sl][t].y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RB; ++k)
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const bool use = ok && 16 * u + i16 < nm;
+          const double2 G = cmul(gn[sl][k], vn[sl][u]);
+          br[k * NU + u] = use ? (T)G.x : T(0);
+          bi[k * NU + u] = use ? (T)G.y : T(0);
+        }
+      fetch(sl, js + 4 * S);
+      mfma_cstep<T, NT, NC, SommForm<T>::k3MDis>(ar, ai, a3, er, ei, br, bi);
+    }
+  }
+  mfma_cfinish<T, NT, NC, SommForm<T>::k3MDis>(ar, ai, a3);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -666,6 +714,23 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
   return 0;
 }
 
+// The aggregate's coefficient operand: x in depth order, one row of 16 NU
+// modes per (right-hand side, wave type, particle), zero outside |n| <= p_m,
+// so the matrix-core loop reads it without index or order lookups.
+__global__ void somm_xpad_kernel(int n, int pmb, int nw, const int *__restrict__ p,
+                                 const int64_t *__restrict__ off, const double2 *__restrict__ x,
+                                 int64_t ldx, const int *__restrict__ sperm,
+                                 double2 *__restrict__ xp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = blockIdx.y, r = blockIdx.z;
+  if (i >= (int64_t)n * nw) return;
+  const int m = (int)(i / nw), k = (int)(i - (int64_t)m * nw);
+  const int mo = sperm[m], pm = p[mo], nn = k - pmb;
+  xp[((int64_t)(r * 2 + w) * n + m) * nw + k] =
+      (nn >= -pm && nn <= pm) ? x[(int64_t)r * ldx + off[mo] + w * (2 * pm + 1) + pm + nn]
+                              : make_double2(0.0, 0.0);
+}
+
 // Operands of one matrix-core launch: the table (nullptr: the exponentials
 // are formed in registers from the node coefficients), the node coefficients
 // of the register form, the power tables.
@@ -676,29 +741,29 @@ struct SommOps {
   const double2 *Vp, *Vs;
 };
 
-template <typename T, int NU, int NT, int RB, bool UNI>
-static void agg_go(const ems_handle *h, const double2 *x, int nrhs, int per, const SommOps<T> &o,
-                   hipStream_t st, const int *cut) {
+template <typename T, int NU, int NT, int RB>
+static void agg_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, hipStream_t st,
+                   const int *cut) {
   const dim3 grid((h->q + 64 * NT - 1) / (64 * NT), h->agg_chunks, 2 * ((nrhs + RB - 1) / RB));
   const int nm = 2 * pm_bucket(h->pmax) + 1;
   if (o.E)
-    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI, false>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, x, h->ncoef, o.Vp, o.Vs,
-                       h->d_agg, h->agg_chunks, per, o.E, h->d_sperm, cut, o.gco, h->d_xys);
+    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0, st,
+                       h->n, h->q, nm, nrhs, h->d_xpad, o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
+                       o.E, cut, o.gco, h->d_xys);
   else
-    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, UNI, true>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, x, h->ncoef, o.Vp, o.Vs,
-                       h->d_agg, h->agg_chunks, per, o.E, h->d_sperm, cut, o.gco, h->d_xys);
+    hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0, st,
+                       h->n, h->q, nm, nrhs, h->d_xpad, o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
+                       o.E, cut, o.gco, h->d_xys);
 }
-template <typename T, int NU, bool UNI>
-static void agg_cand(const ems_handle *h, int idx, const double2 *x, int nrhs, int per,
-                     const SommOps<T> &o, hipStream_t st, const int *cut) {
+template <typename T, int NU>
+static void agg_cand(const ems_handle *h, int idx, int nrhs, int per, const SommOps<T> &o,
+                     hipStream_t st, const int *cut) {
   constexpr int P = std::is_same<T, float>::value ? 1 : 0;
   switch (idx) {
-    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1], UNI>(h, x, nrhs, per, o, st, cut); break;
-    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1], UNI>(h, x, nrhs, per, o, st, cut); break;
-    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1], UNI>(h, x, nrhs, per, o, st, cut); break;
-    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1], UNI>(h, x, nrhs, per, o, st, cut); break;
+    case 0: agg_go<T, NU, kCand[0][P][0][0], kCand[0][P][0][1]>(h, nrhs, per, o, st, cut); break;
+    case 1: agg_go<T, NU, kCand[0][P][1][0], kCand[0][P][1][1]>(h, nrhs, per, o, st, cut); break;
+    case 2: agg_go<T, NU, kCand[0][P][2][0], kCand[0][P][2][1]>(h, nrhs, per, o, st, cut); break;
+    default: agg_go<T, NU, kCand[0][P][3][0], kCand[0][P][3][1]>(h, nrhs, per, o, st, cut); break;
   }
 }
 template <typename T, int NU, int NT, int RB>
@@ -755,22 +820,25 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
   if (!cut) cut = h->d_kcut;
   const int per = (h->n + h->agg_chunks - 1) / h->agg_chunks;
   const int nm = 2 * pm_bucket(h->pmax) + 1, nu = (nm + 15) / 16;
-  const bool uni = h->p_uniform && pm_bucket(h->pmax) == h->pmax;
   if (adj) prec = 0;
   if (!somm_mfma_ready(h, adj) || (prec == 1 && !somm_mfma_fp32(h))) return hipErrorInvalidValue;
   const double4 *gco = gen_coef(h, adj ? 1 : 0);
   const double2 *Vp = adj ? h->d_VpA_agg : h->d_Vp, *Vs = adj ? h->d_VsA_agg : h->d_Vs;
   const SommOps<double> o64{adj ? h->d_EaggA : h->d_Eagg, gco, Vp, Vs};
   const SommOps<float> o32{h->d_Eagg32, gco, Vp, Vs};
+  if (nrhs > h->ws_nrhs || !h->d_xpad) return hipErrorInvalidValue;
+  {
+    const int nw = 16 * nu;
+    hipLaunchKernelGGL(somm_xpad_kernel, dim3((unsigned)(((int64_t)h->n * nw + 255) / 256), 2, nrhs),
+                       dim3(256), 0, st, h->n, pm_bucket(h->pmax), nw, h->d_p, h->d_off, x,
+                       h->ncoef, h->d_sperm, h->d_xpad);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
 #define EMS_AGGM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
-    if (prec == 1) {                                                                         \
-      if (uni) agg_cand<float, NUV, true>(h, idx, x, nrhs, per, o32, st, cut);               \
-      else agg_cand<float, NUV, false>(h, idx, x, nrhs, per, o32, st, cut);                  \
-    } else {                                                                                 \
-      if (uni) agg_cand<double, NUV, true>(h, idx, x, nrhs, per, o64, st, cut);              \
-      else agg_cand<double, NUV, false>(h, idx, x, nrhs, per, o64, st, cut);                 \
-    }                                                                                        \
+    if (prec == 1) agg_cand<float, NUV>(h, idx, nrhs, per, o32, st, cut);                   \
+    else agg_cand<double, NUV>(h, idx, nrhs, per, o64, st, cut);                            \
     return hipGetLastError();                                                                \
   }
   EMS_AGGM_NU(1)
