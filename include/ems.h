@@ -484,12 +484,13 @@ int ems_param_vjp(ems_handle *h, const ems_plane_wave *waves, int32_t nrhs, cons
 
 /* Tile autotuner of the matrix-core Sommerfeld contractions: times each
  * compiled tile shape (nodes or particles per wave NT, right-hand sides per
- * wave RB) of the aggregate and disaggregate, FP64 and (when its complex64
- * tables exist) FP32, on this handle's tables at batch size nrhs, and keeps
- * the fastest for applies with one (nrhs = 1) or several (nrhs > 1)
+ * wave RB) of the aggregate and disaggregate, FP64 and (unless the mixed form
+ * keeps them in FP64) FP32, with this handle's exponentials (tables or the
+ * register form) at batch size nrhs, the best of four launches each, and
+ * keeps the fastest for applies with one (nrhs = 1) or several (nrhs > 1)
  * right-hand sides.  chosen (host, may be NULL) receives
  * {agg FP64 NT, RB, agg FP32 NT, RB, dis FP64 NT, RB, dis FP32 NT, RB}
- * (zeros for forms not tuned; all zeros when the tables were not built).
+ * (zeros for forms not tuned; all zeros when the vector-ALU kernels run).
  * Synchronous; results of later applies are unchanged up to rounding order. */
 int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_stream_t stream);
 

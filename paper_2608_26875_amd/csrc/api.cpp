@@ -223,6 +223,7 @@ void free_device(ems_handle *h) {
   dfree(h->d_gco);
   dfree(h->d_xys);
   dfree(h->d_xpad);
+  dfree(h->d_bpad);
   dfree(h->d_sperm);
   dfree(h->d_kcut);
   dfree(h->d_jr);
@@ -330,6 +331,12 @@ size_t xpad_len(const ems_handle *h, int nrhs) {
   return (size_t)nrhs * 2 * h->n * nw;
 }
 
+// ... and of the disaggregate's padded B operand.
+size_t bpad_len(const ems_handle *h, int nrhs) {
+  const int nw = 16 * ((2 * ems::pm_bucket(h->pmax) + 1 + 15) / 16);
+  return (size_t)nrhs * 2 * h->q * nw;
+}
+
 int ensure_ws(ems_handle *h, int nrhs) {
   if (h->ws_nrhs >= nrhs) return EMS_OK;
   ++h->ws_epoch;
@@ -349,8 +356,11 @@ int ensure_ws(ems_handle *h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_dis, sizeof(double2) * (size_t)nrhs * h->dis_chunks * nc));
   HIPCHK(h, hipMalloc(&h->d_free, sizeof(double2) * (size_t)nrhs * nc));
   dfree(h->d_xpad);
-  if (ems::somm_mfma_ready(h, false) || ems::somm_mfma_ready(h, true))
+  dfree(h->d_bpad);
+  if (ems::somm_mfma_ready(h, false) || ems::somm_mfma_ready(h, true)) {
     HIPCHK(h, hipMalloc(&h->d_xpad, sizeof(double2) * xpad_len(h, nrhs)));
+    HIPCHK(h, hipMalloc(&h->d_bpad, sizeof(double2) * bpad_len(h, nrhs)));
+  }
   dfree(h->d_mult);
   dfree(h->d_loc);
   dfree(h->d_fmm_part);
@@ -2363,7 +2373,7 @@ extern "C" int ems_autotune(ems_handle *h, int32_t nrhs, int32_t *chosen, ems_st
         ems::mfma_candidate(kernel, prec, idx, &nt, &rb);
         if (rb > 1 && nrhs == 1) continue;  // batched shapes only pay with several RHS
         float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < 5; ++rep) {
           HIPCHK(h, hipEventRecord(e0, st));
           hipError_t e = kernel == 0
                              ? ems::launch_somm_aggregate_mfma(h, h->d_tmp, nrhs, prec, idx, st)
@@ -2458,6 +2468,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
     o[2] = t; t += align256(c16 * nrhs * (size_t)d * nc);         // disaggregate partials
     o[3] = t; t += align256(c16 * nrhs * nc);                     // free-space output
     o[8] = t; t += align256(c16 * (h->d_xpad ? xpad_len(h, nrhs) : 0));  // padded coefficients
+    o[9] = t; t += align256(c16 * (h->d_bpad ? bpad_len(h, nrhs) : 0));  // padded node operand
     o[4] = o[5] = o[6] = o[7] = t;
     if (h->fmm_on) {
       o[4] = t; t += align256(c16 * nrhs * (size_t)h->fmm.exp_len);
@@ -2467,7 +2478,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
     }
     return t;
   };
-  size_t o[9];
+  size_t o[10];
   size_t total = need(agg, dis, o);
   while (total > kScratchBytes && (dis > 1 || agg > 1)) {
     if (dis > 1) dis = (dis + 1) / 2;
@@ -2484,14 +2495,15 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
                      (int64_t)(total / c16));
   HIPCHK(h, hipGetLastError());
   char *b = reinterpret_cast<char *>(base);
-  double2 *sv[9] = {h->d_agg,  h->d_refl, h->d_dis,      h->d_free,
-                    h->d_mult, h->d_loc,  h->d_fmm_part, h->d_m2l_part, h->d_xpad};
+  double2 *sv[10] = {h->d_agg,  h->d_refl, h->d_dis,      h->d_free,     h->d_mult,
+                     h->d_loc,  h->d_fmm_part, h->d_m2l_part, h->d_xpad, h->d_bpad};
   const int s_agg = h->agg_chunks, s_dis = h->dis_chunks, s_ws = h->ws_nrhs;
   h->d_agg = reinterpret_cast<double2 *>(b + o[0]);
   h->d_refl = reinterpret_cast<double2 *>(b + o[1]);
   h->d_dis = reinterpret_cast<double2 *>(b + o[2]);
   h->d_free = reinterpret_cast<double2 *>(b + o[3]);
   h->d_xpad = sv[8] ? reinterpret_cast<double2 *>(b + o[8]) : nullptr;
+  h->d_bpad = sv[9] ? reinterpret_cast<double2 *>(b + o[9]) : nullptr;
   h->d_mult = h->fmm_on ? reinterpret_cast<double2 *>(b + o[4]) : nullptr;
   h->d_loc = h->fmm_on ? reinterpret_cast<double2 *>(b + o[5]) : nullptr;
   h->d_fmm_part = (h->fmm_on && h->fmm.max_slots > 0) ? reinterpret_cast<double2 *>(b + o[6])
@@ -2511,6 +2523,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
   h->d_fmm_part = sv[6];
   h->d_m2l_part = sv[7];
   h->d_xpad = sv[8];
+  h->d_bpad = sv[9];
   h->agg_chunks = s_agg;
   h->dis_chunks = s_dis;
   h->ws_nrhs = s_ws;

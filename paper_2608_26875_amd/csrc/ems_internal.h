@@ -257,6 +257,7 @@ struct ems_handle {
   double2 *d_dis = nullptr;      // [nrhs][dis_chunks][ncoef] partial local coefficients
   double2 *d_free = nullptr;     // [nrhs][ncoef]
   double2 *d_xpad = nullptr;     // [nrhs][2][n][16 NU] aggregate operand (matrix-core form)
+  double2 *d_bpad = nullptr;     // [nrhs][2][q][16 NU] disaggregate operand (matrix-core form)
   int64_t n_pairs = 0;
   bool near_fp64 = false;        // mixed form keeps the near field in FP64 (FP32 range)
   bool somm_fp64 = false;        // mixed form keeps the Sommerfeld contractions in FP64

@@ -564,21 +564,21 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
 }
 
 template <typename T, int NU, int NT, int RB, bool GEN>
+// bp: the B operand RW_j V[j][k], zero-padded to 16 NU modes
+// (somm_bpad_kernel), [nrhs][wave][q][16 NU].
 __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
-    const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
-    const double2 *__restrict__ g, double2 *__restrict__ dis, int64_t ncoef, int chunks,
+    const double2 *__restrict__ bp, double2 *__restrict__ dis, int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
     const int2 *__restrict__ jr, const double4 *__restrict__ gco,
     const double2 *__restrict__ xys) {
   using Acc = typename Mfma<T>::Acc;
   using C = typename Mfma<T>::C;
-  constexpr int NC = NU * RB;
+  constexpr int NC = NU * RB, NW = 16 * NU;
   const int PM = nm >> 1;
   const int lane = threadIdx.x & 63, kq = lane >> 4, i16 = lane & 15;
   const int lb = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * NT;
   const int c = blockIdx.y, wave = blockIdx.z & 1, r0 = (blockIdx.z >> 1) * RB;
-  const double2 *Vt = wave ? Vs_t : Vp_t;
   const C *Ew = Etab + (int64_t)wave * q * n;
   Acc ar[NT][NC], ai[NT][NC], a3[NT][NC];
 #pragma unroll
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
   constexpr int S = SommForm<T>::kSlotsDis;
   C en[S][NT];
   double4 gj[S];  // GEN: the coefficients of the step's node
-  double2 vn[S][NU], gn[S][RB];
+  double2 bn[S][NC];
   auto fetch = [&](int sl, int j) {
     const int jc = min(j + kq, j1 - 1);
     if constexpr (GEN) {
@@ -625,11 +625,11 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
       for (int t = 0; t < NT; ++t) en[sl][t] = Ew[(int64_t)jc * n + lc[t]];
     }
 #pragma unroll
-    for (int k = 0; k < RB; ++k)
-      gn[sl][k] = g[(int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc];
+    for (int k = 0; k < RB; ++k) {
+      const double2 *br = bp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc) * NW + i16;
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
-      vn[sl][u] = Vt[(int64_t)jc * nm + min(16 * u + i16, nm - 1)];
+      for (int u = 0; u < NU; ++u) bn[sl][k * NU + u] = br[16 * u];
+    }
   };
   if (j0 < j1) {
 #pragma unroll
@@ -652,14 +652,10 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
         }
       }
 #pragma unroll
-      for (int k = 0; k < RB; ++k)
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const bool use = ok && 16 * u + i16 < nm;
-          const double2 G = cmul(gn[sl][k], vn[sl][u]);
-          br[k * NU + u] = use ? (T)G.x : T(0);
-          bi[k * NU + u] = use ? (T)G.y : T(0);
-        }
+      for (int u = 0; u < NC; ++u) {
+        br[u] = ok ? (T)bn[sl][u].x : T(0);
+        bi[u] = ok ? (T)bn[sl][u].y : T(0);
+      }
       fetch(sl, js + 4 * S);
       mfma_cstep<T, NT, NC, SommForm<T>::k3MDis>(ar, ai, a3, er, ei, br, bi);
     }
@@ -731,6 +727,22 @@ __global__ void somm_xpad_kernel(int n, int pmb, int nw, const int *__restrict__
                               : make_double2(0.0, 0.0);
 }
 
+// The disaggregate's B operand: the reflected node amplitudes times the
+// power table, B[r][w][j][k] = g[r][w][j] V_w[j][k], zero beyond the table's
+// 2 PM + 1 modes, so the matrix-core loop reads it as one padded row.
+__global__ void somm_bpad_kernel(int q, int nm, int nw, const double2 *__restrict__ g,
+                                 const double2 *__restrict__ Vp_t,
+                                 const double2 *__restrict__ Vs_t, double2 *__restrict__ bp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = blockIdx.y, r = blockIdx.z;
+  if (i >= (int64_t)q * nw) return;
+  const int j = (int)(i / nw), k = (int)(i - (int64_t)j * nw);
+  const double2 *Vt = w ? Vs_t : Vp_t;
+  bp[((int64_t)(r * 2 + w) * q + j) * nw + k] =
+      k < nm ? cmul(g[(int64_t)(r * 2 + w) * q + j], Vt[(int64_t)j * nm + k])
+             : make_double2(0.0, 0.0);
+}
+
 // Operands of one matrix-core launch: the table (nullptr: the exponentials
 // are formed in registers from the node coefficients), the node coefficients
 // of the register form, the power tables.
@@ -773,14 +785,12 @@ static void dis_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, 
   const int nm = 2 * pm_bucket(h->pmax) + 1;
   if (o.E)
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, o.Vp, o.Vs, h->d_refl,
-                       h->d_dis, h->ncoef, h->dis_chunks, per, o.E, h->d_sperm,
-                       (const int2 *)cut, o.gco, h->d_xys);
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, h->d_bpad, h->d_dis, h->ncoef,
+                       h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
   else
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, o.Vp, o.Vs, h->d_refl,
-                       h->d_dis, h->ncoef, h->dis_chunks, per, o.E, h->d_sperm,
-                       (const int2 *)cut, o.gco, h->d_xys);
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, h->d_bpad, h->d_dis, h->ncoef,
+                       h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
 }
 template <typename T, int NU>
 static void dis_cand(const ems_handle *h, int idx, int nrhs, int per, const SommOps<T> &o,
@@ -858,6 +868,14 @@ hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec
   const double2 *Vp = adj ? h->d_VpA_dis : h->d_Vp, *Vs = adj ? h->d_VsA_dis : h->d_Vs;
   const SommOps<double> o64{adj ? h->d_EdisA : h->d_Edis, gco, Vp, Vs};
   const SommOps<float> o32{h->d_Edis32, gco, Vp, Vs};
+  if (nrhs > h->ws_nrhs || !h->d_bpad) return hipErrorInvalidValue;
+  {
+    const int nw = 16 * nu;
+    hipLaunchKernelGGL(somm_bpad_kernel, dim3((unsigned)(((int64_t)h->q * nw + 255) / 256), 2, nrhs),
+                       dim3(256), 0, st, h->q, nm, nw, h->d_refl, Vp, Vs, h->d_bpad);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
 #define EMS_DISM_NU(NUV)                                                                     \
   if (nu == NUV) {                                                                           \
     if (prec == 1) dis_cand<float, NUV>(h, idx, nrhs, per, o32, st, cut);                   \
