@@ -174,40 +174,63 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
   const int row0 = 16 * it_rt[it], tile = it_tile[it];
   const int r = blockIdx.y;
   const double2 *M = mult + (int64_t)r * stride + g_off[g];
-  Acc ar = Acc{0, 0, 0, 0}, ai = Acc{0, 0, 0, 0};
+  // 3M complex products: K1 += (Ar + Ai) Br, K2 += Ar (Bi - Br),
+  // K3 += Ai (Br + Bi); Re = K1 - K3, Im = K1 + K2 after the loop.
+  Acc k1 = Acc{0, 0, 0, 0}, k2 = Acc{0, 0, 0, 0}, k3 = Acc{0, 0, 0, 0};
   const int krow = row0 + i16;  // A row of this lane
-  for (int e = it_e0[it]; e < it_e1[it]; ++e) {
-    const double2 *sym = pool + ent_sym[e];
-    const int sb = ent_src[(int64_t)e * kM2lCols + i16];
-    const double2 *Mb = M + (int64_t)(sb < 0 ? 0 : sb) * N;
-    auto load = [&](int j0, double2 (&a)[kM2lKB], double2 (&b)[kM2lKB]) {
+  const int e0 = it_e0[it], e1 = it_e1[it];
+  // The operand stream runs over (entry, chunk of kM2lKB K steps) without a
+  // break between entries: the last chunk of an entry loads the first chunk
+  // of the next one, whose symbol offset and source box are loaded one
+  // entry ahead.
+  auto entry = [&](int e, const double2 *&sym, const double2 *&Mb, bool &live) {
+    const int ee = min(e, e1 - 1);
+    sym = pool + ent_sym[ee];
+    const int sb = ent_src[(int64_t)ee * kM2lCols + i16];
+    live = sb >= 0;
+    Mb = M + (int64_t)(sb < 0 ? 0 : sb) * N;
+  };
+  auto load = [&](const double2 *sym, const double2 *Mb, bool live, int j0,
+                  double2 (&a)[kM2lKB], double2 (&b)[kM2lKB]) {
 #pragma unroll
-      for (int u = 0; u < kM2lKB; ++u) {
-        const int jj = j0 + 4 * u + kq;
-        const int nu = min(max(jj - krow, -2 * P), 2 * P);
-        a[u] = sym[nu];
-        b[u] = (sb >= 0 && jj < N) ? Mb[jj] : make_double2(0.0, 0.0);
-      }
-    };
+    for (int u = 0; u < kM2lKB; ++u) {
+      const int jj = j0 + 4 * u + kq;
+      const int nu = min(max(jj - krow, -2 * P), 2 * P);
+      a[u] = sym[nu];
+      b[u] = (live && jj < N) ? Mb[jj] : make_double2(0.0, 0.0);
+    }
+  };
+  if (e0 < e1) {
+    const double2 *symc, *Mbc, *symn, *Mbn;
+    bool livec, liven;
+    entry(e0, symc, Mbc, livec);
+    entry(e0 + 1, symn, Mbn, liven);
     double2 ca[kM2lKB], cb[kM2lKB], na[kM2lKB], nb[kM2lKB];
-    load(0, ca, cb);
-    for (int j0 = 0; j0 < N; j0 += 4 * kM2lKB) {
-      if (j0 + 4 * kM2lKB < N) load(j0 + 4 * kM2lKB, na, nb);
+    load(symc, Mbc, livec, 0, ca, cb);
+    for (int e = e0; e < e1; ++e) {
+      for (int j0 = 0; j0 < N; j0 += 4 * kM2lKB) {
+        if (j0 + 4 * kM2lKB < N) load(symc, Mbc, livec, j0 + 4 * kM2lKB, na, nb);
+        else if (e + 1 < e1) load(symn, Mbn, liven, 0, na, nb);
 #pragma unroll
-      for (int u = 0; u < kM2lKB; ++u) {
-        const T are = (T)ca[u].x, aim = (T)ca[u].y, bre = (T)cb[u].x, bim = (T)cb[u].y;
-        ar = M2lM<T>::mf(are, bre, ar);
-        ai = M2lM<T>::mf(are, bim, ai);
-        ar = M2lM<T>::mf(aim, -bim, ar);
-        ai = M2lM<T>::mf(aim, bre, ai);
-      }
+        for (int u = 0; u < kM2lKB; ++u) {
+          const T are = (T)ca[u].x, aim = (T)ca[u].y, bre = (T)cb[u].x, bim = (T)cb[u].y;
+          k1 = M2lM<T>::mf(are + aim, bre, k1);
+          k2 = M2lM<T>::mf(are, bim - bre, k2);
+          k3 = M2lM<T>::mf(aim, bre + bim, k3);
+        }
 #pragma unroll
-      for (int u = 0; u < kM2lKB; ++u) {
-        ca[u] = na[u];
-        cb[u] = nb[u];
+        for (int u = 0; u < kM2lKB; ++u) {
+          ca[u] = na[u];
+          cb[u] = nb[u];
+        }
       }
+      symc = symn;
+      Mbc = Mbn;
+      livec = liven;
+      entry(e + 2, symn, Mbn, liven);
     }
   }
+  const Acc ar = k1 - k3, ai = k1 + k2;
   // accumulator element v: row M2lM::row(kq, v), box column i16
   const int b = tile_box[(int64_t)tile * kM2lCols + i16];
   if (b < 0) return;
