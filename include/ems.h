@@ -338,8 +338,8 @@ int ems_apply_graph(ems_handle *h, const void *x, void *y, int32_t nrhs, int32_t
  * chunk counts of the Sommerfeld contractions are halved until the workspace
  * fits; when it does not fit with one chunk each, EMS_ERR_ARG (use fewer
  * right-hand sides; one right-hand side of the 20000-particle cloud needs
- * about 154 MB, most of it the FMM's M2L partial slots and the free-space
- * output).  The array is shared by every handle and call on that GPU and
+ * about 204 MB: the FMM's M2L partial slots, the padded operands of the
+ * Sommerfeld contractions and the free-space output).  The array is shared by every handle and call on that GPU and
  * keeps the last call's contents; each call clears the part it uses first.
  * Calls that overlap on one GPU (two streams, two threads) race on it and
  * must be serialized by the caller.  EMS_ERR_STATE while kernel profiling
