@@ -124,6 +124,12 @@ typedef struct {
                         (<= 0: 1e-3, above the floor the FP32 products leave) */
   int32_t precond;   /* 0: none; 1: cluster block-Jacobi right preconditioner
                         (ems_set_precond), M^{-H} for the adjoint solve         */
+  int32_t block;     /* 0: independent GMRES per right-hand side (lock-step);
+                        1: block GMRES, one Krylov space for each group of up
+                        to 64 right-hand sides (precision 0 only); restart
+                        then counts block steps (<= 0: from free memory, at
+                        most 8192 basis vectors per group) and maxit block
+                        steps per group                                      */
 } ems_solver_opts;
 
 typedef struct {

@@ -83,7 +83,7 @@ class PlaneWave(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -571,15 +571,17 @@ class Operator:
         return g
 
     def solve(self, b, tol=1e-10, restart=200, maxit=1000, precision=0, inner_tol=0.0,
-              stream=None, adjoint=False, precond=0):
+              stream=None, adjoint=False, precond=0, block=False):
         """GMRES on A (or A^H with adjoint=True); precision 1 = mixed iterative
         refinement; precond 1 = cluster block-Jacobi right preconditioner;
-        restart 0 = as large as half of the free device memory allows."""
+        restart 0 = as large as half of the free device memory allows; block =
+        one Krylov space per group of up to 64 right-hand sides (FP64; restart
+        and maxit then count block steps)."""
         import torch
         nrhs = self._vec_check(b)
         x = torch.empty_like(b)
         o = SolverOpts(float(tol), int(restart), int(maxit), int(precision), float(inner_tol),
-                       int(precond))
+                       int(precond), 1 if block else 0)
         info = SolveInfo()
         fn = _lib.ems_solve_adjoint if adjoint else _lib.ems_solve
         rc = fn(self.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),

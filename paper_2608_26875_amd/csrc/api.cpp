@@ -1861,6 +1861,333 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
   return EMS_OK;
 }
 
+// Cholesky G = R^H R of an s x s Hermitian matrix (row-major), R upper; false
+// when a pivot falls below rel_piv times the largest diagonal entry (the
+// block is numerically rank deficient).
+bool chol_upper(const std::vector<cd> &G, int s, std::vector<cd> &R, double rel_piv) {
+  R.assign((size_t)s * s, cd(0.0));
+  double gmax = 0.0;
+  for (int i = 0; i < s; ++i) gmax = std::max(gmax, G[(size_t)i * s + i].real());
+  for (int i = 0; i < s; ++i) {
+    double d = G[(size_t)i * s + i].real();
+    for (int l = 0; l < i; ++l) d -= std::norm(R[(size_t)l * s + i]);
+    if (!(d > rel_piv * gmax) || !std::isfinite(d)) return false;
+    const double rii = std::sqrt(d);
+    R[(size_t)i * s + i] = rii;
+    for (int c = i + 1; c < s; ++c) {
+      cd v = G[(size_t)i * s + c];
+      for (int l = 0; l < i; ++l) v -= std::conj(R[(size_t)l * s + i]) * R[(size_t)l * s + c];
+      R[(size_t)i * s + c] = v / rii;
+    }
+  }
+  return true;
+}
+
+// Inverse of an upper triangular s x s matrix (row-major).
+std::vector<cd> inv_upper(const std::vector<cd> &R, int s) {
+  std::vector<cd> X((size_t)s * s, cd(0.0));
+  for (int c = 0; c < s; ++c) {
+    X[(size_t)c * s + c] = 1.0 / R[(size_t)c * s + c];
+    for (int i = c - 1; i >= 0; --i) {
+      cd v = 0.0;
+      for (int l = i + 1; l <= c; ++l) v += R[(size_t)i * s + l] * X[(size_t)l * s + c];
+      X[(size_t)i * s + c] = -v / R[(size_t)i * s + i];
+    }
+  }
+  return X;
+}
+
+std::vector<double2> to_dev_layout(const std::vector<cd> &a) {
+  std::vector<double2> o(a.size());
+  for (size_t i = 0; i < a.size(); ++i) o[i] = make_double2(a[i].real(), a[i].imag());
+  return o;
+}
+
+// Block GMRES (Section 4.2 and 5.2 systems, several right-hand sides sharing
+// one Krylov space): for the s <= 64 columns of b, the block Arnoldi process
+// on A M^{-1} (right preconditioning, or A) with block classical
+// Gram-Schmidt run twice (bdot / baxpy on the matrix cores) and the new block
+// orthonormalised by Cholesky QR run twice; the block upper Hessenberg matrix
+// is reduced by Givens rotations on the host (its s sub-diagonals), so every
+// column's residual estimate is known after each block step.  A cycle ends
+// after mblk block steps, when every column meets tol, or at a breakdown;
+// x += M^{-1} V Y, then the next cycle starts from the true residual of the
+// columns that still miss tol (converged columns leave the block).
+// op(in, out, cnt) / prec(in, out, cnt) act on cnt stacked vectors.
+template <typename Op, typename Prec>
+int block_gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
+                    int s0, double tol, int mblk, int maxit, hipStream_t st, int &iters,
+                    double &relres) {
+  const int64_t n = h->ncoef;
+  const size_t vec = (size_t)n;
+  mblk = std::max(1, std::min(mblk, maxit));
+  const size_t vbytes = sizeof(double2) * (size_t)(mblk + 1) * s0 * vec;
+  if (h->V_bytes < vbytes) {
+    if (h->d_V) (void)hipFree(h->d_V);
+    h->d_V = nullptr;
+    h->V_bytes = 0;
+    HIPCHK(h, hipMalloc(&h->d_V, vbytes));
+    h->V_bytes = vbytes;
+  }
+  int rc = ensure_tmp(h, sizeof(double2) * 2 * s0 * vec);
+  if (rc) return rc;
+  if (use_prec && (rc = ensure_pcz(h, s0))) return rc;
+  const int kmax = (mblk + 1) * s0;
+  const size_t hlen = (size_t)kmax * s0;
+  const size_t plen = (size_t)ems::bdot_chunks(kmax, n) * kmax * s0 + (size_t)32768 * s0;
+  rc = ensure_red(h, sizeof(double2) * (hlen + plen + s0 * s0) + 8 * sizeof(double) +
+                         sizeof(double2) * ems::kRedBlocks);
+  if (rc) return rc;
+  double2 *Hd = reinterpret_cast<double2 *>(h->d_red);
+  double2 *part = Hd + hlen;
+  double2 *Sd = part + plen;  // s x s factors on device
+  double *d_nrm = reinterpret_cast<double *>(Sd + (size_t)s0 * s0);
+  double *scratch = d_nrm + 8;
+  double2 *W = h->d_tmp, *Qv = h->d_tmp + (size_t)s0 * vec;
+  double2 *Z = h->d_pcz;
+  double2 *V = h->d_V;
+
+  auto col_norms = [&](const double2 *v, int cnt, std::vector<double> &out) -> int {
+    out.assign(cnt, 0.0);
+    for (int c = 0; c < cnt; ++c) {
+      HIPCHK(h, ems::launch_norm2(v + (size_t)c * vec, n, d_nrm, scratch, st));
+      HIPCHK(h, hipMemcpyAsync(&out[c], d_nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(h, hipStreamSynchronize(st));
+    }
+    return EMS_OK;
+  };
+  auto gram = [&](const double2 *A, int k, const double2 *B, int cnt, std::vector<cd> &out) -> int {
+    HIPCHK(h, ems::launch_bdot(A, k, B, cnt, n, Hd, part, st));
+    std::vector<double2> t((size_t)k * cnt);
+    HIPCHK(h, hipMemcpyAsync(t.data(), Hd, sizeof(double2) * t.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    out.resize(t.size());
+    for (size_t i = 0; i < t.size(); ++i) out[i] = cd(t[i].x, t[i].y);
+    return EMS_OK;
+  };
+  // out = in * F (cnt vectors, F cnt x cnt row-major on the host)
+  auto transform = [&](const double2 *in, int cnt, const std::vector<cd> &F, double2 *out) -> int {
+    const auto f = to_dev_layout(F);
+    HIPCHK(h, hipMemcpyAsync(Sd, f.data(), sizeof(double2) * f.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(h, ems::launch_baxpy(in, cnt, Sd, cnt, n, out, 1.0, 0.0, st));
+    return EMS_OK;
+  };
+  // Cholesky QR twice, the first on the column-scaled Gram matrix: out =
+  // in T^{-1} orthonormal, T upper (in is used as scratch); ok = false when a
+  // scaled pivot falls below 1e-14 (the block is numerically rank deficient)
+  auto cholqr2 = [&](double2 *in, int cnt, double2 *out, std::vector<cd> &T, bool &ok) -> int {
+    std::vector<cd> G, R1, R2;
+    ok = false;
+    int r;
+    if ((r = gram(in, cnt, in, cnt, G))) return r;
+    std::vector<double> d(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      d[i] = std::sqrt(std::max(G[(size_t)i * cnt + i].real(), 0.0));
+      if (!(d[i] > 0)) return EMS_OK;
+    }
+    for (int i = 0; i < cnt; ++i)
+      for (int c = 0; c < cnt; ++c) G[(size_t)i * cnt + c] /= d[i] * d[c];
+    if (!chol_upper(G, cnt, R1, 1e-14)) return EMS_OK;
+    std::vector<cd> F = inv_upper(R1, cnt);
+    for (int i = 0; i < cnt; ++i)
+      for (int c = 0; c < cnt; ++c) F[(size_t)i * cnt + c] /= d[i];
+    if ((r = transform(in, cnt, F, out))) return r;
+    for (int i = 0; i < cnt; ++i)
+      for (int c = 0; c < cnt; ++c) R1[(size_t)i * cnt + c] *= d[c];
+    if ((r = gram(out, cnt, out, cnt, G))) return r;
+    if (!chol_upper(G, cnt, R2, 1e-14)) return EMS_OK;
+    if ((r = transform(out, cnt, inv_upper(R2, cnt), in))) return r;
+    HIPCHK(h, hipMemcpyAsync(out, in, sizeof(double2) * cnt * vec, hipMemcpyDeviceToDevice, st));
+    T.assign((size_t)cnt * cnt, cd(0.0));
+    for (int i = 0; i < cnt; ++i)
+      for (int c = i; c < cnt; ++c) {
+        cd v = 0.0;
+        for (int l = i; l <= c; ++l) v += R2[(size_t)i * cnt + l] * R1[(size_t)l * cnt + c];
+        T[(size_t)i * cnt + c] = v;
+      }
+    ok = true;
+    return EMS_OK;
+  };
+
+  std::vector<double> bnorm;
+  if ((rc = col_norms(b, s0, bnorm))) return rc;
+  iters = 0;
+  relres = 0.0;
+  bool first = true;
+  while (true) {
+    // true residual of every column, the active ones gathered into W
+    std::vector<double> rn;
+    if (first) {
+      HIPCHK(h, hipMemcpyAsync(Qv, b, sizeof(double2) * s0 * vec, hipMemcpyDeviceToDevice, st));
+    } else {
+      if ((rc = op(x, Qv, s0))) return rc;
+      for (int c = 0; c < s0; ++c) {
+        HIPCHK(h, ems::launch_scale(Qv + c * vec, n, -1.0, st));
+        HIPCHK(h, ems::launch_axpy(Qv + c * vec, b + c * vec, n, 1.0, st));
+      }
+    }
+    first = false;
+    if ((rc = col_norms(Qv, s0, rn))) return rc;
+    std::vector<int> act;
+    relres = 0.0;
+    for (int c = 0; c < s0; ++c) {
+      const double rel = bnorm[c] > 0 ? rn[c] / bnorm[c] : 0.0;
+      relres = std::max(relres, rel);
+      if (bnorm[c] > 0 && rel > tol) act.push_back(c);
+    }
+    if (act.empty() || iters >= maxit) break;
+    // The cycle's block: residual columns taken by decreasing relative size
+    // while they stay independent (pivoted Cholesky of the column-scaled Gram
+    // matrix, scaled pivot above 1e-10); a column close to the span of the
+    // others waits for a later cycle.
+    {
+      std::sort(act.begin(), act.end(), [&](int a, int c) {
+        return rn[a] / bnorm[a] > rn[c] / bnorm[c];
+      });
+      const int na = (int)act.size();
+      for (int a = 0; a < na; ++a)
+        HIPCHK(h, hipMemcpyAsync(W + (size_t)a * vec, Qv + (size_t)act[a] * vec,
+                                 sizeof(double2) * vec, hipMemcpyDeviceToDevice, st));
+      std::vector<cd> G;
+      if ((rc = gram(W, na, W, na, G))) return rc;
+      std::vector<double> d(na);
+      for (int a = 0; a < na; ++a) d[a] = std::sqrt(std::max(G[(size_t)a * na + a].real(), 1e-300));
+      std::vector<int> keep;          // positions in act
+      std::vector<std::vector<cd>> L;  // rows of the partial factor (scaled)
+      for (int a = 0; a < na; ++a) {
+        std::vector<cd> row(keep.size());
+        // row a of the lower factor of the scaled Gram matrix over the kept columns
+        for (size_t t = 0; t < keep.size(); ++t) {
+          cd v = G[(size_t)a * na + keep[t]] / (d[a] * d[keep[t]]);
+          for (size_t l = 0; l < t; ++l) v -= row[l] * std::conj(L[t][l]);
+          row[t] = v / L[t][t];
+        }
+        double piv = 1.0;
+        for (const auto &v : row) piv -= std::norm(v);
+        if (piv > 1e-10) {
+          row.push_back(std::sqrt(piv));
+          L.push_back(row);
+          keep.push_back(a);
+        }
+      }
+      std::vector<int> sel;
+      for (int a : keep) sel.push_back(act[a]);
+      act.swap(sel);
+    }
+    const int sa = (int)act.size();
+    for (int a = 0; a < sa; ++a)
+      HIPCHK(h, hipMemcpyAsync(W + (size_t)a * vec, Qv + (size_t)act[a] * vec,
+                               sizeof(double2) * vec, hipMemcpyDeviceToDevice, st));
+    // W = V_0 beta
+    std::vector<cd> beta;
+    bool ok = false;
+    if ((rc = cholqr2(W, sa, V, beta, ok))) return rc;
+    if (!ok) return fail(h, EMS_ERR_NUMERIC, "block GMRES: residual block is rank deficient");
+    // band Hessenberg columns, their rotations, and the rotated right-hand sides
+    const int ncol = mblk * sa;
+    std::vector<std::vector<cd>> Hc;
+    std::vector<cd> rcs((size_t)ncol * sa), rsn((size_t)ncol * sa);
+    std::vector<cd> Gr((size_t)(mblk + 1) * sa * sa, cd(0.0));  // [row][column]
+    for (int i = 0; i < sa; ++i)
+      for (int c = 0; c < sa; ++c) Gr[(size_t)i * sa + c] = beta[(size_t)i * sa + c];
+    auto rotate = [&](cd cs, cd sn, cd &u, cd &v) {
+      const cd t = cs * u + sn * v;
+      v = -std::conj(sn) * u + std::conj(cs) * v;
+      u = t;
+    };
+    int J = 0;  // completed block steps of this cycle
+    bool breakdown = false;
+    for (int j = 0; j < mblk && iters < maxit; ++j) {
+      const double2 *Vj = V + (size_t)j * sa * vec;
+      if (use_prec) {
+        if ((rc = prec(Vj, Z, sa))) return rc;
+        if ((rc = op(Z, W, sa))) return rc;
+      } else if ((rc = op(Vj, W, sa))) {
+        return rc;
+      }
+      ++iters;
+      const int k = (j + 1) * sa;
+      std::vector<cd> hs((size_t)k * sa, cd(0.0)), hp;
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = gram(V, k, W, sa, hp))) return rc;
+        HIPCHK(h, ems::launch_baxpy(V, k, Hd, sa, n, W, -1.0, 1.0, st));
+        for (size_t e = 0; e < hs.size(); ++e) hs[e] += hp[e];
+      }
+      std::vector<cd> T;
+      if ((rc = cholqr2(W, sa, V + (size_t)k * vec, T, ok))) return rc;
+      if (!ok) {
+        T.assign((size_t)sa * sa, cd(0.0));
+        breakdown = true;
+      }
+      // new columns js .. js + s - 1: rows 0 .. k + s - 1
+      for (int q = 0; q < sa; ++q) {
+        const int c = j * sa + q;
+        std::vector<cd> col((size_t)c + sa + 1, cd(0.0));
+        for (int i = 0; i < k; ++i) col[i] = hs[(size_t)i * sa + q];
+        for (int i = 0; i <= q; ++i) col[(size_t)k + i] = T[(size_t)i * sa + q];
+        for (int cp = 0; cp < c; ++cp)
+          for (int t = 0; t < sa; ++t) {
+            const int row = cp + sa - t;  // rotation of rows (row - 1, row)
+            rotate(rcs[(size_t)cp * sa + t], rsn[(size_t)cp * sa + t], col[row - 1], col[row]);
+          }
+        for (int t = 0; t < sa; ++t) {
+          const int row = c + sa - t;
+          const cd a = col[row - 1], bb = col[row];
+          const double den = std::hypot(std::abs(a), std::abs(bb));
+          cd cs = 1.0, sn = 0.0;
+          if (den > 0) {
+            cs = std::conj(a) / den;
+            sn = std::conj(bb) / den;
+          }
+          rcs[(size_t)c * sa + t] = cs;
+          rsn[(size_t)c * sa + t] = sn;
+          rotate(cs, sn, col[row - 1], col[row]);
+          col[row] = 0.0;
+          for (int r = 0; r < sa; ++r)
+            rotate(cs, sn, Gr[(size_t)(row - 1) * sa + r], Gr[(size_t)row * sa + r]);
+        }
+        Hc.push_back(std::move(col));
+      }
+      J = j + 1;
+      // residual estimates: rows (j + 1) s .. (j + 2) s - 1 of the rotated RHS
+      double emax = 0.0;
+      for (int r = 0; r < sa; ++r) {
+        double e2 = 0.0;
+        for (int i = k; i < k + sa; ++i) e2 += std::norm(Gr[(size_t)i * sa + r]);
+        emax = std::max(emax, std::sqrt(e2) / bnorm[act[r]]);
+      }
+      h->hist.push_back(emax);
+      if (h->progress && h->progress_every > 0 && (int)h->hist.size() % h->progress_every == 0)
+        h->progress((int32_t)h->hist.size(), emax, h->progress_user);
+      if (emax <= tol || breakdown) break;
+    }
+    // Y = R^{-1} G (upper triangular, J s columns), then x += M^{-1} V Y
+    const int m = J * sa;
+    std::vector<cd> Y((size_t)m * sa, cd(0.0));
+    for (int r = 0; r < sa; ++r)
+      for (int i = m - 1; i >= 0; --i) {
+        cd v = Gr[(size_t)i * sa + r];
+        for (int l = i + 1; l < m; ++l) v -= Hc[l][i] * Y[(size_t)l * sa + r];
+        const cd d = Hc[i][i];
+        Y[(size_t)i * sa + r] = std::abs(d) > 0 ? v / d : cd(0.0);
+      }
+    {
+      const auto y = to_dev_layout(Y);
+      HIPCHK(h, hipMemcpyAsync(Hd, y.data(), sizeof(double2) * y.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(h, ems::launch_baxpy(V, m, Hd, sa, n, W, 1.0, 0.0, st));
+      const double2 *upd = W;
+      if (use_prec) {
+        if ((rc = prec(W, Z, sa))) return rc;
+        upd = Z;
+      }
+      for (int a = 0; a < sa; ++a)
+        HIPCHK(h, ems::launch_axpy(x + (size_t)act[a] * vec, upd + (size_t)a * vec, n, 1.0, st));
+      HIPCHK(h, hipStreamSynchronize(st));
+    }
+  }
+  return EMS_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -1919,6 +2246,9 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
   if (!(o->tol > 0) || o->maxit <= 0) return fail(h, EMS_ERR_ARG, "need tol > 0 and maxit > 0");
   if (o->precision != 0 && o->precision != 1) return fail(h, EMS_ERR_ARG, "precision must be 0 or 1");
   if (o->precond != 0 && o->precond != 1) return fail(h, EMS_ERR_ARG, "precond must be 0 or 1");
+  if (o->block != 0 && o->block != 1) return fail(h, EMS_ERR_ARG, "block must be 0 or 1");
+  if (o->block && o->precision != 0)
+    return fail(h, EMS_ERR_ARG, "block GMRES runs in FP64 (precision 0)");
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vec = (size_t)h->ncoef;
@@ -1954,7 +2284,40 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
     HIPCHK(h, ems::launch_pc_apply(h, in, out, nrhs, adjoint, st));
     return EMS_OK;
   };
-  if (o->precision == 0) {
+  if (o->block) {
+    // groups of up to 64 right-hand sides, each one block Krylov space
+    int mblk = o->restart;
+    if (mblk <= 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(h, hipMemGetInfo(&fr, &tot));
+      const size_t have = fr / 2 + h->V_bytes;
+      const int sg = std::min<int>(nrhs, 64);
+      const size_t per = sizeof(double2) * vec * sg;
+      // device basis from free memory; at most 8192 basis columns per cycle
+      // (the host keeps the rotated block Hessenberg, about 0.5 GB there)
+      mblk = (int)std::max<size_t>(2, std::min<size_t>(8192 / sg, have / per - 1));
+    }
+    restart = mblk;
+    relres = 0.0;
+    for (int g0 = 0; g0 < nrhs; g0 += 64) {
+      const int sg = std::min(64, nrhs - g0);
+      auto opb = [&](const double2 *in, double2 *out, int cnt) {
+        return apply_impl(h, in, out, cnt, EMS_APPLY_ALL, adjoint, st);
+      };
+      auto pcb = [&](const double2 *in, double2 *out, int cnt) {
+        ems::ProfScope ps(h, "precond_apply", st, 8.0 * (double)h->pc_store * cnt);
+        HIPCHK(h, ems::launch_pc_apply(h, in, out, cnt, adjoint, st));
+        return EMS_OK;
+      };
+      int it = 0;
+      double rr = 0.0;
+      rc = block_gmres_run(h, opb, pcb, use_prec, B + (size_t)g0 * vec, X + (size_t)g0 * vec, sg,
+                           o->tol, mblk, o->maxit, st, it, rr);
+      if (rc) return rc;
+      iters += it;
+      relres = std::max(relres, rr);
+    }
+  } else if (o->precision == 0) {
     std::vector<double> bn;
     rc = gmres_run(h, op64, pc, use_prec, B, X, nrhs, o->tol, restart, o->maxit, true, st, iters,
                    relres, bn, 1.0);

@@ -418,6 +418,14 @@ hipError_t launch_copy_scaled(const double2 *src, double2 *dst, int64_t n, doubl
 hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
                          int64_t n, hipStream_t st);
 hipError_t launch_axpy(double2 *y, const double2 *x, int64_t n, double a, hipStream_t st);
+// Block operations of the block Krylov solver (block.hip), s <= 64 columns:
+// H[i][c] = sum_r conj(V_i[r]) W_c[r] (k x s, row-major), with part holding
+// bdot_chunks(k, n) k s partial sums; out_c = beta out_c + alpha sum_i V_i H[i][c].
+int bdot_chunks(int k, int64_t n);
+hipError_t launch_bdot(const double2 *V, int k, const double2 *W, int s, int64_t n, double2 *H,
+                       double2 *part, hipStream_t st);
+hipError_t launch_baxpy(const double2 *V, int k, const double2 *H, int s, int64_t n,
+                        double2 *out, double alpha, double beta, hipStream_t st);
 
 // field evaluation
 hipError_t launch_repack(const ems_handle *src, const ems_handle *dst, const double2 *in,
