@@ -330,6 +330,20 @@ __device__ __forceinline__ void mfma_cfinish(typename Mfma<T>::Acc (&k1)[NT][NC]
     }
 }
 
+// Table entries are read exactly once per contraction: non-temporal loads
+// keep them from displacing the reused operands (the padded coefficients and
+// node operands) in the L2 cache.
+typedef double somm_d2v __attribute__((ext_vector_type(2)));
+typedef float somm_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 stream_load(const double2 *p) {
+  const somm_d2v v = __builtin_nontemporal_load(reinterpret_cast<const somm_d2v *>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 stream_load(const float2 *p) {
+  const somm_f2v v = __builtin_nontemporal_load(reinterpret_cast<const somm_f2v *>(p));
+  return make_float2(v.x, v.y);
+}
+
 // e^a (cos b, sin b) without the library's large-argument branches, which
 // cost registers the matrix-core loops need.  Cody-Waite reduction with
 // two-part constants and fused multiply-adds, a = k ln2 + r (|r| <= ln2/2)
@@ -490,7 +504,7 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
       ps[sl] = xys[mc];
     } else {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) en[sl][t] = Ew[(int64_t)mc * q + jl[t]];
+      for (int t = 0; t < NT; ++t) en[sl][t] = stream_load(Ew + (int64_t)mc * q + jl[t]);
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
       gj[sl] = gco[(int64_t)wave * q + jc];
     } else {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) en[sl][t] = Ew[(int64_t)jc * n + lc[t]];
+      for (int t = 0; t < NT; ++t) en[sl][t] = stream_load(Ew + (int64_t)jc * n + lc[t]);
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
