@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <type_traits>
 
 #include "ems_internal.h"
 
@@ -1648,16 +1649,16 @@ struct Givens {
 // stall > 0 (inner solves of the mixed refinement, whose FP32 products put a
 // floor under the reachable residual): a sweep also ends when its estimate
 // fell by less than 10 % over the last `stall` iterations.
-template <typename Op, typename Prec>
-int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
-              int nrhs, double tol, int restart, int maxit, bool x_zero, hipStream_t st,
-              int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale,
-              int stall = 0) {
+template <typename TB, typename Op, typename Prec>
+int gmres_basis(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
+                int nrhs, double tol, int restart, int maxit, bool x_zero, hipStream_t st,
+                int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale,
+                int stall) {
   const int64_t n = h->ncoef;
   const size_t vec = (size_t)n;
   restart = std::max(1, std::min(restart, maxit));
-  // basis V[k][r][n]
-  const size_t vbytes = sizeof(double2) * (size_t)(restart + 1) * nrhs * vec;
+  // basis V[k][r][n] (complex64 in the inner solves of the mixed refinement)
+  const size_t vbytes = sizeof(TB) * (size_t)(restart + 1) * nrhs * vec;
   if (h->V_bytes < vbytes) {
     if (h->d_V) (void)hipFree(h->d_V);
     h->d_V = nullptr;
@@ -1665,7 +1666,8 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
     HIPCHK(h, hipMalloc(&h->d_V, vbytes));
     h->V_bytes = vbytes;
   }
-  int rc = ensure_tmp(h, sizeof(double2) * 2 * nrhs * vec);
+  constexpr bool F32 = std::is_same<TB, float2>::value;
+  int rc = ensure_tmp(h, sizeof(double2) * (F32 ? 3 : 2) * nrhs * vec);
   if (rc) return rc;
   if (use_prec && (rc = ensure_pcz(h, nrhs))) return rc;
   // d_h, d_h2 [restart + 2] each, the norm result (restart + 2 + 8 slots
@@ -1680,7 +1682,18 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
   double2 *d_h2 = d_h + (restart + 2);
   double *d_nrm = reinterpret_cast<double *>(d_h2 + (restart + 2));
   double *scratch = reinterpret_cast<double *>(d_h2 + 2 * (restart + 2) + 8);
-  auto Vk = [&](int k, int r) { return h->d_V + ((size_t)k * nrhs + r) * vec; };
+  TB *Vb = reinterpret_cast<TB *>(h->d_V);
+  auto Vk = [&](int k, int r) { return Vb + ((size_t)k * nrhs + r) * vec; };
+  // the operator's input: the basis vectors themselves, or widened to FP64
+  double2 *Vin = h->d_tmp + (size_t)2 * nrhs * vec;
+  auto opnd = [&](int k) -> const double2 * {
+    if constexpr (F32) {
+      (void)ems::launch_widen(Vk(k, 0), Vin, (int64_t)nrhs * n, st);
+      return Vin;
+    } else {
+      return Vk(k, 0);
+    }
+  };
   const int64_t ldv = (int64_t)nrhs * n;
 
   std::vector<double> bnorm(nrhs), beta(nrhs);
@@ -1739,12 +1752,14 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
     bool stalled = false;
     for (; k < restart && iters < maxit; ++k) {
       // W = A V_k, or A M^{-1} V_k (all right-hand sides; inactive ones are ignored)
+      const double2 *vin = opnd(k);
+      HIPCHK(h, hipGetLastError());
       if (use_prec) {
-        rc = prec(Vk(k, 0), Z);
+        rc = prec(vin, Z);
         if (rc) return rc;
         rc = op(Z, W);
       } else {
-        rc = op(Vk(k, 0), W);
+        rc = op(vin, W);
       }
       if (rc) return rc;
       ++iters;
@@ -1859,6 +1874,21 @@ int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, 
     }
   }
   return EMS_OK;
+}
+
+// GMRES with an FP64 basis, or (f32_basis) a complex64 one: half the
+// Gram-Schmidt traffic, for the inner solves of the mixed refinement whose
+// tolerance stays far above the FP32 orthogonality level.
+template <typename Op, typename Prec>
+int gmres_run(ems_handle *h, Op op, Prec prec, bool use_prec, const double2 *b, double2 *x,
+              int nrhs, double tol, int restart, int maxit, bool x_zero, hipStream_t st,
+              int &iters, double &relres, std::vector<double> &bnorm_out, double hist_scale,
+              int stall = 0, bool f32_basis = false) {
+  if (f32_basis)
+    return gmres_basis<float2>(h, op, prec, use_prec, b, x, nrhs, tol, restart, maxit, x_zero, st,
+                               iters, relres, bnorm_out, hist_scale, stall);
+  return gmres_basis<double2>(h, op, prec, use_prec, b, x, nrhs, tol, restart, maxit, x_zero, st,
+                              iters, relres, bnorm_out, hist_scale, stall);
 }
 
 // Cholesky G = R^H R of an s x s Hermitian matrix (row-major), R upper; false
@@ -2347,8 +2377,9 @@ int solve_impl(ems_handle *h, const void *b, void *x, int32_t nrhs, const ems_so
       HIPCHK(h, hipMemsetAsync(D, 0, sizeof(double2) * vec * nrhs, st));
       // the inner solve needs no more than the factor still missing
       const double need = std::max(itol, 0.5 * o->tol / std::max(relres, 1e-300));
+      // complex64 basis while the inner tolerance stays above 1e-5
       rc = gmres_run(h, op32, pc, use_prec, R, D, nrhs, need, restart, o->maxit - iters, true, st,
-                     it, rr, tmp, relres, 200);
+                     it, rr, tmp, relres, 200, need >= 1e-5);
       if (rc) return rc;
       iters += it;
       for (int r = 0; r < nrhs; ++r)

@@ -403,12 +403,21 @@ hipError_t launch_s_multiply(const ems_handle *h, const double2 *c, double2 *y, 
                              hipStream_t st);
 
 // ---- small BLAS-like kernels for GMRES -------------------------------------
-// partial[i][b] = sum over chunk b of conj(V_i) . w   (i < k)
+// (the basis V in complex128, or complex64 for the mixed inner solves)
+// out[i] = conj(V_i) . w   (i < k)
 hipError_t launch_mdot(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                       double2 *out_dev, double *scratch, hipStream_t st);
+hipError_t launch_mdot(const float2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
                        double2 *out_dev, double *scratch, hipStream_t st);
 // w -= sum_i V_i c_i
 hipError_t launch_mupdate(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
                           int64_t n, hipStream_t st);
+hipError_t launch_mupdate(const float2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                          int64_t n, hipStream_t st);
+// dst = s src narrowed to complex64; dst = src widened to complex128
+hipError_t launch_copy_scaled(const double2 *src, float2 *dst, int64_t n, double s,
+                              hipStream_t st);
+hipError_t launch_widen(const float2 *src, double2 *dst, int64_t n, hipStream_t st);
 hipError_t launch_norm2(const double2 *w, int64_t n, double *out_dev, double *scratch,
                         hipStream_t st);
 hipError_t launch_scale(double2 *w, int64_t n, double s, hipStream_t st);
@@ -416,6 +425,8 @@ hipError_t launch_copy_scaled(const double2 *src, double2 *dst, int64_t n, doubl
                               hipStream_t st);
 // y += sum_i V_i c_i
 hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
+                         int64_t n, hipStream_t st);
+hipError_t launch_maccum(const float2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
                          int64_t n, hipStream_t st);
 hipError_t launch_axpy(double2 *y, const double2 *x, int64_t n, double a, hipStream_t st);
 // Block operations of the block Krylov solver (block.hip), s <= 64 columns:

@@ -421,19 +421,45 @@ __device__ double2 block_reduce(double2 v) {
   return r;
 }
 
-// partial[i][b] = sum_{rows in block b's stripe} conj(V_i[row]) w[row]
-__global__ __launch_bounds__(256) void mdot_kernel(const double2 *__restrict__ V, int64_t ldv,
-                                                  int k, const double2 *__restrict__ w,
-                                                  int64_t n, double2 *__restrict__ part) {
-  const int i = blockIdx.y;
-  const double2 *Vi = V + (int64_t)i * ldv;
-  double2 acc = make_double2(0.0, 0.0);
+// Basis element types of GMRES: complex128, or complex64 for the inner solves
+// of the mixed refinement (values are widened to FP64 on load).
+__device__ __forceinline__ double2 wide(double2 v) { return v; }
+__device__ __forceinline__ double2 wide(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+// partial[i][b] = sum_{rows in block b's stripe} conj(V_i[row]) w[row] for
+// MV consecutive basis vectors i per workgroup: w is read once for all of
+// them and one reduction serves MV sums.
+constexpr int kMdotV = 8;
+template <typename TB>
+__global__ __launch_bounds__(256) void mdot_kernel(const TB *__restrict__ V, int64_t ldv, int k,
+                                                  const double2 *__restrict__ w, int64_t n,
+                                                  double2 *__restrict__ part) {
+  const int i0 = blockIdx.y * kMdotV;
+  const int nv = min(kMdotV, k - i0);
+  double2 acc[kMdotV];
+#pragma unroll
+  for (int v = 0; v < kMdotV; ++v) acc[v] = make_double2(0.0, 0.0);
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
        row += (int64_t)gridDim.x * blockDim.x) {
-    cfma(acc, cconj(Vi[row]), w[row]);
+    const double2 wr = w[row];
+#pragma unroll
+    for (int v = 0; v < kMdotV; ++v)
+      if (v < nv) cfma(acc[v], cconj(wide(V[(int64_t)(i0 + v) * ldv + row])), wr);
   }
-  acc = block_reduce(acc);
-  if (threadIdx.x == 0) part[(int64_t)i * gridDim.x + blockIdx.x] = acc;
+  __shared__ double2 sh[kMdotV][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < kMdotV; ++v) {
+    const double2 r = warp_reduce(acc[v]);
+    if (lane == 0) sh[v][wid] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int v = threadIdx.x;
+    double2 r = make_double2(0.0, 0.0);
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) r = cadd(r, sh[v][q]);
+    part[(int64_t)(i0 + v) * gridDim.x + blockIdx.x] = r;
+  }
 }
 
 __global__ void finish_kernel(const double2 *__restrict__ part, int nb, int k,
@@ -445,36 +471,79 @@ __global__ void finish_kernel(const double2 *__restrict__ part, int nb, int k,
   if (threadIdx.x == 0) out[i] = acc;
 }
 
-hipError_t launch_mdot(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
-                       double2 *out_dev, double *scratch, hipStream_t st) {
+template <typename TB>
+static hipError_t mdot_go(const TB *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                          double2 *out_dev, double *scratch, hipStream_t st) {
   double2 *part = reinterpret_cast<double2 *>(scratch);
-  hipLaunchKernelGGL(mdot_kernel, dim3(kRedBlocks, k), dim3(256), 0, st, V, ldv, k, w, n, part);
+  hipLaunchKernelGGL(mdot_kernel<TB>, dim3(kRedBlocks, (k + kMdotV - 1) / kMdotV), dim3(256), 0,
+                     st, V, ldv, k, w, n, part);
   hipLaunchKernelGGL(finish_kernel, dim3(k), dim3(256), 0, st, part, kRedBlocks, k, out_dev);
   return hipGetLastError();
 }
+hipError_t launch_mdot(const double2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                       double2 *out_dev, double *scratch, hipStream_t st) {
+  return mdot_go(V, ldv, k, w, n, out_dev, scratch, st);
+}
+hipError_t launch_mdot(const float2 *V, int64_t ldv, int k, const double2 *w, int64_t n,
+                       double2 *out_dev, double *scratch, hipStream_t st) {
+  return mdot_go(V, ldv, k, w, n, out_dev, scratch, st);
+}
 
 // w -= sum_i V_i c_i  (c on device)
-__global__ __launch_bounds__(256) void mupdate_kernel(const double2 *__restrict__ V, int64_t ldv,
+template <typename TB>
+__global__ __launch_bounds__(256) void mupdate_kernel(const TB *__restrict__ V, int64_t ldv,
                                                      int k, const double2 *__restrict__ c,
                                                      double2 *__restrict__ w, int64_t n,
                                                      double sgn) {
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
        row += (int64_t)gridDim.x * blockDim.x) {
     double2 acc = make_double2(0.0, 0.0);
-    for (int i = 0; i < k; ++i) cfma(acc, V[(int64_t)i * ldv + row], c[i]);
+    for (int i = 0; i < k; ++i) cfma(acc, wide(V[(int64_t)i * ldv + row]), c[i]);
     w[row] = make_double2(w[row].x + sgn * acc.x, w[row].y + sgn * acc.y);
   }
 }
 
-hipError_t launch_mupdate(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
-                          int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(mupdate_kernel, dim3(2048), dim3(256), 0, st, V, ldv, k, c, w, n, -1.0);
+template <typename TB>
+static hipError_t mupdate_go(const TB *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                             int64_t n, double sgn, hipStream_t st) {
+  hipLaunchKernelGGL(mupdate_kernel<TB>, dim3(2048), dim3(256), 0, st, V, ldv, k, c, w, n, sgn);
   return hipGetLastError();
 }
-
+hipError_t launch_mupdate(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                          int64_t n, hipStream_t st) {
+  return mupdate_go(V, ldv, k, c, w, n, -1.0, st);
+}
+hipError_t launch_mupdate(const float2 *V, int64_t ldv, int k, const double2 *c, double2 *w,
+                          int64_t n, hipStream_t st) {
+  return mupdate_go(V, ldv, k, c, w, n, -1.0, st);
+}
 hipError_t launch_maccum(const double2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
                          int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(mupdate_kernel, dim3(2048), dim3(256), 0, st, V, ldv, k, c, y, n, 1.0);
+  return mupdate_go(V, ldv, k, c, y, n, 1.0, st);
+}
+hipError_t launch_maccum(const float2 *V, int64_t ldv, int k, const double2 *c, double2 *y,
+                         int64_t n, hipStream_t st) {
+  return mupdate_go(V, ldv, k, c, y, n, 1.0, st);
+}
+
+// Narrowing and widening copies between the FP64 vectors and an FP32 basis.
+__global__ void copy_scaled_f32_kernel(const double2 *src, float2 *dst, int64_t n, double s) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x)
+    dst[row] = make_float2((float)(s * src[row].x), (float)(s * src[row].y));
+}
+__global__ void widen_kernel(const float2 *src, double2 *dst, int64_t n) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n;
+       row += (int64_t)gridDim.x * blockDim.x)
+    dst[row] = wide(src[row]);
+}
+hipError_t launch_copy_scaled(const double2 *src, float2 *dst, int64_t n, double s,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(copy_scaled_f32_kernel, dim3(2048), dim3(256), 0, st, src, dst, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_widen(const float2 *src, double2 *dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(widen_kernel, dim3(2048), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 
