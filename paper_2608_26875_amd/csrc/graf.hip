@@ -38,7 +38,9 @@ __device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(
 __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
 
-template <int PM, bool MIXED, int RB, bool STORED>
+// ADJ: the adjoint map (a compile-time choice, so the inner products carry no
+// per-element branch); the tabulated symbols serve only the forward map.
+template <int PM, bool MIXED, int RB, bool STORED, bool ADJ>
 __global__ __launch_bounds__(128) void graf_direct_kernel(
     int n, int nrhs, const double *__restrict__ xy, const int *__restrict__ p,
     const int64_t *__restrict__ off, const double2 *__restrict__ x, int64_t ldx,
@@ -46,6 +48,8 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
     const int *__restrict__ nbr_ptr, const int *__restrict__ nbr_idx,
     const double2 *__restrict__ nsym, const int64_t *__restrict__ nbr_off,
     const int *__restrict__ nbr_p) {
+  static_assert(!(STORED && ADJ), "tabulated near-field symbols are forward only");
+  (void)adjoint;
   using T = typename CT<MIXED>::T;
   constexpr int NT = 4 * PM + 1;
   constexpr int NM = 2 * PM + 1;
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
 #pragma unroll 8
           for (int jj = 0; jj < NM; ++jj) {
             const int nu = i - (jj - PM);
-            T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
+            T tv = ADJ ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
             cfma_any(acc[0], tv, c_lds[s][w][jj]);
           }
         }
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
       if (l < n && l != b) {
         // th_ml: angle of x_m - x_l (m target, l source of the forward map)
         double dx = bx - xy[2 * l], dy = by - xy[2 * l + 1];
-        if (adjoint) {
+        if (ADJ) {
           dx = -dx;
           dy = -dy;
         }
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(128) void graf_direct_kernel(
 #pragma unroll 8
           for (int jj = 0; jj < NM; ++jj) {
             const int nu = i - (jj - PM);
-            T tv = adjoint ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
+            T tv = ADJ ? conj_any(t_lds[w][s][2 * PM - nu]) : t_lds[w][s][2 * PM + nu];
             cfma_any(acc[rr], tv, c_lds[s][w][jj]);
           }
         }
@@ -246,20 +250,22 @@ __global__ __launch_bounds__(256) void near_symbols_kernel(int npairs, const dou
                   nsym + g * NT, [](double2 v) { return v; });
 }
 
-#define EMS_GRAF_LAUNCH(PMV, MIX, RBV, STV)                                                  \
-  hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV, STV>),                                  \
+#define EMS_GRAF_LAUNCH(PMV, MIX, RBV, STV, ADV)                                             \
+  hipLaunchKernelGGL((graf_direct_kernel<PMV, MIX, RBV, STV, ADV>),                             \
                      dim3(h->n, (nrhs + RBV - 1) / RBV), dim3(graf_threads(PMV)), 0, st, h->n,   \
                      nrhs, h->d_xy, h->d_p, h->d_off, x, h->ncoef, out, h->ncoef, h->md.kp,      \
                      h->md.ks, adjoint ? 1 : 0, nptr, nidx, h->d_nsym, h->d_nbr_off, h->d_nbr_p)
-#define EMS_GRAF_RB(PMV, MIX, STV)                                                           \
-  if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, MIX, 8, STV);                                           \
-  else EMS_GRAF_LAUNCH(PMV, MIX, 1, STV);
+#define EMS_GRAF_RB(PMV, MIX, STV, ADV)                                                      \
+  if (nrhs > 1) EMS_GRAF_LAUNCH(PMV, MIX, 8, STV, ADV);                                      \
+  else EMS_GRAF_LAUNCH(PMV, MIX, 1, STV, ADV);
+#define EMS_GRAF_GEN(PMV, MIX)                                                               \
+  if (adjoint) { EMS_GRAF_RB(PMV, MIX, false, true) } else { EMS_GRAF_RB(PMV, MIX, false, false) }
 #define EMS_GRAF_CASE(PMV)                                                                   \
   case PMV:                                                                                  \
     if (stored) {                                                                            \
-      if (mixed) { EMS_GRAF_RB(PMV, true, true) } else { EMS_GRAF_RB(PMV, false, true) }      \
+      if (mixed) { EMS_GRAF_RB(PMV, true, true, false) } else { EMS_GRAF_RB(PMV, false, true, false) } \
     } else {                                                                                 \
-      if (mixed) { EMS_GRAF_RB(PMV, true, false) } else { EMS_GRAF_RB(PMV, false, false) }    \
+      if (mixed) { EMS_GRAF_GEN(PMV, true) } else { EMS_GRAF_GEN(PMV, false) }                \
     }                                                                                        \
     break;
 
