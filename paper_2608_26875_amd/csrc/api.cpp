@@ -350,7 +350,7 @@ int ensure_ws(ems_handle *h, int nrhs) {
   h->agg_chunks = std::max(1, std::min(std::max(1, h->n / 8),
                                        (4096 + 2 * nrhs * node_tiles - 1) / (2 * nrhs * node_tiles)));
   h->dis_chunks = std::max(1, std::min(std::max(1, h->q / 32),
-                                       (4096 + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
+                                       (ems::kDisChunkTarget + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
   const size_t nc = (size_t)h->ncoef;
   HIPCHK(h, hipMalloc(&h->d_agg, sizeof(double2) * (size_t)nrhs * 2 * h->agg_chunks * h->q));
   HIPCHK(h, hipMalloc(&h->d_refl, sizeof(double2) * (size_t)nrhs * 2 * h->q));
@@ -2854,7 +2854,7 @@ extern "C" int ems_apply_noalloc(ems_handle *h, const void *x, void *y, int32_t 
   int agg = std::max(1, std::min(std::max(1, h->n / 8),
                                  (4096 + 2 * nrhs * node_tiles - 1) / (2 * nrhs * node_tiles)));
   int dis = std::max(1, std::min(std::max(1, h->q / 32),
-                                 (4096 + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
+                                 (ems::kDisChunkTarget + 2 * nrhs * part_tiles - 1) / (2 * nrhs * part_tiles)));
   auto need = [&](int a, int d, size_t *o) {
     size_t t = 0;
     o[0] = t; t += align256(c16 * nrhs * 2 * (size_t)a * h->q);   // aggregate partials

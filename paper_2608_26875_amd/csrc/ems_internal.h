@@ -24,6 +24,13 @@ constexpr int kMaxModes = 2 * kMaxP + 1;
 // blocks of the vector reductions (launch_norm2, launch_mdot): each writes
 // kRedBlocks complex partials per reduced vector into its scratch argument
 constexpr int kRedBlocks = 512;
+// Split-K chunks of the Sommerfeld disaggregate over the nodes: about this
+// many (particle tile, chunk, wave, right-hand side) slots per launch.  Every
+// chunk writes one partial coefficient vector that the combine kernel reads
+// back (26 chunks, 0.53 GB each way at 20000 particles); at 2048 or 1024 the
+// combine is faster but the FP64 disaggregate slower by more (fewer, longer
+// wavefronts over uneven depth-truncated node ranges).
+constexpr int kDisChunkTarget = 4096;
 
 struct Media {
   double lam_h, mu_h, rho_h, lam_b, mu_b, rho_b, omega;
