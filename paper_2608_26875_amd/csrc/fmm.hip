@@ -213,6 +213,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
         else if (e + 1 < e1) load(symn, Mbn, liven, 0, na, nb);
 #pragma unroll
         for (int u = 0; u < kM2lKB; ++u) {
+          if (j0 + 4 * u >= N) break;  // K steps past 2P+1 (uniform over the wave)
           const T are = (T)ca[u].x, aim = (T)ca[u].y, bre = (T)cb[u].x, bim = (T)cb[u].y;
           k1 = M2lM<T>::mf(are + aim, bre, k1);
           k2 = M2lM<T>::mf(are, bim - bre, k2);
