@@ -251,15 +251,17 @@ template <> struct Mfma<float> {
 };
 
 // Per kernel and precision: the complex product form (three or four real
-// MFMAs per complex tile) and the operand slots in flight per wave.  Measured
-// at 20000 particles, order 15, against four MFMAs with two slots (aggregate)
-// and one (disaggregate): the 3M form takes the FP64 aggregate from 2.83 to
-// 2.63 ms and, with four slots, the FP32 aggregate and disaggregate down 7 %
-// and 13 %; in the FP64 disaggregate it costs occupancy (2.51 against 3.13 ms),
-// and more FP64 slots did not pay.
+// MFMAs per complex tile) and the operand slots in flight per wave.  Both
+// contractions take the 3M form; both kernels are compiled for four
+// wavefronts per SIMD (amdgpu_waves_per_eu), which puts the accumulators in
+// ordinary vector registers next to the operand slots without spills for the
+// default tiles.  Measured at 20000 particles, order 15: the FP64 aggregate
+// went from 2.54 to 1.92 ms and the FP64 disaggregate from 2.52 (four MFMAs,
+// one slot, three waves) to 2.27 ms; the FP32 forms to 1.12 and 1.21 ms.
+// More FP64 slots did not pay.
 template <typename T> struct SommForm {
   static constexpr bool kFp32 = std::is_same<T, float>::value;
-  static constexpr bool k3MAgg = true, k3MDis = kFp32;
+  static constexpr bool k3MAgg = true, k3MDis = true;
   static constexpr int kSlotsAgg = kFp32 ? 4 : 2, kSlotsDis = kFp32 ? 4 : 1;
 };
 
@@ -455,7 +457,7 @@ __device__ __forceinline__ void gen_exp(const double4 &g, const double2 &ps, T &
 // xp: the coefficients in depth order, modes -PM .. 16 NU - 1 - PM
 // (somm_xpad_kernel), [nrhs][wave][n][16 NU].
 template <typename T, int NU, int NT, int RB, bool GEN>
-__global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void somm_aggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const double2 *__restrict__ xp,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     double2 *__restrict__ agg, int chunks, int per_chunk,
@@ -580,7 +582,7 @@ __global__ __launch_bounds__(256) void somm_aggregate_mfma_kernel(
 template <typename T, int NU, int NT, int RB, bool GEN>
 // bp: the B operand RW_j V[j][k], zero-padded to 16 NU modes
 // (somm_bpad_kernel), [nrhs][wave][q][16 NU].
-__global__ __launch_bounds__(256) void somm_disaggregate_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const double2 *__restrict__ bp, double2 *__restrict__ dis, int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
