@@ -142,10 +142,12 @@ struct FmmLaunch {
 // different interaction lists; the top level is one group), form column
 // tiles of kM2lCols target boxes; a tile's entries are the offsets any of its
 // boxes uses, each with the pool index of s^o_0 and one source box per
-// column (-1: none).  A work item (one wavefront) is 16 rows of one tile over
-// a contiguous group of its entries; with G > 1 groups per tile the items
-// write partial slots that a reduction adds in a fixed order.
+// column (-1: none).  A work item (one wavefront) is kM2lRowTiles row tiles of
+// 16 rows of one tile over a contiguous group of its entries (the row tiles
+// share the multipole operand); with G > 1 groups per tile the items write
+// partial slots that a reduction adds in a fixed order.
 constexpr int kM2lCols = 16;
+constexpr int kM2lRowTiles = 2;
 struct M2lPlan {
   // per product g
   std::vector<int> g_li, g_w, g_P, g_G, g_nb;

@@ -430,7 +430,8 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
       // entry groups: about two wavefronts per SIMD (1024 SIMDs); more groups
       // would cost partial slots (G nb N complex per product and RHS)
       const int nrt = (N + 15) / 16, nt = (int)tiles.size();
-      const int G = std::max(1, std::min(max_ent, (2048 + nrt * nt - 1) / std::max(1, nrt * nt)));
+      const int nit = (nrt + kM2lRowTiles - 1) / kM2lRowTiles;  // items per (tile, group)
+      const int G = std::max(1, std::min(max_ent, (2048 + nit * nt - 1) / std::max(1, nit * nt)));
       Q.g_G.push_back(G);
       Q.g_poff.push_back(G > 1 ? Q.part_len : 0);
       if (G > 1) Q.part_len += (int64_t)G * nb * N;
@@ -439,7 +440,7 @@ int build_fmm(const ems_handle *h, FmmPlan &F, std::string &err) {
         const int e0 = Q.tile_ptr[tid], ne = Q.tile_ptr[tid + 1] - e0;
         for (int gr = 0; gr < G; ++gr) {
           const int a0 = e0 + (int)((int64_t)ne * gr / G), a1 = e0 + (int)((int64_t)ne * (gr + 1) / G);
-          for (int rt = 0; rt < nrt; ++rt) {
+          for (int rt = 0; rt < nrt; rt += kM2lRowTiles) {
             Q.it_g.push_back(g);
             Q.it_rt.push_back(rt);
             Q.it_tile.push_back(tid);

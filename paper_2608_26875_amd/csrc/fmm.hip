@@ -125,15 +125,16 @@ __global__ __launch_bounds__(64) void toep_task_kernel(
 
 // ---------------------------------------------------------------------------
 // M2L on the matrix cores (plan: M2lPlan in fmm.cpp).  One wavefront per work
-// item: rows 16 rt .. 16 rt + 15 of product g, the kM2lCols = 16 target boxes
-// of one tile, over a group of the tile's offsets:
+// item: rows 16 rt .. 16 (rt + kM2lRowTiles) - 1 of product g (kM2lRowTiles
+// row tiles of 16), the kM2lCols = 16 target boxes of one tile, over a group
+// of the tile's offsets:
 //   acc[k][b] += sum_j s^o_{j-k} M_{src(b,o)}[j]
 // as 16x16x4 MFMAs (A = the Toeplitz symbol, B = the gathered source
-// multipoles, a complex product four real MFMAs).  Lane (i16, kq) supplies A
-// entry (row i16, K index kq) and B entry (K index kq, box i16); both are
-// read straight from the symbol pool and the multipole array (L1/L2
-// resident), four K steps at a time, the next four loaded before the current
-// ones are multiplied.  No LDS and no barriers: waves run independently and
+// multipoles, a complex product three real MFMAs).  Lane (i16, kq) supplies A
+// entry (row i16, K index kq) of each row tile and B entry (K index kq, box
+// i16), which all row tiles of the item share; both are read straight from
+// the symbol pool and the multipole array (L1/L2 resident), kM2lKB K steps at
+// a time, the next ones loaded before the current ones are multiplied.  No LDS and no barriers: waves run independently and
 // the hardware overlaps their loads.  T = double (FP64 MFMA) or float (FP32
 // MFMA on rounded operands, FP32 accumulation) for the mixed form.
 typedef double m2l_d4 __attribute__((ext_vector_type(4)));
@@ -154,10 +155,10 @@ template <> struct M2lM<float> {
   __device__ static int row(int kq, int v) { return 4 * kq + v; }
 };
 
-constexpr int kM2lKB = 4;  // K steps of 4 loaded together
+constexpr int kM2lKB = kM2lRowTiles > 1 ? 2 : 4;  // K steps of 4 loaded together
 
 template <typename T>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void m2l_mfma_kernel(
     int i0, int i1, const int *__restrict__ it_g, const int *__restrict__ it_rt,
     const int *__restrict__ it_tile, const int *__restrict__ it_e0,
     const int *__restrict__ it_e1, const int *__restrict__ it_slot,
@@ -174,10 +175,15 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
   const int row0 = 16 * it_rt[it], tile = it_tile[it];
   const int r = blockIdx.y;
   const double2 *M = mult + (int64_t)r * stride + g_off[g];
+  constexpr int RT = kM2lRowTiles;
+  // row tiles of the item inside the product (uniform over the wave)
+  const int nrt = min(RT, (N - row0 + 15) / 16);
   // 3M complex products: K1 += (Ar + Ai) Br, K2 += Ar (Bi - Br),
   // K3 += Ai (Br + Bi); Re = K1 - K3, Im = K1 + K2 after the loop.
-  Acc k1 = Acc{0, 0, 0, 0}, k2 = Acc{0, 0, 0, 0}, k3 = Acc{0, 0, 0, 0};
-  const int krow = row0 + i16;  // A row of this lane
+  Acc k1[RT], k2[RT], k3[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) k1[t] = k2[t] = k3[t] = Acc{0, 0, 0, 0};
+  const int krow = row0 + i16;  // A row of this lane in the first row tile
   const int e0 = it_e0[it], e1 = it_e1[it];
   // The operand stream runs over (entry, chunk of kM2lKB K steps) without a
   // break between entries: the last chunk of an entry loads the first chunk
@@ -191,12 +197,17 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
     Mb = M + (int64_t)(sb < 0 ? 0 : sb) * N;
   };
   auto load = [&](const double2 *sym, const double2 *Mb, bool live, int j0,
-                  double2 (&a)[kM2lKB], double2 (&b)[kM2lKB]) {
+                  double2 (&a)[RT][kM2lKB], double2 (&b)[kM2lKB]) {
 #pragma unroll
     for (int u = 0; u < kM2lKB; ++u) {
       const int jj = j0 + 4 * u + kq;
-      const int nu = min(max(jj - krow, -2 * P), 2 * P);
-      a[u] = sym[nu];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        // rows past the product are never stored; the clamp keeps their
+        // reads inside the symbol
+        const int nu = min(max(jj - krow - 16 * t, -2 * P), 2 * P);
+        a[t][u] = t < nrt ? sym[nu] : make_double2(0.0, 0.0);
+      }
       b[u] = (live && jj < N) ? Mb[jj] : make_double2(0.0, 0.0);
     }
   };
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
     bool livec, liven;
     entry(e0, symc, Mbc, livec);
     entry(e0 + 1, symn, Mbn, liven);
-    double2 ca[kM2lKB], cb[kM2lKB], na[kM2lKB], nb[kM2lKB];
+    double2 ca[RT][kM2lKB], cb[kM2lKB], na[RT][kM2lKB], nb[kM2lKB];
     load(symc, Mbc, livec, 0, ca, cb);
     for (int e = e0; e < e1; ++e) {
       for (int j0 = 0; j0 < N; j0 += 4 * kM2lKB) {
@@ -214,14 +225,20 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
 #pragma unroll
         for (int u = 0; u < kM2lKB; ++u) {
           if (j0 + 4 * u >= N) break;  // K steps past 2P+1 (uniform over the wave)
-          const T are = (T)ca[u].x, aim = (T)ca[u].y, bre = (T)cb[u].x, bim = (T)cb[u].y;
-          k1 = M2lM<T>::mf(are + aim, bre, k1);
-          k2 = M2lM<T>::mf(are, bim - bre, k2);
-          k3 = M2lM<T>::mf(aim, bre + bim, k3);
+          const T bre = (T)cb[u].x, bim = (T)cb[u].y, bd = bim - bre, bs = bre + bim;
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            if (t >= nrt) break;  // uniform over the wave
+            const T are = (T)ca[t][u].x, aim = (T)ca[t][u].y;
+            k1[t] = M2lM<T>::mf(are + aim, bre, k1[t]);
+            k2[t] = M2lM<T>::mf(are, bd, k2[t]);
+            k3[t] = M2lM<T>::mf(aim, bs, k3[t]);
+          }
         }
 #pragma unroll
         for (int u = 0; u < kM2lKB; ++u) {
-          ca[u] = na[u];
+#pragma unroll
+          for (int t = 0; t < RT; ++t) ca[t][u] = na[t][u];
           cb[u] = nb[u];
         }
       }
@@ -231,8 +248,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
       entry(e + 2, symn, Mbn, liven);
     }
   }
-  const Acc ar = k1 - k3, ai = k1 + k2;
-  // accumulator element v: row M2lM::row(kq, v), box column i16
+  // accumulator element v of row tile t: row 16 t + M2lM::row(kq, v), box column i16
   const int b = tile_box[(int64_t)tile * kM2lCols + i16];
   if (b < 0) return;
   const int slot = it_slot[it];
@@ -240,9 +256,13 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(
                           : part + (int64_t)r * pstride + g_poff[g] +
                                 ((int64_t)slot * g_nb[g] + b) * N;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int k = row0 + M2lM<T>::row(kq, v);
-    if (k < N) dst[k] = make_double2((double)ar[v], (double)ai[v]);
+  for (int t = 0; t < RT; ++t) {
+    const Acc ar = k1[t] - k3[t], ai = k1[t] + k2[t];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = row0 + 16 * t + M2lM<T>::row(kq, v);
+      if (k < N) dst[k] = make_double2((double)ar[v], (double)ai[v]);
+    }
   }
 }
 
