@@ -254,15 +254,23 @@ template <> struct Mfma<float> {
 // MFMAs per complex tile) and the operand slots in flight per wave.  Both
 // contractions take the 3M form; both kernels are compiled for four
 // wavefronts per SIMD (amdgpu_waves_per_eu), which puts the accumulators in
-// ordinary vector registers next to the operand slots without spills for the
-// default tiles.  Measured at 20000 particles, order 15: the FP64 aggregate
-// went from 2.54 to 1.92 ms and the FP64 disaggregate from 2.52 (four MFMAs,
-// one slot, three waves) to 2.27 ms; the FP32 forms to 1.12 and 1.21 ms.
-// More FP64 slots did not pay.
+// ordinary vector registers next to the operand slots (the tiles of one
+// right-hand side spill at most a few registers; the batched tiles spill).
+// Measured at 20000 particles, order 15: the FP64 aggregate went from 2.54 to
+// 1.92 ms and the FP64 disaggregate from 2.52 (four MFMAs, one slot, three
+// waves) to 2.27 ms with 32 particles per wave and 2.16 ms with 16 particles
+// and three slots; the FP32 forms to 1.12 and 1.21 ms.  A third FP64
+// aggregate slot did not pay.
 template <typename T> struct SommForm {
   static constexpr bool kFp32 = std::is_same<T, float>::value;
   static constexpr bool k3MAgg = true, k3MDis = true;
-  static constexpr int kSlotsAgg = kFp32 ? 4 : 2, kSlotsDis = kFp32 ? 4 : 1;
+  static constexpr int kSlotsAgg = kFp32 ? 4 : 2;
+  // FP64 disaggregate: one slot beside the accumulators of 32 particles,
+  // three beside those of 16 particles and one right-hand side when the
+  // exponentials come from the table (the register form needs the room)
+  static constexpr int slots_dis(int nt, int rb, bool gen) {
+    return kFp32 ? 4 : (nt == 1 && rb == 1 && !gen ? 3 : 1);
+  }
 };
 
 // One step of the complex product.  The 3M form (three real MFMAs):
@@ -628,7 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   }
   const int j0 = max(c * per_chunk, lo), j1 = min(min(q, c * per_chunk + per_chunk), hi);
   // ring of S operand slots, loads issued S steps ahead
-  constexpr int S = SommForm<T>::kSlotsDis;
+  constexpr int S = SommForm<T>::slots_dis(NT, RB, GEN);
   C en[S][NT];
   double4 gj[S];  // GEN: the coefficients of the step's node
   double2 bn[S][NC];
@@ -717,7 +725,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
 static constexpr int kCand[2][2][4][2] = {
     // [kernel: 0 aggregate, 1 disaggregate][precision: 0 FP64, 1 FP32][candidate] = {NT, RB}
     {{{1, 1}, {2, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 4}, {1, 8}}},
-    {{{2, 1}, {4, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 4}, {1, 8}}}};
+    {{{2, 1}, {1, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 4}, {1, 8}}}};
 
 int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
   if (kernel < 0 || kernel > 1 || prec < 0 || prec > 1 || idx < 0 || idx > 3) return -1;
