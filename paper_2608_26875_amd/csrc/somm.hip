@@ -467,7 +467,7 @@ __device__ __forceinline__ void gen_exp(const double4 &g, const double2 &ps, T &
 // (somm_xpad_kernel), [nrhs][wave][n][16 NU].
 template <typename T, int NU, int NT, int RB, bool GEN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : 4))) void somm_aggregate_mfma_kernel(
-    int n, int q, int nm, int nrhs, const double2 *__restrict__ xp,
+    int n, int q, int nm, int nrhs, const typename Mfma<T>::C *__restrict__ xp,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     double2 *__restrict__ agg, int chunks, int per_chunk,
     const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ kcut,
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
   constexpr int NW = 16 * NU;
   C en[S][NT];
   double2 ps[S];
-  double2 xn[S][NC];
+  C xn[S][NC];
   auto fetch = [&](int sl, int m) {
     const int mc = min(m + kq, m1 - 1);
     if constexpr (GEN) {
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      const double2 *xr = xp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * n + mc) * NW + i16;
+      const C *xr = xp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * n + mc) * NW + i16;
 #pragma unroll
       for (int u = 0; u < NU; ++u) xn[sl][k * NU + u] = xr[16 * u];
     }
@@ -593,7 +593,7 @@ template <typename T, int NU, int NT, int RB, bool GEN>
 // (somm_bpad_kernel), [nrhs][wave][q][16 NU].
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : 4))) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
-    const double2 *__restrict__ bp, double2 *__restrict__ dis, int64_t ncoef, int chunks,
+    const typename Mfma<T>::C *__restrict__ bp, double2 *__restrict__ dis, int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
     const int2 *__restrict__ jr, const double4 *__restrict__ gco,
     const double2 *__restrict__ xys) {
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
   constexpr int S = SommForm<T>::slots_dis(NT, RB, GEN);
   C en[S][NT];
   double4 gj[S];  // GEN: the coefficients of the step's node
-  double2 bn[S][NC];
+  C bn[S][NC];
   auto fetch = [&](int sl, int j) {
     const int jc = min(j + kq, j1 - 1);
     if constexpr (GEN) {
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
     }
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
-      const double2 *br = bp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc) * NW + i16;
+      const C *br = bp + ((int64_t)(min(r0 + k, nrhs - 1) * 2 + wave) * q + jc) * NW + i16;
 #pragma unroll
       for (int u = 0; u < NU; ++u) bn[sl][k * NU + u] = br[16 * u];
     }
@@ -739,35 +739,47 @@ int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
 
 // The aggregate's coefficient operand: x in depth order, one row of 16 NU
 // modes per (right-hand side, wave type, particle), zero outside |n| <= p_m,
-// so the matrix-core loop reads it without index or order lookups.
+// so the matrix-core loop reads it without index or order lookups.  The FP32
+// contraction takes it in complex64 (it rounds the operand to FP32 anyway),
+// which halves the bytes of the operand its waves re-read.
+template <typename OC>
 __global__ void somm_xpad_kernel(int n, int pmb, int nw, const int *__restrict__ p,
                                  const int64_t *__restrict__ off, const double2 *__restrict__ x,
                                  int64_t ldx, const int *__restrict__ sperm,
-                                 double2 *__restrict__ xp) {
+                                 OC *__restrict__ xp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y, r = blockIdx.z;
   if (i >= (int64_t)n * nw) return;
   const int m = (int)(i / nw), k = (int)(i - (int64_t)m * nw);
   const int mo = sperm[m], pm = p[mo], nn = k - pmb;
-  xp[((int64_t)(r * 2 + w) * n + m) * nw + k] =
-      (nn >= -pm && nn <= pm) ? x[(int64_t)r * ldx + off[mo] + w * (2 * pm + 1) + pm + nn]
-                              : make_double2(0.0, 0.0);
+  const double2 v = (nn >= -pm && nn <= pm)
+                        ? x[(int64_t)r * ldx + off[mo] + w * (2 * pm + 1) + pm + nn]
+                        : make_double2(0.0, 0.0);
+  OC o;
+  o.x = v.x;
+  o.y = v.y;
+  xp[((int64_t)(r * 2 + w) * n + m) * nw + k] = o;
 }
 
 // The disaggregate's B operand: the reflected node amplitudes times the
 // power table, B[r][w][j][k] = g[r][w][j] V_w[j][k], zero beyond the table's
-// 2 PM + 1 modes, so the matrix-core loop reads it as one padded row.
+// 2 PM + 1 modes, so the matrix-core loop reads it as one padded row
+// (complex64 for the FP32 contraction).
+template <typename OC>
 __global__ void somm_bpad_kernel(int q, int nm, int nw, const double2 *__restrict__ g,
                                  const double2 *__restrict__ Vp_t,
-                                 const double2 *__restrict__ Vs_t, double2 *__restrict__ bp) {
+                                 const double2 *__restrict__ Vs_t, OC *__restrict__ bp) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y, r = blockIdx.z;
   if (i >= (int64_t)q * nw) return;
   const int j = (int)(i / nw), k = (int)(i - (int64_t)j * nw);
   const double2 *Vt = w ? Vs_t : Vp_t;
-  bp[((int64_t)(r * 2 + w) * q + j) * nw + k] =
-      k < nm ? cmul(g[(int64_t)(r * 2 + w) * q + j], Vt[(int64_t)j * nm + k])
-             : make_double2(0.0, 0.0);
+  const double2 v = k < nm ? cmul(g[(int64_t)(r * 2 + w) * q + j], Vt[(int64_t)j * nm + k])
+                           : make_double2(0.0, 0.0);
+  OC o;
+  o.x = v.x;
+  o.y = v.y;
+  bp[((int64_t)(r * 2 + w) * q + j) * nw + k] = o;
 }
 
 // Operands of one matrix-core launch: the table (nullptr: the exponentials
@@ -787,11 +799,13 @@ static void agg_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, 
   const int nm = 2 * pm_bucket(h->pmax) + 1;
   if (o.E)
     hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0, st,
-                       h->n, h->q, nm, nrhs, h->d_xpad, o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
+                       h->n, h->q, nm, nrhs, reinterpret_cast<const typename Mfma<T>::C *>(h->d_xpad),
+                       o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
                        o.E, cut, o.gco, h->d_xys);
   else
     hipLaunchKernelGGL((somm_aggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0, st,
-                       h->n, h->q, nm, nrhs, h->d_xpad, o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
+                       h->n, h->q, nm, nrhs, reinterpret_cast<const typename Mfma<T>::C *>(h->d_xpad),
+                       o.Vp, o.Vs, h->d_agg, h->agg_chunks, per,
                        o.E, cut, o.gco, h->d_xys);
 }
 template <typename T, int NU>
@@ -812,11 +826,13 @@ static void dis_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, 
   const int nm = 2 * pm_bucket(h->pmax) + 1;
   if (o.E)
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, h->d_bpad, h->d_dis, h->ncoef,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off,
+                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad), h->d_dis, h->ncoef,
                        h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
   else
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0,
-                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off, h->d_bpad, h->d_dis, h->ncoef,
+                       st, h->n, h->q, nm, nrhs, h->d_p, h->d_off,
+                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad), h->d_dis, h->ncoef,
                        h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
 }
 template <typename T, int NU>
@@ -866,9 +882,15 @@ hipError_t launch_somm_aggregate_mfma(const ems_handle *h, const double2 *x, int
   if (nrhs > h->ws_nrhs || !h->d_xpad) return hipErrorInvalidValue;
   {
     const int nw = 16 * nu;
-    hipLaunchKernelGGL(somm_xpad_kernel, dim3((unsigned)(((int64_t)h->n * nw + 255) / 256), 2, nrhs),
-                       dim3(256), 0, st, h->n, pm_bucket(h->pmax), nw, h->d_p, h->d_off, x,
-                       h->ncoef, h->d_sperm, h->d_xpad);
+    const dim3 grid((unsigned)(((int64_t)h->n * nw + 255) / 256), 2, nrhs);
+    if (prec == 1)
+      hipLaunchKernelGGL(somm_xpad_kernel<float2>, grid, dim3(256), 0, st, h->n,
+                         pm_bucket(h->pmax), nw, h->d_p, h->d_off, x, h->ncoef, h->d_sperm,
+                         reinterpret_cast<float2 *>(h->d_xpad));
+    else
+      hipLaunchKernelGGL(somm_xpad_kernel<double2>, grid, dim3(256), 0, st, h->n,
+                         pm_bucket(h->pmax), nw, h->d_p, h->d_off, x, h->ncoef, h->d_sperm,
+                         h->d_xpad);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -898,8 +920,13 @@ hipError_t launch_somm_disaggregate_mfma(const ems_handle *h, int nrhs, int prec
   if (nrhs > h->ws_nrhs || !h->d_bpad) return hipErrorInvalidValue;
   {
     const int nw = 16 * nu;
-    hipLaunchKernelGGL(somm_bpad_kernel, dim3((unsigned)(((int64_t)h->q * nw + 255) / 256), 2, nrhs),
-                       dim3(256), 0, st, h->q, nm, nw, h->d_refl, Vp, Vs, h->d_bpad);
+    const dim3 grid((unsigned)(((int64_t)h->q * nw + 255) / 256), 2, nrhs);
+    if (prec == 1)
+      hipLaunchKernelGGL(somm_bpad_kernel<float2>, grid, dim3(256), 0, st, h->q, nm, nw,
+                         h->d_refl, Vp, Vs, reinterpret_cast<float2 *>(h->d_bpad));
+    else
+      hipLaunchKernelGGL(somm_bpad_kernel<double2>, grid, dim3(256), 0, st, h->q, nm, nw,
+                         h->d_refl, Vp, Vs, h->d_bpad);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
