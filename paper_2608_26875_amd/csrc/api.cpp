@@ -504,7 +504,7 @@ int apply_impl(ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
   int cflags = parts;
   if (adjoint) cflags &= ~EMS_PART_S;
   ems::ProfScope ps(h, "combine_s_apply", st, (cflags & EMS_PART_S) ? h->flops_s * nrhs : 0.0);
-  HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, st));
+  HIPCHK(h, ems::launch_combine(h, x, y, nrhs, cflags, adjoint, mixed, st));
   return EMS_OK;
 }
 
@@ -2584,7 +2584,7 @@ extern "C" int ems_eval_scattered_adjoint(ems_handle *h, const void *res, int32_
   HIPCHK(h, ems::launch_somm_reflect(h, nrhs, true, st));
   HIPCHK(h, ems::launch_somm_disaggregate(h, nrhs, true, false, st, jr));
   HIPCHK(h, ems::launch_combine(h, nullptr, (double2 *)g, nrhs, EMS_PART_FREE | EMS_PART_REFL,
-                                true, st));
+                                true, false, st));
   return EMS_OK;
 }
 

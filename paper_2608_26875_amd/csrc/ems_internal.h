@@ -402,9 +402,10 @@ bool somm_mfma_ready(const ems_handle *h, bool adjoint);
 bool somm_mfma_fp32(const ems_handle *h);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut = nullptr);
-// y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags.
+// y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags;
+// mixed: S from its complex64 copy.
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs,
-                          int flags, bool adjoint, hipStream_t st);
+                          int flags, bool adjoint, bool mixed, hipStream_t st);
 // plane-wave local coefficients (before S): c [nrhs][ncoef]
 hipError_t launch_incident(const ems_handle *h, const int *wave, const double *angle,
                            const double2 *Rinc, int nrhs, double2 *c, hipStream_t st);

@@ -11,10 +11,16 @@
 
 namespace ems {
 
+__device__ __forceinline__ double2 to_c128(double2 v) { return v; }
+__device__ __forceinline__ double2 to_c128(float2 v) { return make_double2(v.x, v.y); }
+
 // One workgroup per particle (64 or 128 lanes); lane = row of the particle block.
+// SC: the S store read, complex128, or its complex64 copy for the mixed form
+// (half the bytes of the kernel's largest stream; products accumulate in FP64).
+template <typename SC>
 __global__ __launch_bounds__(128) void combine_kernel(
     const int *__restrict__ p, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ Soff, const double2 *__restrict__ St,
+    const int64_t *__restrict__ Soff, const SC *__restrict__ St,
     const double2 *__restrict__ x, double2 *__restrict__ y, const double2 *__restrict__ fre,
     const double2 *__restrict__ dis, int chunks, int64_t ncoef, int flags, int sign) {
   __shared__ double2 v[2 * kMaxModes];
@@ -40,8 +46,8 @@ __global__ __launch_bounds__(128) void combine_kernel(
     double2 u;
     if (flags & EMS_PART_S) {
       u = make_double2(0.0, 0.0);
-      const double2 *Sm = St + Soff[m];
-      for (int c = 0; c < K; ++c) cfma(u, Sm[(int64_t)c * K + lane], v[c]);
+      const SC *Sm = St + Soff[m];
+      for (int c = 0; c < K; ++c) cfma(u, to_c128(Sm[(int64_t)c * K + lane]), v[c]);
     } else {
       u = v[lane];
     }
@@ -75,10 +81,15 @@ __global__ __launch_bounds__(128) void s_apply_kernel(
 }
 
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
-                          bool adjoint, hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st, h->d_p, h->d_off,
-                     h->d_Soff, h->d_S, x, y, h->d_free, h->d_dis, h->dis_chunks, h->ncoef,
-                     flags, adjoint ? 0 : 1);
+                          bool adjoint, bool mixed, hipStream_t st) {
+  if (mixed && h->d_S32)
+    hipLaunchKernelGGL(combine_kernel<float2>, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st,
+                       h->d_p, h->d_off, h->d_Soff, h->d_S32, x, y, h->d_free, h->d_dis,
+                       h->dis_chunks, h->ncoef, flags, adjoint ? 0 : 1);
+  else
+    hipLaunchKernelGGL(combine_kernel<double2>, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st,
+                       h->d_p, h->d_off, h->d_Soff, h->d_S, x, y, h->d_free, h->d_dis,
+                       h->dis_chunks, h->ncoef, flags, adjoint ? 0 : 1);
   return hipGetLastError();
 }
 
