@@ -40,6 +40,13 @@ template <> struct CT<true> {
 __device__ __forceinline__ void cfma_any(double2 &a, double2 x, double2 y) { cfma(a, x, y); }
 __device__ __forceinline__ void cfma_any(float2 &a, float2 x, float2 y) { cfmaf(a, x, y); }
 __device__ __forceinline__ double2 conj_any(double2 v) { return make_double2(v.x, -v.y); }
+// the tabulated near-pair symbols are read once per apply: non-temporal
+// loads keep them from displacing the partner coefficients in the caches
+typedef double graf_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 sym_load(const double2 *p) {
+  const graf_d2v v = __builtin_nontemporal_load(reinterpret_cast<const graf_d2v *>(p));
+  return make_double2(v.x, v.y);
+}
 __device__ __forceinline__ float2 conj_any(float2 v) { return make_float2(v.x, -v.y); }
 
 // ADJ: the adjoint map (a compile-time choice, so the inner products carry no
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(STORED && R
 #pragma unroll
       for (int q = 0; q < PS; ++q) {
         const int e = lane + q * TH;
-        rs[q] = e < ns * 2 * NT ? src[e] : make_double2(0.0, 0.0);
+        rs[q] = e < ns * 2 * NT ? sym_load(src + e) : make_double2(0.0, 0.0);
       }
 #pragma unroll
       for (int q = 0; q < PC; ++q) {
