@@ -402,8 +402,11 @@ bool somm_mfma_ready(const ems_handle *h, bool adjoint);
 bool somm_mfma_fp32(const ems_handle *h);
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut = nullptr);
+// True when the disaggregate of this apply writes complex64 partial sums (the
+// FP32 matrix-core kernel of a forward mixed apply).
+bool somm_dis_c64(const ems_handle *h, bool adjoint, bool mixed);
 // y = x*idscale - S^{(H)} (a_free + sum of disaggregate partials) per flags;
-// mixed: S from its complex64 copy.
+// mixed: S from its complex64 copy, the partials as somm_dis_c64 says.
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs,
                           int flags, bool adjoint, bool mixed, hipStream_t st);
 // plane-wave local coefficients (before S): c [nrhs][ncoef]

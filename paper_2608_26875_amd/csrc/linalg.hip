@@ -17,12 +17,13 @@ __device__ __forceinline__ double2 to_c128(float2 v) { return make_double2(v.x, 
 // One workgroup per particle (64 or 128 lanes); lane = row of the particle block.
 // SC: the S store read, complex128, or its complex64 copy for the mixed form
 // (half the bytes of the kernel's largest stream; products accumulate in FP64).
-template <typename SC>
+// DC: the disaggregate's partial sums (complex64 from the FP32 kernel).
+template <typename SC, typename DC>
 __global__ __launch_bounds__(128) void combine_kernel(
     const int *__restrict__ p, const int64_t *__restrict__ off,
     const int64_t *__restrict__ Soff, const SC *__restrict__ St,
     const double2 *__restrict__ x, double2 *__restrict__ y, const double2 *__restrict__ fre,
-    const double2 *__restrict__ dis, int chunks, int64_t ncoef, int flags, int sign) {
+    const DC *__restrict__ dis, int chunks, int64_t ncoef, int flags, int sign) {
   __shared__ double2 v[2 * kMaxModes];
   const int m = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
   const int pm = p[m];
@@ -33,8 +34,8 @@ __global__ __launch_bounds__(128) void combine_kernel(
     if (flags & EMS_PART_FREE) val = fre[base + lane];
     if (flags & EMS_PART_REFL) {
       double2 s = make_double2(0.0, 0.0);
-      const double2 *dr = dis + (int64_t)r * chunks * ncoef + off[m] + lane;
-      for (int c = 0; c < chunks; ++c) s = cadd(s, dr[(int64_t)c * ncoef]);
+      const DC *dr = dis + (int64_t)r * chunks * ncoef + off[m] + lane;
+      for (int c = 0; c < chunks; ++c) s = cadd(s, to_c128(dr[(int64_t)c * ncoef]));
       const int nn = (lane < N ? lane : lane - N) - pm;
       if (sign && (nn & 1)) s = cscale(s, -1.0);
       val = cadd(val, s);
@@ -82,14 +83,19 @@ __global__ __launch_bounds__(128) void s_apply_kernel(
 
 hipError_t launch_combine(const ems_handle *h, const double2 *x, double2 *y, int nrhs, int flags,
                           bool adjoint, bool mixed, hipStream_t st) {
-  if (mixed && h->d_S32)
-    hipLaunchKernelGGL(combine_kernel<float2>, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st,
-                       h->d_p, h->d_off, h->d_Soff, h->d_S32, x, y, h->d_free, h->d_dis,
-                       h->dis_chunks, h->ncoef, flags, adjoint ? 0 : 1);
-  else
-    hipLaunchKernelGGL(combine_kernel<double2>, dim3(h->n, nrhs), dim3(part_threads(h)), 0, st,
-                       h->d_p, h->d_off, h->d_Soff, h->d_S, x, y, h->d_free, h->d_dis,
-                       h->dis_chunks, h->ncoef, flags, adjoint ? 0 : 1);
+  const dim3 grid(h->n, nrhs), block(part_threads(h));
+  const int sg = adjoint ? 0 : 1;
+  // the partials' type follows the kernel that wrote them; S independently
+  const bool s32 = mixed && h->d_S32, d32 = somm_dis_c64(h, adjoint, mixed);
+  const float2 *dis32 = reinterpret_cast<const float2 *>(h->d_dis);
+#define EMS_COMBINE(SC, DC, S, D)                                                               \
+  hipLaunchKernelGGL((combine_kernel<SC, DC>), grid, block, 0, st, h->d_p, h->d_off, h->d_Soff, \
+                     S, x, y, h->d_free, D, h->dis_chunks, h->ncoef, flags, sg)
+  if (s32 && d32) EMS_COMBINE(float2, float2, h->d_S32, dis32);
+  else if (s32) EMS_COMBINE(float2, double2, h->d_S32, h->d_dis);
+  else if (d32) EMS_COMBINE(double2, float2, h->d_S, dis32);
+  else EMS_COMBINE(double2, double2, h->d_S, h->d_dis);
+#undef EMS_COMBINE
   return hipGetLastError();
 }
 

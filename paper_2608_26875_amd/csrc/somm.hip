@@ -593,7 +593,8 @@ template <typename T, int NU, int NT, int RB, bool GEN>
 // (somm_bpad_kernel), [nrhs][wave][q][16 NU].
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : 4))) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
-    const typename Mfma<T>::C *__restrict__ bp, double2 *__restrict__ dis, int64_t ncoef, int chunks,
+    const typename Mfma<T>::C *__restrict__ bp, typename Mfma<T>::C *__restrict__ dis,
+    int64_t ncoef, int chunks,
     int per_chunk, const typename Mfma<T>::C *__restrict__ Etab, const int *__restrict__ sperm,
     const int2 *__restrict__ jr, const double4 *__restrict__ gco,
     const double2 *__restrict__ xys) {
@@ -697,12 +698,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
 #pragma unroll
       for (int k = 0; k < RB; ++k) {
         if (r0 + k >= nrhs) break;
-        double2 *o = dis + ((int64_t)(r0 + k) * chunks + c) * ncoef + off[lo_] + wave * (2 * pl + 1) + pl;
+        C *o = dis + ((int64_t)(r0 + k) * chunks + c) * ncoef + off[lo_] + wave * (2 * pl + 1) + pl;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int nn = 16 * u + i16 - PM;
-          if (nn >= -pl && nn <= pl)
-            o[nn] = make_double2((double)ar[t][k * NU + u][v], (double)ai[t][k * NU + u][v]);
+          if (nn >= -pl && nn <= pl) {
+            C ov;
+            ov.x = ar[t][k * NU + u][v];
+            ov.y = ai[t][k * NU + u][v];
+            o[nn] = ov;
+          }
         }
       }
     }
@@ -827,12 +832,14 @@ static void dis_go(const ems_handle *h, int nrhs, int per, const SommOps<T> &o, 
   if (o.E)
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, false>), grid, dim3(256), 0,
                        st, h->n, h->q, nm, nrhs, h->d_p, h->d_off,
-                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad), h->d_dis, h->ncoef,
+                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad),
+                       reinterpret_cast<typename Mfma<T>::C *>(h->d_dis), h->ncoef,
                        h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
   else
     hipLaunchKernelGGL((somm_disaggregate_mfma_kernel<T, NU, NT, RB, true>), grid, dim3(256), 0,
                        st, h->n, h->q, nm, nrhs, h->d_p, h->d_off,
-                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad), h->d_dis, h->ncoef,
+                       reinterpret_cast<const typename Mfma<T>::C *>(h->d_bpad),
+                       reinterpret_cast<typename Mfma<T>::C *>(h->d_dis), h->ncoef,
                        h->dis_chunks, per, o.E, h->d_sperm, (const int2 *)cut, o.gco, h->d_xys);
 }
 template <typename T, int NU>
@@ -996,11 +1003,17 @@ hipError_t launch_somm_reflect(const ems_handle *h, int nrhs, bool adjoint, hipS
     else EMS_DIS_LAUNCH(PMV, 2);                                                           \
     break;
 
+// The disaggregate's split-K partial sums are complex64 exactly when the FP32
+// matrix-core kernel writes them (the combine reads them by the same rule).
+bool somm_dis_c64(const ems_handle *h, bool adjoint, bool mixed) {
+  return somm_mfma_ready(h, adjoint) && !adjoint && mixed && somm_mfma_fp32(h);
+}
+
 hipError_t launch_somm_disaggregate(const ems_handle *h, int nrhs, bool adjoint, bool mixed,
                                     hipStream_t st, const int *cut) {
   const int per = (h->q + h->dis_chunks - 1) / h->dis_chunks;
   if (somm_mfma_ready(h, adjoint)) {
-    const int prec = (!adjoint && mixed && somm_mfma_fp32(h)) ? 1 : 0;
+    const int prec = somm_dis_c64(h, adjoint, mixed) ? 1 : 0;
     return launch_somm_disaggregate_mfma(h, nrhs, prec, pick(h, 1, prec, nrhs), st, adjoint, cut);
   }
   dim3 grid((h->n + 255) / 256, h->dis_chunks, 2 * nrhs);
