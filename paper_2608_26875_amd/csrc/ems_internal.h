@@ -27,10 +27,12 @@ constexpr int kRedBlocks = 512;
 // Split-K chunks of the Sommerfeld disaggregate over the nodes: about this
 // many (particle tile, chunk, wave, right-hand side) slots per launch.  Every
 // chunk writes one partial coefficient vector that the combine kernel reads
-// back (26 chunks, 0.53 GB each way at 20000 particles); at 2048 or 1024 the
-// combine is faster but the FP64 disaggregate slower by more (fewer, longer
-// wavefronts over uneven depth-truncated node ranges).
-constexpr int kDisChunkTarget = 4096;
+// back (13 chunks, 0.26 GB each way at 20000 particles in FP64).  With the
+// 16-particle FP64 tile, 13 chunks cost the disaggregate nothing against 26
+// and save the combine 0.08 ms; at 7 the disaggregate loses more than the
+// combine gains (fewer, longer wavefronts over uneven depth-truncated node
+// ranges).
+constexpr int kDisChunkTarget = 2048;
 
 struct Media {
   double lam_h, mu_h, rho_h, lam_b, mu_b, rho_b, omega;
