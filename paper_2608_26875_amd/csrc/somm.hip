@@ -255,8 +255,11 @@ template <> struct Mfma<float> {
 // contractions take the 3M form.  Tiles of one right-hand side and at most
 // 32 rows are compiled for four wavefronts per SIMD (amdgpu_waves_per_eu),
 // which puts the accumulators in ordinary vector registers next to the
-// operand slots (at most a few spilled registers); larger and batched tiles
-// for two, where the candidates below fit without spills.
+// operand slots (at most a few spilled registers), except FP64 tiles of 32
+// rows, which take three (the 32-node FP64 aggregate re-reads half the
+// coefficient operand of the 16-node one: 2.0 -> 1.92 ms at 20000 particles);
+// larger and batched tiles take two, where the candidates below fit without
+// spills.
 // Measured at 20000 particles, order 15: the FP64 aggregate went from 2.54 to
 // 1.92 ms and the FP64 disaggregate from 2.52 (four MFMAs, one slot, three
 // waves) to 2.27 ms with 32 particles per wave and 2.16 ms with 16 particles
@@ -466,7 +469,7 @@ __device__ __forceinline__ void gen_exp(const double4 &g, const double2 &ps, T &
 // xp: the coefficients in depth order, modes -PM .. 16 NU - 1 - PM
 // (somm_xpad_kernel), [nrhs][wave][n][16 NU].
 template <typename T, int NU, int NT, int RB, bool GEN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : 4))) void somm_aggregate_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : (NT == 2 && sizeof(T) == 8 ? 3 : 4)))) void somm_aggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const typename Mfma<T>::C *__restrict__ xp,
     const double2 *__restrict__ Vp_t, const double2 *__restrict__ Vs_t,
     double2 *__restrict__ agg, int chunks, int per_chunk,
@@ -591,7 +594,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
 template <typename T, int NU, int NT, int RB, bool GEN>
 // bp: the B operand RW_j V[j][k], zero-padded to 16 NU modes
 // (somm_bpad_kernel), [nrhs][wave][q][16 NU].
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : 4))) void somm_disaggregate_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || NT > 2 ? 2 : (NT == 2 && sizeof(T) == 8 ? 3 : 4)))) void somm_disaggregate_mfma_kernel(
     int n, int q, int nm, int nrhs, const int *__restrict__ p, const int64_t *__restrict__ off,
     const typename Mfma<T>::C *__restrict__ bp, typename Mfma<T>::C *__restrict__ dis,
     int64_t ncoef, int chunks,
@@ -732,7 +735,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RB > 1 || N
 // block applies/s once the batched shapes stopped spilling.
 static constexpr int kCand[2][2][4][2] = {
     // [kernel: 0 aggregate, 1 disaggregate][precision: 0 FP64, 1 FP32][candidate] = {NT, RB}
-    {{{1, 1}, {1, 2}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 2}, {1, 4}}},
+    {{{1, 1}, {1, 2}, {2, 2}, {2, 1}}, {{2, 1}, {4, 1}, {2, 2}, {1, 4}}},
     {{{2, 1}, {1, 1}, {2, 2}, {1, 4}}, {{2, 1}, {4, 1}, {2, 2}, {1, 4}}}};
 
 int mfma_candidate(int kernel, int prec, int idx, int *nt, int *rb) {
